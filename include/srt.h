@@ -1,0 +1,273 @@
+/*
+ * srt.h - C ABI of libsrt: stochastic ray tracing of transparent 3D Gaussians
+ * on AMD MI355X (gfx950).
+ *
+ * Method: Sun, Georgiev, Fei, Hasan, "Stochastic Ray Tracing of Transparent
+ * 3D Gaussians" (EGSR 2025). A ray traverses a bounding volume hierarchy over
+ * the Gaussians' k-sigma bounds (Sec. 3.2) once, tests each Gaussian whose
+ * bound it crosses (Alg. "intersect"), accepts it with probability alpha
+ * (eqn "rr"), keeps the closest accepted hit per sample (eqn "cloest"), runs N
+ * samples in one traversal (eqn "multisample") and shades the result once.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named "device" are HIP device pointers; the caller owns them
+ *    and keeps them alive until the work on `stream` has finished. Nothing in
+ *    this library allocates or frees caller memory.
+ *  - All calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream) except srt_build_bvh and srt_batch_plan_create, which
+ *    synchronise `stream` before returning.
+ *  - Errors are status codes; nothing throws across the ABI. Arguments are
+ *    validated on the host before anything is launched; on an error no work
+ *    has been enqueued and outputs are untouched.
+ *  - Geometry arrays are FP32, row-major, contiguous.
+ *  - Acceptance numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ *    (seed low 32 bits, seed high 32 bits) and counter
+ *    (ray id, sample / 4, Gaussian id, purpose); u = (word[sample % 4] >> 8)
+ *    * 2^-24. A candidate is accepted iff u < alpha.
+ *  - A candidate is valid iff its depth t (the mean of the 1D Gaussian the
+ *    ray cuts through it, Sec. 3.1) satisfies tmin < t < tmax and its squared
+ *    Mahalanobis distance q at t satisfies q <= s^2 = 8 (eqn "cuboid",
+ *    s = 2 sqrt 2); alpha = opacity * exp(-q / 2). The depth key is t rounded
+ *    to FP32; keys compare as (t, Gaussian id).
+ */
+#ifndef SRT_H
+#define SRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SRT_OK = 0,
+    SRT_ERR_INVALID_ARG = 1,   /* a null pointer, size or option out of range */
+    SRT_ERR_OOM = 2,           /* a device allocation failed */
+    SRT_ERR_HIP = 3,           /* a HIP runtime call or launch failed */
+    SRT_ERR_UNSUPPORTED = 4,   /* a valid but unimplemented combination */
+    SRT_ERR_WORKSPACE = 5      /* the workspace is smaller than required */
+} srt_status;
+
+/* Human-readable name of a status code (static storage). */
+const char* srt_status_str(srt_status s);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int32_t srt_version(void);
+
+/* ------------------------------------------------------------------------
+ * Scene: raw Gaussian parameters as a training pipeline keeps them
+ * (eqn "gaussian": G(x) = exp(-(x-mu)^T Sigma^-1 (x-mu) / 2)).
+ *   means          [G,3] device  mu
+ *   log_scales     [G,3] device  per-axis log standard deviation (S = diag(exp))
+ *   quats          [G,4] device  rotation as an unnormalised (w, x, y, z)
+ *                                quaternion; R = R(q / |q|) maps the
+ *                                Gaussian's frame to the world and
+ *                                Sigma = R S^2 R^T
+ *   opacity_logits [G]   device  opacity o = 1 / (1 + exp(-logit))
+ *   sh             [G,(deg+1)^2,3] device  real SH colour coefficients; the
+ *                                colour seen along unit direction d is
+ *                                max(0, 0.5 + sum_lm k_lm Y_lm(d)) per channel
+ *   sh_degree      0..3
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t num_gaussians;
+    int32_t sh_degree;
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* opacity_logits;
+    const float* sh;
+} srt_scene;
+
+/* ------------------------------------------------------------------------
+ * Acceleration structure (Sec. 3.2: a BVH over per-Gaussian bounds).
+ * width 2, 4 or 8 children per node; leaf_size 1..8 Gaussians per leaf.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t width;
+    int32_t leaf_size;
+} srt_build_opts;
+
+typedef struct srt_bvh srt_bvh; /* opaque, library-owned */
+
+typedef struct {
+    int64_t num_gaussians;
+    int64_t num_nodes;
+    int32_t width;
+    int32_t leaf_size;
+    int32_t depth;          /* levels of wide nodes */
+    int32_t sh_degree;
+    int64_t device_bytes;   /* memory held by the handle */
+} srt_bvh_info;
+
+/* Derive each Gaussian's canonical record (whitening matrix M = S^-1 R^T
+ * computed in FP64 and rounded to FP32, opacity, conservative FP32 box of the
+ * k-sigma ellipsoid) and build a `width`-wide BVH with at most `leaf_size`
+ * Gaussians per leaf. The scene's SH buffer is referenced, not copied: it
+ * must stay alive and unchanged while the handle is used. Synchronises
+ * `stream`. On success *out receives a handle for srt_destroy_bvh.
+ * Errors: INVALID_ARG (null pointers with num_gaussians > 0, negative count,
+ * sh_degree outside 0..3, width not in {2,4,8}, leaf_size outside 1..8,
+ * more than 2^28 Gaussians), OOM, HIP. */
+srt_status srt_build_bvh(const srt_scene* scene, const srt_build_opts* opts, void* stream,
+                         srt_bvh** out);
+
+/* Free a handle (null is ignored). No work on the handle may be pending. */
+void srt_destroy_bvh(srt_bvh* bvh);
+
+srt_status srt_bvh_get_info(const srt_bvh* bvh, srt_bvh_info* info);
+
+/* Copy the canonical records out, in Gaussian-id order, for validation:
+ * mu [G,3], M [G,9] (row-major), opacity [G], box_lo/box_hi [G,3]; all
+ * device, any may be null. Asynchronous on `stream`. */
+srt_status srt_bvh_records(const srt_bvh* bvh, float* mu, float* M, float* opacity,
+                           float* box_lo, float* box_hi, void* stream);
+
+/* Copy the wide-node array out (device, srt_bvh_info.num_nodes nodes of
+ * 32 * width bytes: lo_x[W] lo_y[W] lo_z[W] hi_x[W] hi_y[W] hi_z[W] as FP32
+ * then child[W] as int32, padded; child >= 0 is a node index, child < 0 a
+ * leaf ~((first << 3) | (count - 1)) over the leaf-ordered Gaussians) and
+ * the leaf order (device int32 [G]: Gaussian id at each leaf position).
+ * Either pointer may be null. */
+srt_status srt_bvh_nodes(const srt_bvh* bvh, void* nodes, int32_t* leaf_order, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Rays. origins/dirs [R,3] device (dirs need not be unit length; SH colour
+ * uses the normalised direction). tmin/tmax [R] device or null (0, +inf).
+ * ignore_gid [R] device or null: a Gaussian id the ray never hits (-1 none).
+ * ray_ids [R] device or null (the ray index): Philox counter word 0.
+ * sample_ids [R] device or null: the sample index of the ray's first sample
+ * (added to srt_trace_opts.sample_offset). purpose: Philox counter word 3
+ * (0 camera, 2 shadow, 3 mirror, 4 incoherent by convention).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t count;
+    const float* origins;
+    const float* dirs;
+    const float* tmin;
+    const float* tmax;
+    const int32_t* ignore_gid;
+    const uint32_t* ray_ids;
+    const uint32_t* sample_ids;
+    uint32_t purpose;
+} srt_rays;
+
+/* Trace options.
+ * seed            Philox key.
+ * spp             samples per ray (>= 1); the pixel value is their mean
+ *                 (eqn "multisample").
+ * n_per_traversal samples resolved in one traversal: 1, 2, 4 or 8; samples
+ *                 pass*N + k, so results do not depend on N.
+ * sample_offset   added to every sample index.
+ * bg              colour of a sample that accepts nothing.
+ * any_hit         1: terminate at the first accepted hit (shadow rays); the
+ *                 sample's "colour" is visibility (1 unoccluded, 0 occluded)
+ *                 in all three channels and hit_gid is any accepted id.
+ *                 Requires n_per_traversal == 1.
+ * stack_limit     0 = default; otherwise caps the on-chip traversal stack
+ *                 (testing: forces the deep-stack path).                     */
+typedef struct {
+    uint64_t seed;
+    int32_t spp;
+    int32_t n_per_traversal;
+    uint32_t sample_offset;
+    float bg[3];
+    int32_t any_hit;
+    int32_t stack_limit;
+} srt_trace_opts;
+
+/* Counters accumulated (+=) into a device uint64 array of SRT_NUM_COUNTERS
+ * when a non-null pointer is passed. */
+enum {
+    SRT_CNT_TRAVERSALS = 0, /* ray traversals started */
+    SRT_CNT_NODES = 1,      /* wide nodes visited */
+    SRT_CNT_PRIMS = 2,      /* Gaussians tested in leaves */
+    SRT_CNT_CANDIDATES = 3, /* valid candidates (passed range + ellipsoid) */
+    SRT_CNT_PHILOX = 4,     /* Philox4x32-10 evaluations */
+    SRT_CNT_DEEP = 5,       /* traversals rerun with the deep stack */
+    SRT_CNT_RAY_SAMPLES = 6,/* ray-samples resolved */
+    SRT_CNT_LOST = 7,       /* rays left unresolved (deep stack or step bound
+                               exceeded); zero for every tree this library builds */
+    SRT_NUM_COUNTERS = 8
+};
+
+/* Bytes of device workspace srt_trace_forward / srt_trace_backward need for
+ * `num_rays` rays. */
+size_t srt_trace_workspace_size(const srt_bvh* bvh, int64_t num_rays);
+
+/* Forward trace (Alg. "intersect" applied to every Gaussian whose box the ray
+ * crosses; eqns "rr", "cloest", "multisample").
+ * rgb      [R,3] device or null: mean over samples of the shaded colour.
+ * hit_gid  [R,spp] device int32 or null: accepted Gaussian id, -1 on a miss.
+ * hit_t    [R,spp] device FP32 or null: its depth key, +inf on a miss.
+ * counters device uint64[SRT_NUM_COUNTERS] or null.
+ * workspace / workspace_bytes: device scratch of srt_trace_workspace_size.
+ * The scene must be the one the handle was built from (its sh is read).
+ * Errors: INVALID_ARG, WORKSPACE, HIP. */
+srt_status srt_trace_forward(const srt_bvh* bvh, const srt_rays* rays,
+                             const srt_trace_opts* opts, float* rgb, int32_t* hit_gid,
+                             float* hit_t, uint64_t* counters, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Cameras: pinhole rays through pixel centres, row 0 at the top, FP32 with
+ * single correctly rounded operations in this order (no contraction):
+ *   px = (x + 0.5) / W; sx = ((px * 2) - 1) * tan_half * (W / H)
+ *   py = (y + 0.5) / H; sy = (1 - (py * 2)) * tan_half
+ *   v = (forward + sx * right) + sy * up; d = v / sqrt((vx^2 + vy^2) + vz^2)
+ * The basis (forward, right, up) and tan_half are data, not re-derived.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    float eye[3];
+    float forward[3];
+    float right[3];
+    float up[3];
+    float tan_half;
+    int32_t width;
+    int32_t height;
+    int32_t pad_;
+} srt_camera;
+
+/* Write width*height camera rays (pixel y*width + x): origins, dirs [R,3]
+ * device. */
+srt_status srt_camera_rays(const srt_camera* cam, float* origins, float* dirs, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Path-tracer mix: Gaussians inside a renderer (Sec. 1, Sec. 5: secondary
+ * rays use the same traversal). Per camera sample the shading point P is the
+ * nearer of the accepted Gaussian and the plane y = plane_y; P spawns an
+ * any-hit shadow ray to `light` (Philox purpose 2) and, on the plane, a mirror
+ * ray (purpose 3), both reusing the camera ray id and sample index. In FP32,
+ * single rounded operations: P_i = o_i + (t * d_i) (plane: P_y = plane_y);
+ * v = light - P; len = sqrt((vx^2 + vy^2) + vz^2); l = v / len; the shadow
+ * ray is (P, l, tmin_secondary, len, ignoring the spawning Gaussian); the
+ * mirror ray is (P, (dx, -dy, dz), tmin_secondary, +inf). Colour: Gaussian
+ * c * (0.3 + 0.7 V); plane 0.5 V max(0, l_y) + 0.5 Lm with Lm the mirror
+ * hit's colour (bg on a miss); nothing hit: bg.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    float light[3];
+    float plane_y;
+    float tmin_secondary;
+} srt_pathmix_opts;
+
+size_t srt_pathmix_workspace_size(const srt_bvh* bvh, const srt_camera* cam, int32_t spp);
+
+/* Render one camera's path-tracer mix. Camera ray ids are ray_id_base + pixel.
+ * rgb [H*W,3] device; cam_gid/cam_t [H*W,spp], shadow_vis (uint8: 1 lit,
+ * 0 occluded, 255 no shadow ray) [H*W,spp], mirror_gid (-2 no mirror ray,
+ * -1 miss) [H*W,spp]: device or null. counters as srt_trace_forward; its
+ * SRT_CNT_RAY_SAMPLES entry counts camera samples plus secondary rays.
+ * opts->any_hit must be 0. Errors: INVALID_ARG, WORKSPACE, HIP. */
+srt_status srt_trace_pathmix(const srt_bvh* bvh, const srt_camera* cam, uint32_t ray_id_base,
+                             const srt_trace_opts* opts, const srt_pathmix_opts* pm,
+                             float* rgb, int32_t* cam_gid, float* cam_t, uint8_t* shadow_vis,
+                             int32_t* mirror_gid, uint64_t* counters, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRT_H */

@@ -76,7 +76,9 @@ def _i32(a):
 
 
 def default_threads() -> int:
-    return int(os.environ.get("SRT_ORACLE_THREADS", os.cpu_count() or 1))
+    """OpenMP threads: SRT_ORACLE_THREADS, else OMP_NUM_THREADS, else up to 16."""
+    v = os.environ.get("SRT_ORACLE_THREADS") or os.environ.get("OMP_NUM_THREADS")
+    return int(v) if v else min(16, os.cpu_count() or 1)
 
 
 # ---------------------------------------------------------------------------

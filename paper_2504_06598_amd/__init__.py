@@ -1,0 +1,227 @@
+"""Python binding of libsrt: stochastic ray tracing of transparent 3D Gaussians
+on AMD MI355X (gfx950).
+
+Argument marshalling only: every step runs in the HIP kernels of libsrt.so,
+reached through its C ABI (include/srt.h). PyTorch provides device memory and
+the current stream. The functions carry the C entry points' names.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import COUNTER_NAMES, SRT_NUM_COUNTERS, SrtError
+
+__all__ = ["DeviceScene", "Bvh", "srt_build_bvh", "srt_trace_forward", "srt_camera_rays",
+           "srt_trace_pathmix", "counters_dict", "new_counters", "COUNTER_NAMES"]
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libsrt takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libsrt takes contiguous tensors")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _f32(x, device):
+    return torch.as_tensor(x, dtype=torch.float32, device=device).contiguous()
+
+
+class DeviceScene:
+    """Raw Gaussian parameters on the device (FP32, contiguous)."""
+
+    def __init__(self, means, log_scales, quats, opacity_logits, sh, sh_degree):
+        self.means = means
+        self.log_scales = log_scales
+        self.quats = quats
+        self.opacity_logits = opacity_logits
+        self.sh = sh
+        self.sh_degree = int(sh_degree)
+
+    @classmethod
+    def from_host(cls, scene, device="cuda"):
+        """From any object with NumPy fields means, log_scales, quats,
+        opacity_logits, sh and sh_degree."""
+        return cls(_f32(scene.means, device), _f32(scene.log_scales, device),
+                   _f32(scene.quats, device), _f32(scene.opacity_logits, device),
+                   _f32(scene.sh, device), scene.sh_degree)
+
+    @property
+    def num_gaussians(self):
+        return int(self.means.shape[0])
+
+    def c_struct(self):
+        return _lib.SrtScene(self.num_gaussians, self.sh_degree, _ptr(self.means),
+                             _ptr(self.log_scales), _ptr(self.quats),
+                             _ptr(self.opacity_logits), _ptr(self.sh))
+
+
+class Bvh:
+    """Owning wrapper of an srt_bvh handle; keeps its scene (whose SH buffer the
+    handle reads) alive."""
+
+    def __init__(self, handle, scene):
+        self.handle = handle
+        self.scene = scene
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                torch.cuda.synchronize()
+            except Exception:
+                pass
+            _lib.load().srt_destroy_bvh(self.handle)
+            self.handle = None
+
+    def info(self):
+        inf = _lib.SrtBvhInfo()
+        _lib.check("srt_bvh_get_info", _lib.load().srt_bvh_get_info(self.handle, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _lib.SrtBvhInfo._fields_}
+
+    def records(self):
+        G = self.scene.num_gaussians
+        dev = self.scene.means.device
+        out = dict(mu=torch.empty((G, 3), device=dev), M=torch.empty((G, 9), device=dev),
+                   opacity=torch.empty(G, device=dev), box_lo=torch.empty((G, 3), device=dev),
+                   box_hi=torch.empty((G, 3), device=dev))
+        _lib.check("srt_bvh_records", _lib.load().srt_bvh_records(
+            self.handle, _ptr(out["mu"]), _ptr(out["M"]), _ptr(out["opacity"]),
+            _ptr(out["box_lo"]), _ptr(out["box_hi"]), _stream()))
+        return out
+
+    def nodes(self):
+        inf = self.info()
+        W = inf["width"]
+        dev = self.scene.means.device
+        raw = torch.empty((inf["num_nodes"], 8 * W), dtype=torch.int32, device=dev)
+        order = torch.empty(max(1, self.scene.num_gaussians), dtype=torch.int32, device=dev)
+        _lib.check("srt_bvh_nodes", _lib.load().srt_bvh_nodes(self.handle, _ptr(raw), _ptr(order),
+                                                              _stream()))
+        return raw, order[: self.scene.num_gaussians]
+
+
+def srt_build_bvh(scene: DeviceScene, width: int = 4, leaf_size: int = 4) -> Bvh:
+    lib = _lib.load()
+    sc = scene.c_struct()
+    opts = _lib.SrtBuildOpts(int(width), int(leaf_size))
+    h = C.c_void_p()
+    _lib.check("srt_build_bvh", lib.srt_build_bvh(C.byref(sc), C.byref(opts), _stream(),
+                                                  C.byref(h)))
+    return Bvh(h.value, scene)
+
+
+def new_counters(device="cuda"):
+    return torch.zeros(SRT_NUM_COUNTERS, dtype=torch.int64, device=device)
+
+
+def counters_dict(c):
+    v = c.tolist()
+    return {n: int(x) for n, x in zip(COUNTER_NAMES, v)}
+
+
+def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit):
+    o = _lib.SrtTraceOpts()
+    o.seed = int(seed)
+    o.spp = int(spp)
+    o.n_per_traversal = int(n_per_traversal)
+    o.sample_offset = int(sample_offset)
+    for i in range(3):
+        o.bg[i] = float(bg[i])
+    o.any_hit = 1 if any_hit else 0
+    o.stack_limit = int(stack_limit)
+    return o
+
+
+def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_gid=None,
+                      ray_ids=None, sample_ids=None, purpose=0, seed=0, spp=1,
+                      n_per_traversal=1, sample_offset=0, bg=(0.0, 0.0, 0.0), any_hit=False,
+                      stack_limit=0, want_rgb=True, want_hits=True, counters=None,
+                      out=None, workspace=None):
+    """Trace rays (device tensors [R,3]); returns dict(rgb [R,3], hit_gid [R,spp],
+    hit_t [R,spp])."""
+    lib = _lib.load()
+    R = int(origins.shape[0])
+    dev = origins.device
+    rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
+                        _ptr(ray_ids), _ptr(sample_ids), int(purpose))
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit)
+    res = dict(out or {})
+    if want_rgb and "rgb" not in res:
+        res["rgb"] = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    if want_hits and "hit_gid" not in res:
+        res["hit_gid"] = torch.empty((R, spp), dtype=torch.int32, device=dev)
+        res["hit_t"] = torch.empty((R, spp), dtype=torch.float32, device=dev)
+    need = lib.srt_trace_workspace_size(bvh.handle, R)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _lib.check("srt_trace_forward", lib.srt_trace_forward(
+        bvh.handle, C.byref(rays), C.byref(opts), _ptr(res.get("rgb")), _ptr(res.get("hit_gid")),
+        _ptr(res.get("hit_t")), _ptr(counters), _ptr(workspace), need, _stream()))
+    return res
+
+
+def _camera(cam):
+    c = _lib.SrtCamera()
+    for name in ("eye", "forward", "right", "up"):
+        v = getattr(cam, name)
+        arr = getattr(c, name)
+        for i in range(3):
+            arr[i] = float(v[i])
+    c.tan_half = float(cam.tan_half)
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    return c
+
+
+def srt_camera_rays(cam, device="cuda"):
+    """Canonical pinhole rays of a camera (origins, dirs) [H*W,3]."""
+    lib = _lib.load()
+    R = int(cam.width) * int(cam.height)
+    o = torch.empty((R, 3), dtype=torch.float32, device=device)
+    d = torch.empty((R, 3), dtype=torch.float32, device=device)
+    c = _camera(cam)
+    _lib.check("srt_camera_rays", lib.srt_camera_rays(C.byref(c), _ptr(o), _ptr(d), _stream()))
+    return o, d
+
+
+def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_traversal=1,
+                      sample_offset=0, bg=(0.0, 0.0, 0.0), light=(5.0, 5.0, 5.0), plane_y=-2.5,
+                      tmin_secondary=1e-4, want_hits=True, counters=None, workspace=None,
+                      out=None):
+    """Path-tracer mix of one camera; returns dict(rgb [, cam_gid, cam_t,
+    shadow_vis, mirror_gid])."""
+    lib = _lib.load()
+    dev = bvh.scene.means.device
+    R = int(cam.width) * int(cam.height)
+    c = _camera(cam)
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0)
+    pm = _lib.SrtPathmixOpts()
+    for i in range(3):
+        pm.light[i] = float(light[i])
+    pm.plane_y = float(plane_y)
+    pm.tmin_secondary = float(tmin_secondary)
+    res = dict(out or {})
+    if "rgb" not in res:
+        res["rgb"] = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    if want_hits and "cam_gid" not in res:
+        res["cam_gid"] = torch.empty((R, spp), dtype=torch.int32, device=dev)
+        res["cam_t"] = torch.empty((R, spp), dtype=torch.float32, device=dev)
+        res["shadow_vis"] = torch.empty((R, spp), dtype=torch.uint8, device=dev)
+        res["mirror_gid"] = torch.empty((R, spp), dtype=torch.int32, device=dev)
+    need = lib.srt_pathmix_workspace_size(bvh.handle, C.byref(c), int(spp))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _lib.check("srt_trace_pathmix", lib.srt_trace_pathmix(
+        bvh.handle, C.byref(c), int(ray_id_base), C.byref(opts), C.byref(pm), _ptr(res["rgb"]),
+        _ptr(res.get("cam_gid")), _ptr(res.get("cam_t")), _ptr(res.get("shadow_vis")),
+        _ptr(res.get("mirror_gid")), _ptr(counters), _ptr(workspace), need, _stream()))
+    return res

@@ -1,0 +1,682 @@
+// Canonical records and BVH construction on the GPU.
+//
+// Sec. 3.1-3.2 of the paper: each Gaussian is bounded by the box of its
+// k-sigma ellipsoid (eqn "cuboid") and a BVH is built over the boxes. The
+// paper used Embree / OptiX builders; here the build is a GPU LBVH
+// (63-bit Morton codes of box centres, radix sort, Karras' 2012 parallel
+// binary hierarchy, bottom-up box refit) collapsed top-down into W-wide nodes
+// by greedily opening the child of largest surface area, with subtrees of at
+// most L Gaussians turned into leaves. Records are then stored in leaf order
+// so a leaf is one contiguous run of 64-B records.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "srt_internal.hpp"
+
+using namespace srt;
+
+namespace {
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Canonical record: whitening matrix M = S^-1 R^T from the normalised
+// quaternion and exp(log-scales), and opacity sigmoid(logit), computed in
+// FP64 and rounded to nearest FP32. The box is that of the ellipsoid
+// q <= 8 of the ROUNDED record: Sigma' = (M^T M)^-1 = M^-1 M^-T, half extent
+// sqrt(8 Sigma'_ii), padded by 2^-20 relative and rounded outward to FP32.
+__global__ void k_preprocess(int64_t G, const float* __restrict__ means,
+                             const float* __restrict__ log_scales, const float* __restrict__ quats,
+                             const float* __restrict__ logits, Record* __restrict__ recs,
+                             float* __restrict__ box_lo, float* __restrict__ box_hi)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    double qw = quats[4 * g], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
+    const double nrm = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    if (nrm > 0.0) {
+        qw /= nrm; qx /= nrm; qy /= nrm; qz /= nrm;
+    } else {
+        qw = 1.0; qx = qy = qz = 0.0;
+    }
+    // R maps the Gaussian's frame to the world (Hamilton convention).
+    const double R[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz),
+                         2.0 * (qx * qz + qw * qy),       2.0 * (qx * qy + qw * qz),
+                         1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                         2.0 * (qx * qz - qw * qy),       2.0 * (qy * qz + qw * qx),
+                         1.0 - 2.0 * (qx * qx + qy * qy)};
+    Record r;
+    for (int i = 0; i < 3; ++i) {
+        const double inv_s = exp(-(double)log_scales[3 * g + i]);
+        for (int j = 0; j < 3; ++j) r.M[3 * i + j] = (float)(R[3 * j + i] * inv_s);
+        r.mu[i] = means[3 * g + i];
+    }
+    r.opacity = (float)(1.0 / (1.0 + exp(-(double)logits[g])));
+    r.gid = (int32_t)g;
+    r.pad[0] = r.pad[1] = 0.0f;
+    recs[g] = r;
+
+    const double a = r.M[0], b = r.M[1], c = r.M[2];
+    const double d = r.M[3], e = r.M[4], f = r.M[5];
+    const double gg = r.M[6], h = r.M[7], k = r.M[8];
+    const double c00 = e * k - f * h, c01 = -(d * k - f * gg), c02 = d * h - e * gg;
+    const double det = a * c00 + b * c01 + c * c02;
+    // rows of M^-1 = adj(M)^T / det
+    const double inv[9] = {c00 / det, -(b * k - c * h) / det, (b * f - c * e) / det,
+                           c01 / det, (a * k - c * gg) / det, -(a * f - c * d) / det,
+                           c02 / det, -(a * h - b * gg) / det, (a * e - b * d) / det};
+    for (int i = 0; i < 3; ++i) {
+        const double s2 = inv[3 * i] * inv[3 * i] + inv[3 * i + 1] * inv[3 * i + 1] +
+                          inv[3 * i + 2] * inv[3 * i + 2];
+        const double hx = sqrt(kEllipsoidQ * s2) * (1.0 + 0x1p-20);
+        box_lo[3 * g + i] = __double2float_rd((double)r.mu[i] - hx);
+        box_hi[3 * g + i] = __double2float_ru((double)r.mu[i] + hx);
+    }
+}
+
+__device__ __forceinline__ uint32_t f2ord(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ float ord2f(uint32_t o)
+{
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+// Bounds of box centres: [0..2] min, [3..5] max, as order-preserving uints.
+__global__ void k_centre_bounds(int64_t G, const float* __restrict__ lo, const float* __restrict__ hi,
+                                uint32_t* out)
+{
+    __shared__ uint32_t smin[3][256], smax[3][256];
+    uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < G;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        for (int i = 0; i < 3; ++i) {
+            const uint32_t c = f2ord(0.5f * (lo[3 * g + i] + hi[3 * g + i]));
+            mn[i] = min(mn[i], c);
+            mx[i] = max(mx[i], c);
+        }
+    }
+    for (int i = 0; i < 3; ++i) {
+        smin[i][threadIdx.x] = mn[i];
+        smax[i][threadIdx.x] = mx[i];
+    }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int i = 0; i < 3; ++i) {
+                smin[i][threadIdx.x] = min(smin[i][threadIdx.x], smin[i][threadIdx.x + s]);
+                smax[i][threadIdx.x] = max(smax[i][threadIdx.x], smax[i][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int i = 0; i < 3; ++i) {
+            atomicMin(&out[i], smin[i][0]);
+            atomicMax(&out[3 + i], smax[i][0]);
+        }
+}
+
+__device__ __forceinline__ uint64_t spread3_21(uint32_t v)
+{
+    uint64_t x = v & 0x1FFFFFu;
+    x = (x | (x << 32)) & 0x1F00000000FFFFull;
+    x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ void k_morton(int64_t G, const float* __restrict__ lo, const float* __restrict__ hi,
+                         const uint32_t* __restrict__ bounds, uint64_t* __restrict__ keys,
+                         uint32_t* __restrict__ idx)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    uint32_t q[3];
+    for (int i = 0; i < 3; ++i) {
+        const float bmin = ord2f(bounds[i]), bmax = ord2f(bounds[3 + i]);
+        const float ext = bmax - bmin;
+        const float c = 0.5f * (lo[3 * g + i] + hi[3 * g + i]);
+        float t = ext > 0.0f ? (c - bmin) / ext : 0.0f;
+        t = fminf(fmaxf(t, 0.0f), 1.0f);
+        q[i] = min((uint32_t)(t * 2097152.0f), 2097151u);
+    }
+    keys[g] = (spread3_21(q[0]) << 2) | (spread3_21(q[1]) << 1) | spread3_21(q[2]);
+    idx[g] = (uint32_t)g;
+}
+
+// Length of the common prefix of sorted keys i and j (ties extended by the
+// index), -1 outside the array.
+__device__ __forceinline__ int prefix_len(const uint64_t* __restrict__ k, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    const uint64_t a = k[i], b = k[j];
+    if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+    return __clzll(a ^ b);
+}
+
+// Karras (HPG 2012): internal node i covers a key range found by a doubling
+// then binary search of common-prefix lengths, and splits where the prefix
+// length of the range drops. Child refs: >= 0 internal, < 0 leaf ~k.
+__global__ void k_karras(int n, const uint64_t* __restrict__ keys, int32_t* __restrict__ left,
+                         int32_t* __restrict__ right, int32_t* __restrict__ parent,
+                         int32_t* __restrict__ leaf_parent, int32_t* __restrict__ first,
+                         int32_t* __restrict__ last)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (prefix_len(keys, n, i, i + 1) - prefix_len(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = prefix_len(keys, n, i, i - d);
+    int lmax = 2;
+    while (prefix_len(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (prefix_len(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = prefix_len(keys, n, i, j);
+    int s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (prefix_len(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int split = i + s * d + min(d, 0);
+    const int lo_i = min(i, j), hi_i = max(i, j);
+    const int32_t lc = (lo_i == split) ? ~split : split;
+    const int32_t rc = (hi_i == split + 1) ? ~(split + 1) : split + 1;
+    left[i] = lc;
+    right[i] = rc;
+    first[i] = lo_i;
+    last[i] = hi_i;
+    if (lc < 0) leaf_parent[~lc] = i; else parent[lc] = i;
+    if (rc < 0) leaf_parent[~rc] = i; else parent[rc] = i;
+    if (i == 0) parent[0] = -1;
+}
+
+__device__ __forceinline__ float load_coherent(const float* p)
+{
+    return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Bottom-up refit: the second thread to reach a node unions its children.
+__global__ void k_refit(int n, const int32_t* __restrict__ leaf_parent,
+                        const int32_t* __restrict__ parent, const int32_t* __restrict__ left,
+                        const int32_t* __restrict__ right, const uint32_t* __restrict__ order,
+                        const float* __restrict__ lo, const float* __restrict__ hi, float* blo,
+                        float* bhi, uint32_t* flags)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int node = leaf_parent[k];
+    while (node >= 0) {
+        __threadfence();
+        if (atomicAdd(&flags[node], 1u) == 0u) return;
+        __threadfence();
+        float l[3], h[3];
+        for (int i = 0; i < 3; ++i) {
+            l[i] = INFINITY;
+            h[i] = -INFINITY;
+        }
+        const int32_t ch[2] = {left[node], right[node]};
+        for (int c = 0; c < 2; ++c) {
+            if (ch[c] < 0) {
+                const uint32_t g = order[~ch[c]];
+                for (int i = 0; i < 3; ++i) {
+                    l[i] = fminf(l[i], lo[3 * g + i]);
+                    h[i] = fmaxf(h[i], hi[3 * g + i]);
+                }
+            } else {
+                for (int i = 0; i < 3; ++i) {
+                    l[i] = fminf(l[i], load_coherent(&blo[3 * ch[c] + i]));
+                    h[i] = fmaxf(h[i], load_coherent(&bhi[3 * ch[c] + i]));
+                }
+            }
+        }
+        for (int i = 0; i < 3; ++i) {
+            blo[3 * node + i] = l[i];
+            bhi[3 * node + i] = h[i];
+        }
+        node = parent[node];
+    }
+}
+
+struct Task {
+    int32_t bin;
+    int32_t node;
+};
+
+struct BinTree {
+    const int32_t *left, *right, *first, *last;
+    const float *blo, *bhi;  // internal boxes
+    const float *lo, *hi;    // Gaussian boxes (id order)
+    const uint32_t* order;   // leaf position -> id
+};
+
+__device__ __forceinline__ void bin_box(const BinTree& t, int32_t c, float l[3], float h[3])
+{
+    if (c < 0) {
+        const uint32_t g = t.order[~c];
+        for (int i = 0; i < 3; ++i) {
+            l[i] = t.lo[3 * g + i];
+            h[i] = t.hi[3 * g + i];
+        }
+    } else {
+        for (int i = 0; i < 3; ++i) {
+            l[i] = t.blo[3 * c + i];
+            h[i] = t.bhi[3 * c + i];
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t bin_size(const BinTree& t, int32_t c)
+{
+    return c < 0 ? 1 : t.last[c] - t.first[c] + 1;
+}
+
+// One level of the top-down collapse into W-wide nodes.
+template <int W>
+__global__ void k_collapse(BinTree t, int L, const Task* __restrict__ in,
+                           const uint32_t* __restrict__ n_in, Task* __restrict__ out,
+                           uint32_t* n_out, uint32_t* node_counter, WideNode<W>* nodes)
+{
+    const uint32_t ti = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ti >= *n_in) return;
+    const Task tk = in[ti];
+    int32_t C[W];
+    float area[W];
+    int nc = 2;
+    C[0] = t.left[tk.bin];
+    C[1] = t.right[tk.bin];
+    for (int j = 0; j < 2; ++j) {
+        float l[3], h[3];
+        bin_box(t, C[j], l, h);
+        const float dx = h[0] - l[0], dy = h[1] - l[1], dz = h[2] - l[2];
+        area[j] = (C[j] >= 0 && bin_size(t, C[j]) > L) ? dx * dy + dy * dz + dz * dx : -1.0f;
+    }
+    while (nc < W) {
+        int best = -1;
+        float ba = -1.0f;
+        for (int j = 0; j < nc; ++j)
+            if (area[j] > ba) {
+                ba = area[j];
+                best = j;
+            }
+        if (best < 0 || ba < 0.0f) break;
+        const int32_t c = C[best];
+        C[best] = t.left[c];
+        C[nc] = t.right[c];
+        for (int r = 0; r < 2; ++r) {
+            const int j = r == 0 ? best : nc;
+            float l[3], h[3];
+            bin_box(t, C[j], l, h);
+            const float dx = h[0] - l[0], dy = h[1] - l[1], dz = h[2] - l[2];
+            area[j] = (C[j] >= 0 && bin_size(t, C[j]) > L) ? dx * dy + dy * dz + dz * dx : -1.0f;
+        }
+        ++nc;
+    }
+    WideNode<W> nd;
+    for (int s = 0; s < W; ++s) {
+        if (s < nc) {
+            const int32_t c = C[s];
+            float l[3], h[3];
+            bin_box(t, c, l, h);
+            for (int i = 0; i < 3; ++i) {
+                nd.lo[i][s] = l[i];
+                nd.hi[i][s] = h[i];
+            }
+            const int32_t sz = bin_size(t, c);
+            if (c < 0) {
+                nd.child[s] = make_leaf((uint32_t)~c, 1u);
+            } else if (sz <= L) {
+                nd.child[s] = make_leaf((uint32_t)t.first[c], (uint32_t)sz);
+            } else {
+                const uint32_t idx = atomicAdd(node_counter, 1u);
+                nd.child[s] = (int32_t)idx;
+                out[atomicAdd(n_out, 1u)] = Task{c, (int32_t)idx};
+            }
+        } else {
+            for (int i = 0; i < 3; ++i) {
+                nd.lo[i][s] = INFINITY;
+                nd.hi[i][s] = -INFINITY;
+            }
+            nd.child[s] = kEmptyChild;
+        }
+        nd.pad[s] = 0;
+    }
+    nodes[tk.node] = nd;
+}
+
+// A scene of at most L Gaussians: one root with a single leaf.
+template <int W>
+__global__ void k_single_leaf(int64_t G, const float* __restrict__ lo, const float* __restrict__ hi,
+                              WideNode<W>* nodes)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    WideNode<W> nd;
+    for (int s = 0; s < W; ++s) {
+        for (int i = 0; i < 3; ++i) {
+            nd.lo[i][s] = INFINITY;
+            nd.hi[i][s] = -INFINITY;
+        }
+        nd.child[s] = kEmptyChild;
+        nd.pad[s] = 0;
+    }
+    for (int64_t g = 0; g < G; ++g)
+        for (int i = 0; i < 3; ++i) {
+            nd.lo[i][0] = fminf(nd.lo[i][0], lo[3 * g + i]);
+            nd.hi[i][0] = fmaxf(nd.hi[i][0], hi[3 * g + i]);
+        }
+    if (G > 0) nd.child[0] = make_leaf(0u, (uint32_t)G);
+    nodes[0] = nd;
+}
+
+__global__ void k_permute(int64_t G, const uint32_t* __restrict__ order, const Record* __restrict__ in,
+                          Record* __restrict__ out, int32_t* __restrict__ leaf_order)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= G) return;
+    const uint32_t g = order[k];
+    out[k] = in[g];
+    leaf_order[k] = (int32_t)g;
+}
+
+__global__ void k_unpermute_records(int64_t G, const Record* __restrict__ recs, float* mu, float* M,
+                                    float* op)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= G) return;
+    const Record r = recs[k];
+    const int64_t g = r.gid;
+    if (mu)
+        for (int i = 0; i < 3; ++i) mu[3 * g + i] = r.mu[i];
+    if (M)
+        for (int i = 0; i < 9; ++i) M[9 * g + i] = r.M[i];
+    if (op) op[g] = r.opacity;
+}
+
+// Device allocations released on scope exit unless released to the caller.
+struct DevAlloc {
+    std::vector<void*> ptrs;
+    template <class T>
+    hipError_t get(T** p, size_t bytes)
+    {
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, bytes > 0 ? bytes : 16);
+        if (e == hipSuccess) ptrs.push_back(q);
+        *p = static_cast<T*>(q);
+        return e;
+    }
+    void release(void* p)
+    {
+        ptrs.erase(std::remove(ptrs.begin(), ptrs.end(), p), ptrs.end());
+    }
+    ~DevAlloc()
+    {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+};
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
+
+template <int W>
+srt_status collapse_all(hipStream_t s, DevAlloc& tmp, const BinTree& t, int64_t n, int L,
+                        WideNode<W>* nodes, int64_t* num_nodes, int32_t* depth)
+{
+    Task *qa = nullptr, *qb = nullptr;
+    uint32_t* ctr = nullptr;  // [0] n_in, [1] n_out, [2] node counter
+    SRT_HIP_TRY(tmp.get(&qa, sizeof(Task) * (size_t)n));
+    SRT_HIP_TRY(tmp.get(&qb, sizeof(Task) * (size_t)n));
+    SRT_HIP_TRY(tmp.get(&ctr, 4 * sizeof(uint32_t)));
+    const Task root{0, 0};
+    const uint32_t init[4] = {1u, 0u, 1u, 0u};
+    SRT_HIP_TRY(hipMemcpyAsync(qa, &root, sizeof(Task), hipMemcpyHostToDevice, s));
+    SRT_HIP_TRY(hipMemcpyAsync(ctr, init, sizeof(init), hipMemcpyHostToDevice, s));
+    uint32_t n_level = 1;
+    int32_t levels = 0;
+    while (n_level > 0) {
+        k_fill_u32<<<1, 1, 0, s>>>(ctr + 1, 0u, 1);
+        k_collapse<W><<<blocks_for(n_level, 128), 128, 0, s>>>(t, L, qa, ctr, qb, ctr + 1, ctr + 2,
+                                                                nodes);
+        SRT_HIP_TRY(hipGetLastError());
+        SRT_HIP_TRY(hipMemcpyAsync(ctr, ctr + 1, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        uint32_t host[3];
+        SRT_HIP_TRY(hipMemcpyAsync(host, ctr, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SRT_HIP_TRY(hipStreamSynchronize(s));
+        n_level = host[0];
+        *num_nodes = host[2];
+        std::swap(qa, qb);
+        ++levels;
+        if (levels > 4096) return SRT_ERR_HIP;  // cannot happen for a valid tree
+    }
+    *depth = levels;
+    return SRT_OK;
+}
+
+template <int W>
+srt_status build_impl(const srt_scene* sc, int L, hipStream_t s, srt_bvh* b)
+{
+    const int64_t G = sc->num_gaussians;
+    DevAlloc tmp;
+    if (G == 0) {
+        WideNode<W>* nodes = nullptr;
+        SRT_HIP_TRY(hipMalloc(&nodes, sizeof(WideNode<W>)));
+        b->nodes = nodes;
+        k_single_leaf<W><<<1, 1, 0, s>>>(0, nullptr, nullptr, nodes);
+        SRT_HIP_TRY(hipGetLastError());
+        b->num_nodes = 1;
+        b->depth = 1;
+        b->bytes = sizeof(WideNode<W>);
+        SRT_HIP_TRY(hipStreamSynchronize(s));
+        return SRT_OK;
+    }
+    Record* recs_id = nullptr;
+    SRT_HIP_TRY(tmp.get(&recs_id, sizeof(Record) * (size_t)G));
+    SRT_HIP_TRY(hipMalloc(&b->box_lo, sizeof(float) * 3 * (size_t)G));
+    SRT_HIP_TRY(hipMalloc(&b->box_hi, sizeof(float) * 3 * (size_t)G));
+    SRT_HIP_TRY(hipMalloc(&b->recs, sizeof(Record) * (size_t)G));
+    SRT_HIP_TRY(hipMalloc(&b->leaf_order, sizeof(int32_t) * (size_t)G));
+    b->bytes = (int64_t)(sizeof(float) * 6 + sizeof(Record) + sizeof(int32_t)) * G;
+
+    k_preprocess<<<blocks_for(G, 256), 256, 0, s>>>(G, sc->means, sc->log_scales, sc->quats,
+                                                    sc->opacity_logits, recs_id, b->box_lo,
+                                                    b->box_hi);
+    SRT_HIP_TRY(hipGetLastError());
+
+    uint32_t* bounds = nullptr;
+    SRT_HIP_TRY(tmp.get(&bounds, 8 * sizeof(uint32_t)));
+    const uint32_t binit[8] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
+    SRT_HIP_TRY(hipMemcpyAsync(bounds, binit, sizeof(binit), hipMemcpyHostToDevice, s));
+    k_centre_bounds<<<std::min<unsigned>(blocks_for(G, 256), 1024u), 256, 0, s>>>(G, b->box_lo,
+                                                                               b->box_hi, bounds);
+    SRT_HIP_TRY(hipGetLastError());
+
+    uint64_t *keys = nullptr, *keys_sorted = nullptr;
+    uint32_t *idx = nullptr, *order = nullptr;
+    SRT_HIP_TRY(tmp.get(&keys, sizeof(uint64_t) * (size_t)G));
+    SRT_HIP_TRY(tmp.get(&keys_sorted, sizeof(uint64_t) * (size_t)G));
+    SRT_HIP_TRY(tmp.get(&idx, sizeof(uint32_t) * (size_t)G));
+    SRT_HIP_TRY(tmp.get(&order, sizeof(uint32_t) * (size_t)G));
+    k_morton<<<blocks_for(G, 256), 256, 0, s>>>(G, b->box_lo, b->box_hi, bounds, keys, idx);
+    SRT_HIP_TRY(hipGetLastError());
+    size_t sort_bytes = 0;
+    SRT_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, keys, keys_sorted, idx,
+                                                   order, (int)G, 0, 63, s));
+    void* sort_tmp = nullptr;
+    SRT_HIP_TRY(tmp.get(&sort_tmp, sort_bytes));
+    SRT_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, keys, keys_sorted, idx,
+                                                   order, (int)G, 0, 63, s));
+
+    k_permute<<<blocks_for(G, 256), 256, 0, s>>>(G, order, recs_id, b->recs, b->leaf_order);
+    SRT_HIP_TRY(hipGetLastError());
+
+    WideNode<W>* nodes_max = nullptr;
+    int64_t num_nodes = 1;
+    int32_t depth = 1;
+    if (G <= L) {
+        SRT_HIP_TRY(tmp.get(&nodes_max, sizeof(WideNode<W>)));
+        k_single_leaf<W><<<1, 1, 0, s>>>(G, b->box_lo, b->box_hi, nodes_max);
+        SRT_HIP_TRY(hipGetLastError());
+    } else {
+        const int n = (int)G;
+        int32_t *left, *right, *parent, *leaf_parent, *first, *last;
+        float *blo, *bhi;
+        uint32_t* flags;
+        SRT_HIP_TRY(tmp.get(&left, sizeof(int32_t) * (n - 1)));
+        SRT_HIP_TRY(tmp.get(&right, sizeof(int32_t) * (n - 1)));
+        SRT_HIP_TRY(tmp.get(&parent, sizeof(int32_t) * (n - 1)));
+        SRT_HIP_TRY(tmp.get(&first, sizeof(int32_t) * (n - 1)));
+        SRT_HIP_TRY(tmp.get(&last, sizeof(int32_t) * (n - 1)));
+        SRT_HIP_TRY(tmp.get(&leaf_parent, sizeof(int32_t) * n));
+        SRT_HIP_TRY(tmp.get(&blo, sizeof(float) * 3 * (n - 1)));
+        SRT_HIP_TRY(tmp.get(&bhi, sizeof(float) * 3 * (n - 1)));
+        SRT_HIP_TRY(tmp.get(&flags, sizeof(uint32_t) * (n - 1)));
+        k_karras<<<blocks_for(n - 1, 256), 256, 0, s>>>(n, keys_sorted, left, right, parent,
+                                                        leaf_parent, first, last);
+        SRT_HIP_TRY(hipGetLastError());
+        k_fill_u32<<<blocks_for(n - 1, 256), 256, 0, s>>>(flags, 0u, (size_t)(n - 1));
+        k_refit<<<blocks_for(n, 256), 256, 0, s>>>(n, leaf_parent, parent, left, right, order,
+                                                   b->box_lo, b->box_hi, blo, bhi, flags);
+        SRT_HIP_TRY(hipGetLastError());
+        SRT_HIP_TRY(tmp.get(&nodes_max, sizeof(WideNode<W>) * (size_t)(n - 1)));
+        const BinTree t{left, right, first, last, blo, bhi, b->box_lo, b->box_hi, order};
+        const srt_status st = collapse_all<W>(s, tmp, t, n, L, nodes_max, &num_nodes, &depth);
+        if (st != SRT_OK) return st;
+    }
+    WideNode<W>* nodes = nullptr;
+    SRT_HIP_TRY(hipMalloc(&nodes, sizeof(WideNode<W>) * (size_t)num_nodes));
+    b->nodes = nodes;
+    SRT_HIP_TRY(hipMemcpyAsync(nodes, nodes_max, sizeof(WideNode<W>) * (size_t)num_nodes,
+                               hipMemcpyDeviceToDevice, s));
+    SRT_HIP_TRY(hipStreamSynchronize(s));
+    b->num_nodes = num_nodes;
+    b->depth = depth;
+    b->bytes += (int64_t)sizeof(WideNode<W>) * num_nodes;
+    return SRT_OK;
+}
+
+}  // namespace
+
+namespace srt {
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    k_fill_u32<<<(unsigned)std::min<size_t>((n + 255) / 256, 1024), 256, 0, s>>>(p, v, n);
+}
+}  // namespace srt
+
+extern "C" {
+
+const char* srt_status_str(srt_status s)
+{
+    switch (s) {
+    case SRT_OK: return "SRT_OK";
+    case SRT_ERR_INVALID_ARG: return "SRT_ERR_INVALID_ARG";
+    case SRT_ERR_OOM: return "SRT_ERR_OOM";
+    case SRT_ERR_HIP: return "SRT_ERR_HIP";
+    case SRT_ERR_UNSUPPORTED: return "SRT_ERR_UNSUPPORTED";
+    case SRT_ERR_WORKSPACE: return "SRT_ERR_WORKSPACE";
+    }
+    return "SRT_ERR_UNKNOWN";
+}
+
+int32_t srt_version(void) { return 10000; }
+
+srt_status srt_build_bvh(const srt_scene* sc, const srt_build_opts* opts, void* stream,
+                         srt_bvh** out)
+{
+    if (!sc || !opts || !out) return SRT_ERR_INVALID_ARG;
+    *out = nullptr;
+    const int64_t G = sc->num_gaussians;
+    if (G < 0 || G > (int64_t(1) << 28)) return SRT_ERR_INVALID_ARG;
+    if (sc->sh_degree < 0 || sc->sh_degree > 3) return SRT_ERR_INVALID_ARG;
+    if (G > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
+        return SRT_ERR_INVALID_ARG;
+    if (opts->width != 2 && opts->width != 4 && opts->width != 8) return SRT_ERR_INVALID_ARG;
+    if (opts->leaf_size < 1 || opts->leaf_size > 8) return SRT_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    srt_bvh* b = new srt_bvh();
+    b->G = G;
+    b->W = opts->width;
+    b->L = opts->leaf_size;
+    b->deg = sc->sh_degree;
+    b->sh = sc->sh;
+    srt_status st = SRT_ERR_INVALID_ARG;
+    switch (b->W) {
+    case 2: st = build_impl<2>(sc, b->L, s, b); break;
+    case 4: st = build_impl<4>(sc, b->L, s, b); break;
+    case 8: st = build_impl<8>(sc, b->L, s, b); break;
+    }
+    if (st != SRT_OK) {
+        (void)hipStreamSynchronize(s);
+        srt_destroy_bvh(b);
+        return st;
+    }
+    *out = b;
+    return SRT_OK;
+}
+
+void srt_destroy_bvh(srt_bvh* b)
+{
+    if (!b) return;
+    (void)hipFree(b->nodes);
+    (void)hipFree(b->recs);
+    (void)hipFree(b->leaf_order);
+    (void)hipFree(b->box_lo);
+    (void)hipFree(b->box_hi);
+    delete b;
+}
+
+srt_status srt_bvh_get_info(const srt_bvh* b, srt_bvh_info* info)
+{
+    if (!b || !info) return SRT_ERR_INVALID_ARG;
+    info->num_gaussians = b->G;
+    info->num_nodes = b->num_nodes;
+    info->width = b->W;
+    info->leaf_size = b->L;
+    info->depth = b->depth;
+    info->sh_degree = b->deg;
+    info->device_bytes = b->bytes;
+    return SRT_OK;
+}
+
+srt_status srt_bvh_records(const srt_bvh* b, float* mu, float* M, float* opacity, float* box_lo,
+                           float* box_hi, void* stream)
+{
+    if (!b) return SRT_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->G == 0) return SRT_OK;
+    if (mu || M || opacity) {
+        k_unpermute_records<<<blocks_for(b->G, 256), 256, 0, s>>>(b->G, b->recs, mu, M, opacity);
+        SRT_HIP_TRY(hipGetLastError());
+    }
+    const size_t bytes = sizeof(float) * 3 * (size_t)b->G;
+    if (box_lo) SRT_HIP_TRY(hipMemcpyAsync(box_lo, b->box_lo, bytes, hipMemcpyDeviceToDevice, s));
+    if (box_hi) SRT_HIP_TRY(hipMemcpyAsync(box_hi, b->box_hi, bytes, hipMemcpyDeviceToDevice, s));
+    return SRT_OK;
+}
+
+srt_status srt_bvh_nodes(const srt_bvh* b, void* nodes, int32_t* leaf_order, void* stream)
+{
+    if (!b) return SRT_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nodes)
+        SRT_HIP_TRY(hipMemcpyAsync(nodes, b->nodes, (size_t)b->num_nodes * 32 * (size_t)b->W,
+                                   hipMemcpyDeviceToDevice, s));
+    if (leaf_order && b->G > 0)
+        SRT_HIP_TRY(hipMemcpyAsync(leaf_order, b->leaf_order, sizeof(int32_t) * (size_t)b->G,
+                                   hipMemcpyDeviceToDevice, s));
+    return SRT_OK;
+}
+
+}  // extern "C"

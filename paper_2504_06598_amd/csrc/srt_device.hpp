@@ -1,0 +1,344 @@
+// Device-side building blocks of libsrt (gfx950 / CDNA4).
+//
+// Data layout in HBM:
+//   Record      64 B per Gaussian, leaf order: mu(3) M(9) opacity gid pad(2).
+//               M = S^-1 R^T is the whitening matrix of the Gaussian
+//               (eqn "gaussian"), so q(x) = |M (x - mu)|^2.
+//   WideNode<W> 32*W bytes: lo_x[W] lo_y[W] lo_z[W] hi_x[W] hi_y[W] hi_z[W]
+//               child[W], padded; W = 2/4/8 gives 64/128/256 B, one or two
+//               128-B cache lines, loaded as 16-B vectors.
+//   child >= 0: wide-node index; child < 0: leaf ~((first << 3) | (count-1))
+//   over the leaf-ordered records; empty slots have an inverted box.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srt {
+
+// Squared k-sigma radius of the bounding ellipsoid, s = 2 sqrt 2 (eqn "cuboid").
+constexpr double kEllipsoidQ = 8.0;
+
+struct alignas(16) Record {
+    float mu[3];
+    float M[9];
+    float opacity;
+    int32_t gid;
+    float pad[2];
+};
+static_assert(sizeof(Record) == 64, "record is one 64-B line");
+
+template <int W>
+struct alignas(16) WideNode {
+    float lo[3][W];
+    float hi[3][W];
+    int32_t child[W];
+    int32_t pad[W];
+};
+static_assert(sizeof(WideNode<4>) == 128, "BVH4 node is 128 B");
+
+// Number of 16-B vectors that hold the used part of a node.
+template <int W>
+struct NodeVecs {
+    static constexpr int value = (28 * W + 15) / 16;
+};
+
+template <int W>
+struct NodeBuf {
+    struct {
+        float lo[3][W];
+        float hi[3][W];
+        int32_t child[W];
+    } n;
+};
+
+template <int W>
+__device__ __forceinline__ void load_node(const WideNode<W>* nodes, int32_t idx, NodeBuf<W>& b)
+{
+    constexpr int NV = NodeVecs<W>::value;
+    const float4* p = reinterpret_cast<const float4*>(nodes + idx);
+    float f[4 * NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const float4 v = p[i];
+        f[4 * i] = v.x;
+        f[4 * i + 1] = v.y;
+        f[4 * i + 2] = v.z;
+        f[4 * i + 3] = v.w;
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            b.n.lo[a][c] = f[a * W + c];
+            b.n.hi[a][c] = f[(3 + a) * W + c];
+        }
+        b.n.child[c] = __float_as_int(f[6 * W + c]);
+    }
+}
+
+// Child reference of slot `slot`, selected with bit masks: a select between
+// two loads of the register-resident node can be folded by the compiler into
+// a load through a selected address, which spills the node to scratch.
+template <int W>
+__device__ __forceinline__ int32_t child_at(const NodeBuf<W>& b, uint32_t slot)
+{
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) c |= (uint32_t)b.n.child[j] & (0u - (uint32_t)(slot == (uint32_t)j));
+    return (int32_t)c;
+}
+
+__device__ __forceinline__ bool ref_is_leaf(int32_t c) { return c < 0; }
+__device__ __forceinline__ uint32_t leaf_first(int32_t c) { return ((uint32_t)~c) >> 3; }
+__device__ __forceinline__ uint32_t leaf_count(int32_t c) { return (((uint32_t)~c) & 7u) + 1u; }
+__host__ __device__ __forceinline__ int32_t make_leaf(uint32_t first, uint32_t count)
+{
+    return (int32_t)~((first << 3) | (count - 1u));
+}
+constexpr int32_t kEmptyChild = 0x7FFFFFFF;
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with Weyl-sequence key bumps between rounds.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a_hi = __umulhi(0xD2511F53u, c.x);
+        const uint32_t a_lo = 0xD2511F53u * c.x;
+        const uint32_t b_hi = __umulhi(0xCD9E8D57u, c.z);
+        const uint32_t b_lo = 0xCD9E8D57u * c.z;
+        c = make_uint4(b_hi ^ c.y ^ k0, b_lo, a_hi ^ c.w ^ k1, a_lo);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4& w, uint32_t i)
+{
+    return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
+}
+
+// u in [0, 1 - 2^-24], exact in FP32 and FP64.
+__device__ __forceinline__ double u_of_word(uint32_t w) { return (double)(w >> 8) * 0x1p-24; }
+
+// --------------------------------------------------------------------------
+// Real spherical harmonics up to degree 3 at a unit direction, orthonormal,
+// Condon-Shortley phase, index l*l + l + m (m = -l..l).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void sh_eval(int deg, float x, float y, float z, float* Y)
+{
+    Y[0] = 0.28209479177387814f;
+    if (deg < 1) return;
+    const float k1 = 0.48860251190291987f;
+    Y[1] = -k1 * y;
+    Y[2] = k1 * z;
+    Y[3] = -k1 * x;
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float xy = x * y, yz = y * z, xz = x * z;
+    Y[4] = 1.0925484305920792f * xy;
+    Y[5] = -1.0925484305920792f * yz;
+    Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * xz;
+    Y[8] = 0.54627421529603959f * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -0.59004358992664352f * y * (3.0f * xx - yy);
+    Y[10] = 2.8906114426405538f * xy * z;
+    Y[11] = -0.45704579946446577f * y * (4.0f * zz - xx - yy);
+    Y[12] = 0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -0.45704579946446577f * x * (4.0f * zz - xx - yy);
+    Y[14] = 1.4453057213202769f * z * (xx - yy);
+    Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
+}
+
+// Unclamped SH colour sum of Gaussian gid (0.5 + sum k Y).
+__device__ __forceinline__ float3 sh_colour_pre(const float* sh, int deg, int32_t gid, const float* Y)
+{
+    const int K = (deg + 1) * (deg + 1);
+    const float* p = sh + (size_t)gid * (size_t)(3 * K);
+    float r = 0.5f, g = 0.5f, b = 0.5f;
+    for (int j = 0; j < K; ++j) {
+        r = fmaf(p[3 * j + 0], Y[j], r);
+        g = fmaf(p[3 * j + 1], Y[j], g);
+        b = fmaf(p[3 * j + 2], Y[j], b);
+    }
+    return make_float3(r, g, b);
+}
+
+__device__ __forceinline__ float3 clamp0(float3 c)
+{
+    return make_float3(fmaxf(c.x, 0.0f), fmaxf(c.y, 0.0f), fmaxf(c.z, 0.0f));
+}
+
+// --------------------------------------------------------------------------
+// Ray state and the conservative slab test.
+// Node culling only has to be conservative: a box that contains a valid
+// candidate's 1D-Gaussian mean must never be culled. The FP32 box contains
+// the FP64 ellipsoid (rounded outward); Ize's robust factor 1 + 2*gamma_3 on
+// the exit distance covers the slab arithmetic; the depth cut carries a
+// 2^-20 relative slack, far above the few-ulp error of the entry distance.
+// --------------------------------------------------------------------------
+constexpr float kIzeFactor = 1.0000003576278687f;  // 1 + 2 gamma_3, gamma_3 = 3u/(1-3u)
+constexpr float kCutSlack = 1.00000095367431641f;  // 1 + 2^-20
+
+struct RayF {
+    float ox, oy, oz;
+    float ix, iy, iz;  // 1 / d, with |d_i| clamped away from 0
+    float tmin;
+};
+
+__device__ __forceinline__ float safe_inv(float d)
+{
+    const float a = fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
+    return 1.0f / a;
+}
+
+// Hit mask and near-to-far sort keys of the W children of a node.
+template <int W>
+__device__ __forceinline__ void slab_keys(const NodeBuf<W>& b, const RayF& r, float tcut,
+                                          uint32_t key[W])
+{
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        const float ax = (b.n.lo[0][c] - r.ox) * r.ix, bx = (b.n.hi[0][c] - r.ox) * r.ix;
+        const float ay = (b.n.lo[1][c] - r.oy) * r.iy, by = (b.n.hi[1][c] - r.oy) * r.iy;
+        const float az = (b.n.lo[2][c] - r.oz) * r.iz, bz = (b.n.hi[2][c] - r.oz) * r.iz;
+        const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
+        const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz)) * kIzeFactor;
+        const bool hit = (t0 <= t1) & (t0 <= tcut) & (t1 >= r.tmin) & (b.n.child[c] != kEmptyChild);
+        const float tn = fmaxf(t0, 0.0f);
+        key[c] = hit ? ((__float_as_uint(tn) & ~7u) | (uint32_t)c) : 0xFFFFFFFFu;
+    }
+}
+
+__device__ __forceinline__ void cswap(uint32_t& a, uint32_t& b)
+{
+    const uint32_t lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+}
+
+// Ascending sort of W keys (optimal networks for 2, 4 and 8 inputs).
+template <int W>
+__device__ __forceinline__ void sort_keys(uint32_t k[W]);
+
+template <>
+__device__ __forceinline__ void sort_keys<2>(uint32_t k[2])
+{
+    cswap(k[0], k[1]);
+}
+
+template <>
+__device__ __forceinline__ void sort_keys<4>(uint32_t k[4])
+{
+    cswap(k[0], k[1]);
+    cswap(k[2], k[3]);
+    cswap(k[0], k[2]);
+    cswap(k[1], k[3]);
+    cswap(k[1], k[2]);
+}
+
+template <>
+__device__ __forceinline__ void sort_keys<8>(uint32_t k[8])
+{
+    cswap(k[0], k[2]); cswap(k[1], k[3]); cswap(k[4], k[6]); cswap(k[5], k[7]);
+    cswap(k[0], k[4]); cswap(k[1], k[5]); cswap(k[2], k[6]); cswap(k[3], k[7]);
+    cswap(k[0], k[1]); cswap(k[2], k[3]); cswap(k[4], k[5]); cswap(k[6], k[7]);
+    cswap(k[2], k[4]); cswap(k[3], k[5]);
+    cswap(k[1], k[4]); cswap(k[3], k[6]);
+    cswap(k[1], k[2]); cswap(k[3], k[4]); cswap(k[5], k[6]);
+}
+
+// --------------------------------------------------------------------------
+// Candidate test in FP64 (Sec. 3.1 and eqn "cuboid"): the ray x(t) = o + t d
+// cuts the Gaussian in a 1D Gaussian with mean t* = -(o'.d')/(d'.d'), where
+// o' = M (o - mu) and d' = M d; q = |o' + t* d'|^2 and alpha = o exp(-q/2).
+// --------------------------------------------------------------------------
+struct RayD {
+    double ox, oy, oz, dx, dy, dz;
+};
+
+struct Isect {
+    double t, q;
+    double p[3];  // whitened position at t*
+    double w[3];  // world offset x(t*) - mu
+};
+
+__device__ __forceinline__ void isect_record(const Record& r, const RayD& ray, Isect& out)
+{
+    const double wx = ray.ox - (double)r.mu[0];
+    const double wy = ray.oy - (double)r.mu[1];
+    const double wz = ray.oz - (double)r.mu[2];
+    double op[3], dp[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double m0 = r.M[3 * i], m1 = r.M[3 * i + 1], m2 = r.M[3 * i + 2];
+        op[i] = fma(m2, wz, fma(m1, wy, m0 * wx));
+        dp[i] = fma(m2, ray.dz, fma(m1, ray.dy, m0 * ray.dx));
+    }
+    const double dd = fma(dp[2], dp[2], fma(dp[1], dp[1], dp[0] * dp[0]));
+    const double od = fma(op[2], dp[2], fma(op[1], dp[1], op[0] * dp[0]));
+    const double t = -od / dd;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out.p[i] = fma(t, dp[i], op[i]);
+    out.q = fma(out.p[2], out.p[2], fma(out.p[1], out.p[1], out.p[0] * out.p[0]));
+    out.t = t;
+    out.w[0] = fma(t, ray.dx, wx);
+    out.w[1] = fma(t, ray.dy, wy);
+    out.w[2] = fma(t, ray.dz, wz);
+}
+
+// Only t and q (the forward needs nothing else).
+__device__ __forceinline__ void isect_tq(const Record& r, const RayD& ray, double& t_out,
+                                         double& q_out)
+{
+    const double wx = ray.ox - (double)r.mu[0];
+    const double wy = ray.oy - (double)r.mu[1];
+    const double wz = ray.oz - (double)r.mu[2];
+    double op[3], dp[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double m0 = r.M[3 * i], m1 = r.M[3 * i + 1], m2 = r.M[3 * i + 2];
+        op[i] = fma(m2, wz, fma(m1, wy, m0 * wx));
+        dp[i] = fma(m2, ray.dz, fma(m1, ray.dy, m0 * ray.dx));
+    }
+    const double dd = fma(dp[2], dp[2], fma(dp[1], dp[1], dp[0] * dp[0]));
+    const double od = fma(op[2], dp[2], fma(op[1], dp[1], op[0] * dp[0]));
+    const double t = -od / dd;
+    const double p0 = fma(t, dp[0], op[0]);
+    const double p1 = fma(t, dp[1], op[1]);
+    const double p2 = fma(t, dp[2], op[2]);
+    t_out = t;
+    q_out = fma(p2, p2, fma(p1, p1, p0 * p0));
+}
+
+__device__ __forceinline__ Record load_record(const Record* recs, uint32_t i)
+{
+    const float4* p = reinterpret_cast<const float4*>(recs + i);
+    const float4 a = p[0], b = p[1], c = p[2], d = p[3];
+    Record r;
+    r.mu[0] = a.x; r.mu[1] = a.y; r.mu[2] = a.z; r.M[0] = a.w;
+    r.M[1] = b.x; r.M[2] = b.y; r.M[3] = b.z; r.M[4] = b.w;
+    r.M[5] = c.x; r.M[6] = c.y; r.M[7] = c.z; r.M[8] = c.w;
+    r.opacity = d.x; r.gid = __float_as_int(d.y); r.pad[0] = d.z; r.pad[1] = d.w;
+    return r;
+}
+
+// (t, gid) lexicographic order of depth keys.
+__device__ __forceinline__ bool key_less(float ta, int32_t ga, float tb, int32_t gb)
+{
+    return ta < tb || (ta == tb && ga < gb);
+}
+
+// Wave-level sum, then one atomic per wave.
+__device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+
+}  // namespace srt

@@ -1,0 +1,77 @@
+// Host-side internals shared by the translation units of libsrt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "srt.h"
+#include "srt_device.hpp"
+
+struct srt_bvh {
+    int64_t G = 0;
+    int32_t W = 4, L = 4, depth = 0, deg = 0;
+    int64_t num_nodes = 0;
+    void* nodes = nullptr;           // WideNode<W>[num_nodes]
+    srt::Record* recs = nullptr;     // leaf order
+    int32_t* leaf_order = nullptr;   // Gaussian id at each leaf position
+    float* box_lo = nullptr;         // [G,3], Gaussian-id order
+    float* box_hi = nullptr;
+    const float* sh = nullptr;       // borrowed from the scene
+    int64_t bytes = 0;
+};
+
+namespace srt {
+
+#define SRT_HIP_TRY(expr)                              \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return map_hip_error(e_); \
+    } while (0)
+
+inline srt_status map_hip_error(hipError_t e)
+{
+    return e == hipErrorOutOfMemory ? SRT_ERR_OOM : SRT_ERR_HIP;
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Deep-stack fallback: fixed grid of lanes that rerun rays whose on-chip
+// stack overflowed, each with a stack in global memory.
+constexpr int kDeepThreads = 16384;
+
+inline int32_t deep_stack_cap(const srt_bvh* b)
+{
+    // a wide traversal pushes at most W-1 entries per level below the root
+    return (b->depth + 2) * b->W + 8;
+}
+
+// Trace workspace layout.
+struct TraceWorkspace {
+    uint32_t* ctrl;        // [64]: [0] overflow count
+    uint32_t* ovf_list;    // [R]
+    int32_t* deep_stack;   // [kDeepThreads * cap]
+    size_t bytes;
+};
+
+inline TraceWorkspace trace_workspace(const srt_bvh* b, int64_t R, void* base)
+{
+    TraceWorkspace w{};
+    size_t off = 0;
+    char* p = static_cast<char*>(base);
+    w.ctrl = reinterpret_cast<uint32_t*>(p + off);
+    off += 256;
+    w.ovf_list = reinterpret_cast<uint32_t*>(p + off);
+    off = align_up(off + (size_t)(R > 0 ? R : 1) * 4, 256);
+    w.deep_stack = reinterpret_cast<int32_t*>(p + off);
+    off = align_up(off + (size_t)kDeepThreads * (size_t)deep_stack_cap(b) * 4, 256);
+    w.bytes = off;
+    return w;
+}
+
+// Fill a device array with a 32-bit value (used instead of a memset so the
+// work is capturable in graphs).
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+
+}  // namespace srt

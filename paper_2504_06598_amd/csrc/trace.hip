@@ -1,0 +1,714 @@
+// Forward stochastic ray tracing on gfx950.
+//
+// One lane per ray. The lane walks the W-wide BVH with a per-lane stack in
+// LDS (stride = block size, so the 64 lanes of a wave hit 64 distinct banks
+// whatever their depths), visiting hit children near to far. Each Gaussian of
+// a reached leaf is tested in FP64 (Sec. 3.1, eqn "cuboid"); a valid one
+// draws u from Philox per sample and is accepted iff u < alpha (eqn "rr");
+// each of the N samples of the traversal keeps its closest accepted
+// (depth, id) (eqns "cloest", "multisample"). Once every sample holds a hit,
+// boxes entering beyond the farthest of them are culled (the clipping of the
+// paper's ReportIntersection). A lane whose stack overflows abandons the ray
+// and queues it; a second launch reruns queued rays with a stack in global
+// memory sized by the tree depth.
+#include <algorithm>
+#include <climits>
+
+#include "srt_internal.hpp"
+
+using namespace srt;
+
+namespace {
+
+constexpr int kBlock = 128;
+
+template <int W>
+struct LdsStack {
+    static constexpr int value = (W == 8) ? 48 : 32;
+};
+
+struct TraceArgs {
+    const void* nodes;
+    const Record* recs;
+    const float* sh;
+    int32_t deg;
+    int64_t R;
+    const float* o;
+    const float* d;
+    const float* tmin;
+    const float* tmax;
+    const int32_t* ign;
+    const uint32_t* rid;
+    const uint32_t* sid;
+    uint32_t purpose;
+    uint32_t k0, k1;
+    int32_t spp;
+    uint32_t soff;
+    float bg[3];
+    int32_t stack_cap;
+    float* rgb;
+    int32_t* hit_gid;
+    float* hit_t;
+    unsigned long long* counters;
+    uint32_t* ctrl;  // [0] overflow count, [1] rays lost by the deep pass
+    uint32_t* ovf_list;
+    int32_t* deep_stack;
+    int32_t deep_cap;
+    int64_t max_steps;  // bound on loop iterations of one traversal (a tree visits
+                        // each node once); exceeding it marks the ray as lost
+};
+
+struct Counts {
+    uint32_t trav = 0, nodes = 0, prims = 0, cands = 0, philox = 0, samples = 0;
+};
+
+// Traverse once for samples s0 .. s0 + n_act - 1 of one ray. Returns false if
+// the stack would overflow (the results are then incomplete).
+template <int W, int N, bool ANY>
+__device__ __forceinline__ bool traverse(const TraceArgs& a, const RayF& rf, const RayD& rd,
+                                         double tmin, double tmax, int32_t ign, uint32_t rid,
+                                         uint32_t s0, int n_act, int32_t* stk, int stride, int cap,
+                                         float (&bt)[N], int32_t (&bgid)[N], Counts& cnt)
+{
+    const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        bt[k] = k < n_act ? INFINITY : -INFINITY;
+        bgid[k] = INT_MAX;
+    }
+    const float tmax_f = (float)tmax;
+    float tcut = tmax_f;
+    float wt = INFINITY;
+    int32_t wg = INT_MAX;
+    int sp = 0;
+    int32_t node = 0;
+    ++cnt.trav;
+    for (int64_t step = 0;; ++step) {
+        if (step > a.max_steps) return false;
+        if (node >= 0) {
+            ++cnt.nodes;
+            NodeBuf<W> b;
+            load_node<W>(nodes, node, b);
+            uint32_t key[W];
+            slab_keys<W>(b, rf, tcut, key);
+            sort_keys<W>(key);
+            int nh = 0;
+#pragma unroll
+            for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
+            if (nh > 0) {
+                if (sp + nh - 1 > cap) return false;
+#pragma unroll
+                for (int c = W - 1; c >= 1; --c)
+                    if (key[c] != 0xFFFFFFFFu) {
+                        stk[sp * stride] = child_at<W>(b, key[c] & 7u);
+                        ++sp;
+                    }
+                node = child_at<W>(b, key[0] & 7u);
+                continue;
+            }
+        } else {
+            const uint32_t first = leaf_first(node), count = leaf_count(node);
+            bool any_accept = false;
+            for (uint32_t i = 0; i < count; ++i) {
+                ++cnt.prims;
+                const Record r = load_record(a.recs, first + i);
+                double t, q;
+                isect_tq(r, rd, t, q);
+                if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) continue;
+                ++cnt.cands;
+                const float t32 = (float)t;
+                if (!key_less(t32, r.gid, wt, wg)) continue;
+                const double alpha = (double)r.opacity * exp(-0.5 * q);
+                uint4 w = make_uint4(0, 0, 0, 0);
+                uint32_t grp = 0xFFFFFFFFu;
+                bool changed = false;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    if (k < n_act && key_less(t32, r.gid, bt[k], bgid[k])) {
+                        const uint32_t s = s0 + (uint32_t)k;
+                        if ((s >> 2) != grp) {
+                            grp = s >> 2;
+                            w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, a.purpose), a.k0,
+                                              a.k1);
+                            ++cnt.philox;
+                        }
+                        if (u_of_word(word_of(w, s & 3u)) < alpha) {
+                            bt[k] = t32;
+                            bgid[k] = r.gid;
+                            changed = true;
+                        }
+                    }
+                }
+                if (changed) {
+                    if (ANY) {
+                        any_accept = true;
+                        break;
+                    }
+                    wt = -INFINITY;
+                    wg = INT_MIN;
+#pragma unroll
+                    for (int k = 0; k < N; ++k)
+                        if (k < n_act && key_less(wt, wg, bt[k], bgid[k])) {
+                            wt = bt[k];
+                            wg = bgid[k];
+                        }
+                    tcut = fminf(wt + fabsf(wt) * 0x1p-20f + 1e-30f, tmax_f);
+                }
+            }
+            if (ANY && any_accept) return true;
+        }
+        if (sp == 0) break;
+        --sp;
+        node = stk[sp * stride];
+    }
+    return true;
+}
+
+// Trace every pass of one ray, shade and write its outputs. Returns false on
+// a stack overflow (nothing is written then).
+template <int W, int N, bool ANY>
+__device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32_t* stk, int stride,
+                                          int cap, Counts& cnt)
+{
+    const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
+    const float dx = a.d[3 * ray], dy = a.d[3 * ray + 1], dz = a.d[3 * ray + 2];
+    const float tmin_f = a.tmin ? a.tmin[ray] : 0.0f;
+    const float tmax_f = a.tmax ? a.tmax[ray] : INFINITY;
+    const int32_t ign = a.ign ? a.ign[ray] : -1;
+    const uint32_t rid = a.rid ? a.rid[ray] : (uint32_t)ray;
+    const uint32_t sbase = (a.sid ? a.sid[ray] : 0u) + a.soff;
+    const bool live = tmax_f > tmin_f;
+
+    RayF rf;
+    rf.ox = ox; rf.oy = oy; rf.oz = oz;
+    rf.ix = safe_inv(dx); rf.iy = safe_inv(dy); rf.iz = safe_inv(dz);
+    rf.tmin = tmin_f;
+    RayD rd{ox, oy, oz, dx, dy, dz};
+
+    const bool shade = a.rgb != nullptr && !ANY;
+    float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+    for (int pass = 0; pass * N < a.spp; ++pass) {
+        const int n_act = min(N, a.spp - pass * N);
+        float bt[N];
+        int32_t bgid[N];
+        if (live) {
+            if (!traverse<W, N, ANY>(a, rf, rd, (double)tmin_f, (double)tmax_f, ign, rid,
+                                     sbase + (uint32_t)(pass * N), n_act, stk, stride, cap, bt,
+                                     bgid, cnt))
+                return false;
+            cnt.samples += (uint32_t)n_act;
+        } else {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                bt[k] = INFINITY;
+                bgid[k] = INT_MAX;
+            }
+        }
+        // the SH basis is formed after the traversal so it is not live during it
+        float Y[16];
+        if (shade) {
+            const float n = sqrtf(dx * dx + dy * dy + dz * dz);
+            sh_eval(a.deg, dx / n, dy / n, dz / n, Y);
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (k >= n_act) continue;
+            const bool hit = bgid[k] != INT_MAX;
+            const int64_t o = ray * a.spp + pass * N + k;
+            if (a.hit_gid) a.hit_gid[o] = hit ? bgid[k] : -1;
+            if (a.hit_t) a.hit_t[o] = hit ? bt[k] : INFINITY;
+            if (ANY) {
+                const float v = hit ? 0.0f : 1.0f;
+                acc0 += v; acc1 += v; acc2 += v;
+            } else if (shade) {
+                if (hit) {
+                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, bgid[k], Y));
+                    acc0 += c.x; acc1 += c.y; acc2 += c.z;
+                } else {
+                    acc0 += a.bg[0]; acc1 += a.bg[1]; acc2 += a.bg[2];
+                }
+            }
+        }
+    }
+    if (a.rgb) {
+        const float inv = 1.0f / (float)a.spp;
+        a.rgb[3 * ray] = acc0 * inv;
+        a.rgb[3 * ray + 1] = acc1 * inv;
+        a.rgb[3 * ray + 2] = acc2 * inv;
+    }
+    return true;
+}
+
+template <int W, int N, bool ANY, bool DEEP>
+__global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
+{
+    __shared__ int32_t lds[DEEP ? 1 : LdsStack<W>::value * kBlock];
+    int32_t* stk;
+    int stride, cap;
+    const int64_t gt = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (DEEP) {
+        stk = a.deep_stack + gt;
+        stride = kDeepThreads;
+        cap = a.deep_cap;
+    } else {
+        stk = lds + threadIdx.x;
+        stride = kBlock;
+        cap = min(LdsStack<W>::value, a.stack_cap);
+    }
+    Counts cnt;
+    uint32_t deep_runs = 0, lost = 0;
+    if (DEEP) {
+        const int64_t n = (int64_t)a.ctrl[0];
+        for (int64_t it = gt; it < n; it += (int64_t)gridDim.x * kBlock) {
+            const int64_t ray = a.ovf_list[it];
+            ++deep_runs;
+            if (!trace_ray<W, N, ANY>(a, ray, stk, stride, cap, cnt)) {
+                atomicAdd(&a.ctrl[1], 1u);
+                ++lost;
+            }
+        }
+    } else if (gt < a.R) {
+        if (!trace_ray<W, N, ANY>(a, gt, stk, stride, cap, cnt)) {
+            const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+            a.ovf_list[slot] = (uint32_t)gt;
+        }
+    }
+    if (a.counters) {
+        // every lane of the wave reaches this point (no early return above)
+        wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, cnt.trav);
+        wave_add_u64(a.counters + SRT_CNT_NODES, cnt.nodes);
+        wave_add_u64(a.counters + SRT_CNT_PRIMS, cnt.prims);
+        wave_add_u64(a.counters + SRT_CNT_CANDIDATES, cnt.cands);
+        wave_add_u64(a.counters + SRT_CNT_PHILOX, cnt.philox);
+        wave_add_u64(a.counters + SRT_CNT_DEEP, deep_runs);
+        wave_add_u64(a.counters + SRT_CNT_RAY_SAMPLES, cnt.samples);
+        wave_add_u64(a.counters + SRT_CNT_LOST, lost);
+    }
+}
+
+using KernelFn = void (*)(TraceArgs);
+
+template <int W, int N, bool ANY>
+void pick(KernelFn* fast, KernelFn* deep)
+{
+    *fast = k_trace<W, N, ANY, false>;
+    *deep = k_trace<W, N, ANY, true>;
+}
+
+template <int W>
+bool pick_w(int N, bool any, KernelFn* f, KernelFn* d)
+{
+    if (any) {
+        if (N != 1) return false;
+        pick<W, 1, true>(f, d);
+        return true;
+    }
+    switch (N) {
+    case 1: pick<W, 1, false>(f, d); return true;
+    case 2: pick<W, 2, false>(f, d); return true;
+    case 4: pick<W, 4, false>(f, d); return true;
+    case 8: pick<W, 8, false>(f, d); return true;
+    }
+    return false;
+}
+
+bool pick_kernels(int W, int N, bool any, KernelFn* f, KernelFn* d)
+{
+    switch (W) {
+    case 2: return pick_w<2>(N, any, f, d);
+    case 4: return pick_w<4>(N, any, f, d);
+    case 8: return pick_w<8>(N, any, f, d);
+    }
+    return false;
+}
+
+srt_status validate_opts(const srt_trace_opts* o)
+{
+    if (!o) return SRT_ERR_INVALID_ARG;
+    if (o->spp < 1) return SRT_ERR_INVALID_ARG;
+    const int N = o->n_per_traversal;
+    if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
+    if (o->any_hit && N != 1) return SRT_ERR_INVALID_ARG;
+    if (o->stack_limit < 0) return SRT_ERR_INVALID_ARG;
+    return SRT_OK;
+}
+
+// Enqueue the fast and deep traversal launches for an explicit ray set.
+srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_opts* o,
+                        float* rgb, int32_t* hit_gid, float* hit_t, uint64_t* counters,
+                        void* workspace, hipStream_t s)
+{
+    KernelFn fast = nullptr, deep = nullptr;
+    if (!pick_kernels(b->W, o->n_per_traversal, o->any_hit != 0, &fast, &deep))
+        return SRT_ERR_UNSUPPORTED;
+    const TraceWorkspace ws = trace_workspace(b, rays->count, workspace);
+    TraceArgs a{};
+    a.nodes = b->nodes;
+    a.recs = b->recs;
+    a.sh = b->sh;
+    a.deg = b->deg;
+    a.R = rays->count;
+    a.o = rays->origins;
+    a.d = rays->dirs;
+    a.tmin = rays->tmin;
+    a.tmax = rays->tmax;
+    a.ign = rays->ignore_gid;
+    a.rid = rays->ray_ids;
+    a.sid = rays->sample_ids;
+    a.purpose = rays->purpose;
+    a.k0 = (uint32_t)o->seed;
+    a.k1 = (uint32_t)(o->seed >> 32);
+    a.spp = o->spp;
+    a.soff = o->sample_offset;
+    for (int i = 0; i < 3; ++i) a.bg[i] = o->bg[i];
+    a.stack_cap = o->stack_limit > 0 ? o->stack_limit : INT_MAX;
+    a.rgb = rgb;
+    a.hit_gid = hit_gid;
+    a.hit_t = hit_t;
+    a.counters = reinterpret_cast<unsigned long long*>(counters);
+    a.ctrl = ws.ctrl;
+    a.ovf_list = ws.ovf_list;
+    a.deep_stack = ws.deep_stack;
+    a.deep_cap = deep_stack_cap(b);
+    a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
+    fill_u32(ws.ctrl, 0u, 2, s);
+    if (rays->count > 0) {
+        const unsigned grid = (unsigned)((rays->count + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(fast, dim3(grid), dim3(kBlock), 0, s, a);
+        SRT_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(deep, dim3(kDeepThreads / kBlock), dim3(kBlock), 0, s, a);
+        SRT_HIP_TRY(hipGetLastError());
+    }
+    return SRT_OK;
+}
+
+// --------------------------------------------------------------------------
+// Camera rays (canonical FP32; this translation unit is compiled without
+// floating-point contraction, and FP32 division and square root are
+// correctly rounded).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void camera_ray(const srt_camera& c, int32_t x, int32_t y, float o[3],
+                                           float d[3])
+{
+    const float aspect = (float)c.width / (float)c.height;
+    const float px = ((float)x + 0.5f) / (float)c.width;
+    const float sx = ((px * 2.0f) - 1.0f) * c.tan_half * aspect;
+    const float py = ((float)y + 0.5f) / (float)c.height;
+    const float sy = (1.0f - (py * 2.0f)) * c.tan_half;
+    float v[3];
+    for (int i = 0; i < 3; ++i) {
+        const float a = sx * c.right[i];
+        const float b = sy * c.up[i];
+        v[i] = (c.forward[i] + a) + b;
+    }
+    const float xx = v[0] * v[0];
+    const float yy = v[1] * v[1];
+    const float zz = v[2] * v[2];
+    const float n = sqrtf((xx + yy) + zz);
+    for (int i = 0; i < 3; ++i) {
+        d[i] = v[i] / n;
+        o[i] = c.eye[i];
+    }
+}
+
+__global__ void k_camera_rays(srt_camera c, float* __restrict__ o, float* __restrict__ d)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t R = (int64_t)c.width * c.height;
+    if (p >= R) return;
+    float oo[3], dd[3];
+    camera_ray(c, (int32_t)(p % c.width), (int32_t)(p / c.width), oo, dd);
+    for (int i = 0; i < 3; ++i) {
+        o[3 * p + i] = oo[i];
+        d[3 * p + i] = dd[i];
+    }
+}
+
+// --------------------------------------------------------------------------
+// Path-tracer mix: spawn secondaries from camera hits, then compose.
+// --------------------------------------------------------------------------
+struct SecRays {
+    float *o, *d, *tmin, *tmax;
+    int32_t* ign;
+    uint32_t *rid, *sid;
+};
+
+__global__ void k_spawn(int64_t R, int32_t spp, uint32_t rid_base, const float* __restrict__ co,
+                        const float* __restrict__ cd, const int32_t* __restrict__ cam_gid,
+                        const float* __restrict__ cam_t, srt_pathmix_opts pm, SecRays sh,
+                        SecRays mr)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= R * spp) return;
+    const int64_t p = idx / spp;
+    const uint32_t s = (uint32_t)(idx % spp);
+    const float o[3] = {co[3 * p], co[3 * p + 1], co[3 * p + 2]};
+    const float d[3] = {cd[3 * p], cd[3 * p + 1], cd[3 * p + 2]};
+    const int32_t g = cam_gid[idx];
+    const float tg = g >= 0 ? cam_t[idx] : INFINITY;
+    float tp = INFINITY;
+    if (d[1] < 0.0f) {
+        const float num = pm.plane_y - o[1];
+        const float tt = num / d[1];
+        if (tt > 0.0f) tp = tt;
+    }
+    const bool on_gauss = g >= 0 && tg <= tp;
+    const bool on_plane = !on_gauss && tp < INFINITY;
+    const uint32_t rid = rid_base + (uint32_t)p;
+    // empty slots: tmin = 1 > tmax = 0 (the trace skips them)
+    sh.tmin[idx] = 1.0f;
+    sh.tmax[idx] = 0.0f;
+    mr.tmin[idx] = 1.0f;
+    mr.tmax[idx] = 0.0f;
+    for (int i = 0; i < 3; ++i) {
+        sh.o[3 * idx + i] = 0.0f;
+        sh.d[3 * idx + i] = 0.0f;
+        mr.o[3 * idx + i] = 0.0f;
+        mr.d[3 * idx + i] = 0.0f;
+    }
+    sh.ign[idx] = -1;
+    mr.ign[idx] = -1;
+    sh.rid[idx] = rid;
+    mr.rid[idx] = rid;
+    sh.sid[idx] = s;
+    mr.sid[idx] = s;
+    if (!on_gauss && !on_plane) return;
+    const float t = on_gauss ? tg : tp;
+    float P[3];
+    for (int i = 0; i < 3; ++i) {
+        const float prod = t * d[i];
+        P[i] = o[i] + prod;
+    }
+    if (on_plane) P[1] = pm.plane_y;
+    const float v[3] = {pm.light[0] - P[0], pm.light[1] - P[1], pm.light[2] - P[2]};
+    const float vx2 = v[0] * v[0];
+    const float vy2 = v[1] * v[1];
+    const float vz2 = v[2] * v[2];
+    const float len = sqrtf((vx2 + vy2) + vz2);
+    for (int i = 0; i < 3; ++i) {
+        sh.o[3 * idx + i] = P[i];
+        sh.d[3 * idx + i] = v[i] / len;
+    }
+    sh.tmin[idx] = pm.tmin_secondary;
+    sh.tmax[idx] = len;
+    sh.ign[idx] = on_gauss ? g : -1;
+    if (on_plane) {
+        for (int i = 0; i < 3; ++i) mr.o[3 * idx + i] = P[i];
+        mr.d[3 * idx] = d[0];
+        mr.d[3 * idx + 1] = -d[1];
+        mr.d[3 * idx + 2] = d[2];
+        mr.tmin[idx] = pm.tmin_secondary;
+        mr.tmax[idx] = INFINITY;
+    }
+}
+
+__global__ void k_compose(int64_t R, int32_t spp, int32_t deg, const float* __restrict__ sh,
+                          const float* __restrict__ cd, const int32_t* __restrict__ cam_gid,
+                          SecRays shr, SecRays mrr, const int32_t* __restrict__ sh_hit,
+                          const int32_t* __restrict__ mr_hit, float bg0, float bg1, float bg2,
+                          float* __restrict__ rgb, uint8_t* __restrict__ vis_out,
+                          int32_t* __restrict__ mirror_out)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= R) return;
+    const float dx = cd[3 * p], dy = cd[3 * p + 1], dz = cd[3 * p + 2];
+    const float n = sqrtf(dx * dx + dy * dy + dz * dz);
+    float Yc[16], Ym[16];
+    sh_eval(deg, dx / n, dy / n, dz / n, Yc);
+    sh_eval(deg, dx / n, -dy / n, dz / n, Ym);
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    for (int32_t s = 0; s < spp; ++s) {
+        const int64_t i = p * spp + s;
+        const bool has_shadow = shr.tmax[i] > shr.tmin[i];
+        const bool has_mirror = mrr.tmax[i] > mrr.tmin[i];
+        float c0 = bg0, c1 = bg1, c2 = bg2;
+        uint8_t vis = 255;
+        int32_t mg = -2;
+        if (has_shadow) {
+            const float V = sh_hit[i] < 0 ? 1.0f : 0.0f;
+            vis = sh_hit[i] < 0 ? 1 : 0;
+            if (!has_mirror) {
+                const float3 c = clamp0(sh_colour_pre(sh, deg, cam_gid[i], Yc));
+                const float f = 0.3f + 0.7f * V;
+                c0 = c.x * f; c1 = c.y * f; c2 = c.z * f;
+            } else {
+                float3 Lm = make_float3(bg0, bg1, bg2);
+                mg = mr_hit[i];
+                if (mg >= 0) Lm = clamp0(sh_colour_pre(sh, deg, mg, Ym));
+                const float nl = fmaxf(shr.d[3 * i + 1], 0.0f);
+                const float lit = 0.5f * V * nl;
+                c0 = lit + 0.5f * Lm.x; c1 = lit + 0.5f * Lm.y; c2 = lit + 0.5f * Lm.z;
+            }
+        }
+        a0 += c0; a1 += c1; a2 += c2;
+        if (vis_out) vis_out[i] = vis;
+        if (mirror_out) mirror_out[i] = mg;
+    }
+    const float inv = 1.0f / (float)spp;
+    rgb[3 * p] = a0 * inv;
+    rgb[3 * p + 1] = a1 * inv;
+    rgb[3 * p + 2] = a2 * inv;
+}
+
+__global__ void k_iota(uint32_t* p, uint32_t base, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = base + (uint32_t)i;
+}
+
+struct PathmixWs {
+    float *co, *cd;
+    int32_t* cam_gid;
+    float* cam_t;
+    SecRays sh, mr;
+    int32_t *sh_hit, *mr_hit;
+    void* trace_ws;
+    size_t bytes;
+};
+
+PathmixWs pathmix_ws(const srt_bvh* b, int64_t R, int32_t spp, void* base)
+{
+    PathmixWs w{};
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    const int64_t n = R * spp;
+    auto take = [&](size_t bytes) {
+        void* q = p ? p + off : nullptr;
+        off = align_up(off + bytes, 256);
+        return q;
+    };
+    w.co = static_cast<float*>(take(12 * (size_t)R));
+    w.cd = static_cast<float*>(take(12 * (size_t)R));
+    w.cam_gid = static_cast<int32_t*>(take(4 * (size_t)n));
+    w.cam_t = static_cast<float*>(take(4 * (size_t)n));
+    for (SecRays* s : {&w.sh, &w.mr}) {
+        s->o = static_cast<float*>(take(12 * (size_t)n));
+        s->d = static_cast<float*>(take(12 * (size_t)n));
+        s->tmin = static_cast<float*>(take(4 * (size_t)n));
+        s->tmax = static_cast<float*>(take(4 * (size_t)n));
+        s->ign = static_cast<int32_t*>(take(4 * (size_t)n));
+        s->rid = static_cast<uint32_t*>(take(4 * (size_t)n));
+        s->sid = static_cast<uint32_t*>(take(4 * (size_t)n));
+    }
+    w.sh_hit = static_cast<int32_t*>(take(4 * (size_t)n));
+    w.mr_hit = static_cast<int32_t*>(take(4 * (size_t)n));
+    TraceWorkspace tw = trace_workspace(b, n, nullptr);
+    w.trace_ws = take(tw.bytes);
+    w.bytes = off;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t srt_trace_workspace_size(const srt_bvh* b, int64_t num_rays)
+{
+    if (!b || num_rays < 0) return 0;
+    return trace_workspace(b, num_rays, nullptr).bytes;
+}
+
+srt_status srt_trace_forward(const srt_bvh* b, const srt_rays* rays, const srt_trace_opts* opts,
+                             float* rgb, int32_t* hit_gid, float* hit_t, uint64_t* counters,
+                             void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!b || !rays) return SRT_ERR_INVALID_ARG;
+    const srt_status vs = validate_opts(opts);
+    if (vs != SRT_OK) return vs;
+    if (rays->count < 0 || rays->count > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;
+    if (rays->count > 0 && (!rays->origins || !rays->dirs)) return SRT_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < srt_trace_workspace_size(b, rays->count))
+        return SRT_ERR_WORKSPACE;
+    return launch_trace(b, rays, opts, rgb, hit_gid, hit_t, counters, workspace,
+                        static_cast<hipStream_t>(stream));
+}
+
+srt_status srt_camera_rays(const srt_camera* cam, float* origins, float* dirs, void* stream)
+{
+    if (!cam || !origins || !dirs || cam->width < 1 || cam->height < 1) return SRT_ERR_INVALID_ARG;
+    const int64_t R = (int64_t)cam->width * cam->height;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    k_camera_rays<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(*cam, origins, dirs);
+    SRT_HIP_TRY(hipGetLastError());
+    return SRT_OK;
+}
+
+size_t srt_pathmix_workspace_size(const srt_bvh* b, const srt_camera* cam, int32_t spp)
+{
+    if (!b || !cam || spp < 1 || cam->width < 1 || cam->height < 1) return 0;
+    return pathmix_ws(b, (int64_t)cam->width * cam->height, spp, nullptr).bytes;
+}
+
+srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t ray_id_base,
+                             const srt_trace_opts* opts, const srt_pathmix_opts* pm, float* rgb,
+                             int32_t* cam_gid, float* cam_t, uint8_t* shadow_vis,
+                             int32_t* mirror_gid, uint64_t* counters, void* workspace,
+                             size_t workspace_bytes, void* stream)
+{
+    if (!b || !cam || !pm || !rgb) return SRT_ERR_INVALID_ARG;
+    const srt_status vs = validate_opts(opts);
+    if (vs != SRT_OK) return vs;
+    if (opts->any_hit) return SRT_ERR_INVALID_ARG;
+    if (cam->width < 1 || cam->height < 1) return SRT_ERR_INVALID_ARG;
+    const int64_t R = (int64_t)cam->width * cam->height;
+    if (R * opts->spp > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < srt_pathmix_workspace_size(b, cam, opts->spp))
+        return SRT_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PathmixWs w = pathmix_ws(b, R, opts->spp, workspace);
+    int32_t* cg = cam_gid ? cam_gid : w.cam_gid;
+    float* ct = cam_t ? cam_t : w.cam_t;
+    const int64_t n = R * opts->spp;
+
+    k_camera_rays<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(*cam, w.co, w.cd);
+    SRT_HIP_TRY(hipGetLastError());
+    srt_rays cr{};
+    cr.count = R;
+    cr.origins = w.co;
+    cr.dirs = w.cd;
+    // camera ray ids: base + pixel
+    // (ray_ids null means the index; a nonzero base is added via a table)
+    uint32_t* rid_tab = nullptr;
+    if (ray_id_base != 0) {
+        rid_tab = w.sh.rid;  // scratch: overwritten later by the spawn kernel
+        k_iota<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(rid_tab, ray_id_base, R);
+        SRT_HIP_TRY(hipGetLastError());
+        cr.ray_ids = rid_tab;
+    }
+    cr.purpose = 0;
+    srt_status st = launch_trace(b, &cr, opts, nullptr, cg, ct, counters, w.trace_ws, s);
+    if (st != SRT_OK) return st;
+
+    k_spawn<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(R, opts->spp, ray_id_base, w.co, w.cd, cg,
+                                                        ct, *pm, w.sh, w.mr);
+    SRT_HIP_TRY(hipGetLastError());
+
+    srt_trace_opts so = *opts;
+    so.spp = 1;
+    so.n_per_traversal = 1;
+    so.sample_offset = opts->sample_offset;
+    for (int pass = 0; pass < 2; ++pass) {
+        const SecRays& sr = pass == 0 ? w.sh : w.mr;
+        srt_rays rr{};
+        rr.count = n;
+        rr.origins = sr.o;
+        rr.dirs = sr.d;
+        rr.tmin = sr.tmin;
+        rr.tmax = sr.tmax;
+        rr.ignore_gid = sr.ign;
+        rr.ray_ids = sr.rid;
+        rr.sample_ids = sr.sid;
+        rr.purpose = pass == 0 ? 2u : 3u;
+        so.any_hit = pass == 0 ? 1 : 0;
+        st = launch_trace(b, &rr, &so, nullptr, pass == 0 ? w.sh_hit : w.mr_hit, nullptr, counters,
+                          w.trace_ws, s);
+        if (st != SRT_OK) return st;
+    }
+    k_compose<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(
+        R, opts->spp, b->deg, b->sh, w.cd, cg, w.sh, w.mr, w.sh_hit, w.mr_hit, opts->bg[0],
+        opts->bg[1], opts->bg[2], rgb, shadow_vis, mirror_gid);
+    SRT_HIP_TRY(hipGetLastError());
+    return SRT_OK;
+}
+
+}  // extern "C"

@@ -226,7 +226,7 @@ def camera_rays(cam: Camera):
         d[..., i] = (cam.forward[i] + SX * cam.right[i]) + SY * cam.up[i]
     n = np.sqrt((d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2])
     d = d / n[..., None]
-    o = np.broadcast_to(cam.eye, (H * W, 3)).astype(F32)
+    o = np.ascontiguousarray(np.broadcast_to(cam.eye, (H * W, 3)), dtype=F32)
     return o, np.ascontiguousarray(d.reshape(H * W, 3), dtype=F32)
 
 

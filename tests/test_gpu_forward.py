@@ -1,0 +1,319 @@
+"""GPU parity of the forward path against the FP64 oracle, through the C ABI.
+
+Accepted ids must match the oracle bit for bit on every sample it does not
+flag (|alpha - u| < 1e-6 or a geometric tie); pixel colours within 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import srt_inputs as si
+from _parity import (compare_ids, compare_rgb, device_scene, say, tiny_scene, to_np)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def srt():
+    import paper_2504_06598_amd as srt
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    srt._lib.load()
+    return srt
+
+
+def _cuda(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _trace(srt, bvh, o, d, **kw):
+    res = srt.srt_trace_forward(bvh, _cuda(o), _cuda(d), **kw)
+    torch.cuda.synchronize()
+    return {k: to_np(v) for k, v in res.items()}
+
+
+def _ulps(a, b):
+    a = np.asarray(a, np.float32).view(np.int32).astype(np.int64)
+    b = np.asarray(b, np.float32).view(np.int32).astype(np.int64)
+    return np.abs(a - b)
+
+
+# --------------------------------------------------------------------------
+def test_records_match_oracle(srt):
+    say("records: tiny cube scene, 1000 Gaussians")
+    sc = si.workload(1)["scene"]
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    r = {k: to_np(v) for k, v in bvh.records().items()}
+    ora = oracle.Records(sc)
+    dM = _ulps(r["M"], ora.M.astype(np.float32))
+    dop = _ulps(r["opacity"], ora.op.astype(np.float32))
+    assert dM.max() <= 1 and (dM == 0).mean() > 0.999
+    assert dop.max() <= 1 and (dop == 0).mean() > 0.999
+    assert np.array_equal(r["mu"], sc.means)
+    # each box contains the exact box of its record's k-sigma ellipsoid
+    M = r["M"].astype(np.float64).reshape(-1, 3, 3)
+    Minv = np.linalg.inv(M)
+    h = np.sqrt(8.0 * (Minv ** 2).sum(2))
+    mu = r["mu"].astype(np.float64)
+    assert np.all(r["box_lo"] <= mu - h) and np.all(r["box_hi"] >= mu + h)
+    assert np.all(r["box_hi"] - r["box_lo"] <= 2 * h * (1 + 1e-5) + 1e-6)
+
+
+def _parse_nodes(raw, W):
+    f = raw.view(np.float32)
+    lo = f[:, 0:3 * W].reshape(-1, 3, W)
+    hi = f[:, 3 * W:6 * W].reshape(-1, 3, W)
+    child = raw[:, 6 * W:7 * W]
+    return lo, hi, child
+
+
+@pytest.mark.parametrize("W,L", [(2, 1), (4, 4), (8, 8), (4, 1), (8, 3)])
+def test_bvh_structure(srt, W, L):
+    say(f"bvh structure W={W} L={L}")
+    sc = si.scene_shell(9, 5000, 0)
+    bvh = srt.srt_build_bvh(device_scene(sc), W, L)
+    info = bvh.info()
+    raw, order = bvh.nodes()
+    raw, order = to_np(raw), to_np(order)
+    recs = {k: to_np(v) for k, v in bvh.records().items()}
+    lo, hi, child = _parse_nodes(raw, W)
+    assert sorted(order.tolist()) == list(range(5000))
+    seen = np.zeros(5000, np.int32)
+    stack = [(0, 1)]
+    max_depth = 0
+    visited = 0
+    while stack:
+        n, depth = stack.pop()
+        visited += 1
+        assert visited <= info["num_nodes"], "node reached twice"
+        assert 0 <= n < info["num_nodes"]
+        max_depth = max(max_depth, depth)
+        for c in range(W):
+            ref = int(child[n, c])
+            if ref == 0x7FFFFFFF:
+                assert lo[n, 0, c] > hi[n, 0, c]
+                continue
+            if ref >= 0:
+                # the slot box contains every box of the child node
+                sub = child[ref] != 0x7FFFFFFF
+                assert np.all(lo[n, :, c][:, None] <= lo[ref][:, sub])
+                assert np.all(hi[n, :, c][:, None] >= hi[ref][:, sub])
+                stack.append((ref, depth + 1))
+            else:
+                v = ~ref & 0xFFFFFFFF
+                first, count = v >> 3, (v & 7) + 1
+                assert count <= L
+                for p in range(first, first + count):
+                    seen[p] += 1
+                    g = order[p]
+                    assert np.all(lo[n, :, c] <= recs["box_lo"][g])
+                    assert np.all(hi[n, :, c] >= recs["box_hi"][g])
+    assert np.all(seen == 1), "every Gaussian in exactly one leaf"
+    assert visited == info["num_nodes"]
+    assert max_depth <= info["depth"]
+
+
+def test_camera_rays_bit_exact(srt):
+    cams = [si.look_at((0, 0, 3), (0, 0, 0), 64, 64),
+            si.look_at((0.3, -1.0, 2.5), (0.1, 0, 0), 97, 41, vfov_deg=45.0),
+            *si.ring_cameras(3, 3.0, 33, 17), *si.fibonacci_cameras(4, 3.0, 20, 20)]
+    for cam in cams:
+        say(f"camera rays {cam.width}x{cam.height}")
+        o, d = srt.srt_camera_rays(cam)
+        ho, hd = si.camera_rays(cam)
+        assert np.array_equal(to_np(o).view(np.uint32), ho.view(np.uint32))
+        assert np.array_equal(to_np(d).view(np.uint32), hd.view(np.uint32))
+
+
+def test_forward_parity_tiny_workload(srt):
+    say("forward parity: 1000 Gaussians, 64x64, 1 spp, N=1")
+    w = si.workload(1)
+    sc, cam = w["scene"], w["cameras"][0]
+    o, d = si.camera_rays(cam)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    g = _trace(srt, bvh, o, d, seed=0, spp=1, n_per_traversal=1)
+    ora = oracle.trace(oracle.Records(sc), oracle.Rays(o, d), spp=1, seed=0)
+    nf = compare_ids(g["hit_gid"], ora["hit_gid"], ora["flags"])
+    same = (g["hit_gid"] == ora["hit_gid"]) & (ora["hit_gid"] >= 0)
+    assert same.sum() > 500 and (ora["hit_gid"] < 0).sum() > 500
+    assert _ulps(g["hit_t"][same], ora["hit_t"][same]).max() <= 1
+    err = compare_rgb(g["rgb"], ora["rgb"], ora["flags"])
+    say(f"  flagged {nf}, colour err {err:.2e}")
+
+
+@pytest.mark.parametrize("N,spp", [(1, 8), (2, 8), (4, 8), (8, 8), (4, 6), (8, 3)])
+def test_multisample_matches_oracle(srt, N, spp):
+    say(f"multi-sample N={N} spp={spp}")
+    sc = tiny_scene(11, 1500, (0.02, 0.08), deg=2)
+    cam = si.look_at((0.2, 0.3, 3), (0, 0, 0), 40, 30)
+    o, d = si.camera_rays(cam)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
+    g = _trace(srt, bvh, o, d, seed=123456789012345, spp=spp, n_per_traversal=N,
+               sample_offset=5, bg=(0.1, 0.2, 0.3))
+    ora = oracle.trace(oracle.Records(sc), oracle.Rays(o, d, sample_base=np.full(len(o), 5)),
+                       spp=spp, seed=123456789012345, bg=(0.1, 0.2, 0.3))
+    compare_ids(g["hit_gid"], ora["hit_gid"], ora["flags"])
+    compare_rgb(g["rgb"], ora["rgb"], ora["flags"])
+    if N > 1:
+        g1 = _trace(srt, bvh, o, d, seed=123456789012345, spp=spp, n_per_traversal=1,
+                    sample_offset=5, bg=(0.1, 0.2, 0.3))
+        assert np.array_equal(g1["hit_gid"], g["hit_gid"]), "N per traversal changes results"
+
+
+def test_width_and_leaf_size_invariance(srt):
+    sc = tiny_scene(12, 3000, (0.01, 0.06))
+    cam = si.look_at((0, 0.5, 2.8), (0, 0, 0), 48, 48)
+    o, d = si.camera_rays(cam)
+    ref = None
+    dsc = device_scene(sc)
+    for W in (2, 4, 8):
+        for L in (1, 2, 4, 8):
+            say(f"invariance W={W} L={L}")
+            bvh = srt.srt_build_bvh(dsc, W, L)
+            g = _trace(srt, bvh, o, d, seed=3, spp=4, n_per_traversal=4)
+            if ref is None:
+                ref = g["hit_gid"]
+                ora = oracle.trace(oracle.Records(sc), oracle.Rays(o, d), spp=4, seed=3)
+                compare_ids(ref, ora["hit_gid"], ora["flags"])
+            else:
+                assert np.array_equal(g["hit_gid"], ref), (W, L)
+
+
+def test_deep_stack_fallback_is_exact(srt, tmp_path):
+    say("deep-stack fallback: stack limit 1 and 2")
+    sc = tiny_scene(13, 2000, (0.03, 0.1))
+    cam = si.look_at((0, 0, 3), (0, 0, 0), 32, 32)
+    o, d = si.camera_rays(cam)
+    bvh = srt.srt_build_bvh(device_scene(sc), 2, 1)
+    base = _trace(srt, bvh, o, d, seed=1, spp=2, n_per_traversal=2)
+    for lim in (1, 2):
+        cnt = srt.new_counters()
+        g = _trace(srt, bvh, o, d, seed=1, spp=2, n_per_traversal=2, stack_limit=lim,
+                   counters=cnt)
+        c = srt.counters_dict(cnt)
+        assert c["deep"] > 0
+        assert np.array_equal(g["hit_gid"], base["hit_gid"])
+        np.testing.assert_array_equal(g["rgb"], base["rgb"])
+
+
+def test_coincident_duplicates_tie_by_id(srt):
+    say("coincident duplicates: 300 copies, W=2 L=1")
+    base = tiny_scene(14, 1, (0.2, 0.2))
+    n = 300
+    sc = si.Scene(np.repeat(base.means, n, 0), np.repeat(base.log_scales, n, 0),
+                  np.repeat(base.quats, n, 0), np.full(n, -1.0, np.float32),
+                  np.repeat(base.sh, n, 0), 0)
+    mu = base.means[0]
+    o = np.tile((mu + np.array([0, 0, 3])).astype(np.float32), (64, 1))
+    rng = np.random.default_rng(0)
+    d = np.tile(np.array([0, 0, -1], np.float32), (64, 1))
+    d[:, :2] += rng.normal(0, 0.02, (64, 2)).astype(np.float32)
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    bvh = srt.srt_build_bvh(device_scene(sc), 2, 1)
+    g = _trace(srt, bvh, o, d, seed=2, spp=4, n_per_traversal=4)
+    ora = oracle.trace(oracle.Records(sc), oracle.Rays(o, d), spp=4, seed=2)
+    compare_ids(g["hit_gid"], ora["hit_gid"], ora["flags"])
+    # equal depth keys: the smallest accepted id wins
+    assert (g["hit_gid"] >= 0).mean() > 0.9
+
+
+def test_ray_fields_and_any_hit(srt):
+    say("ray fields: tmin/tmax/ignore/ray ids/sample ids/purpose; any-hit")
+    sc = tiny_scene(15, 2000, (0.02, 0.06), deg=1)
+    rng = np.random.default_rng(5)
+    R = 3000
+    o = rng.uniform(-1.2, 1.2, (R, 3)).astype(np.float32)
+    d = rng.normal(0, 1, (R, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    tmin = rng.uniform(0, 0.3, R).astype(np.float32)
+    tmax = rng.uniform(0.5, 3.0, R).astype(np.float32)
+    tmax[:20] = tmin[:20] * 0.5  # empty ranges
+    ign = rng.integers(-1, 2000, R).astype(np.int32)
+    rid = rng.integers(0, 2 ** 32, R, dtype=np.uint64).astype(np.uint32)
+    sid = rng.integers(0, 1000, R).astype(np.uint32)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    rec = oracle.Records(sc)
+    for purpose, any_hit in [(4, False), (2, True)]:
+        g = _trace(srt, bvh, o, d, tmin=_cuda(tmin), tmax=_cuda(tmax), ignore_gid=_cuda(ign),
+                   ray_ids=_cuda(rid), sample_ids=_cuda(sid), purpose=purpose, seed=77, spp=1,
+                   n_per_traversal=1, any_hit=any_hit)
+        ora = oracle.trace(rec, oracle.Rays(o, d, tmin, tmax, ign, rid, sid), spp=1, seed=77,
+                           purpose=purpose, any_hit=any_hit)
+        if any_hit:
+            occl_g = g["hit_gid"] >= 0
+            occl_o = ora["hit_gid"] >= 0
+            bad = (occl_g != occl_o) & (ora["flags"] == 0)
+            assert not bad.any()
+            assert occl_o.sum() > 50
+            vis = 1.0 - occl_g[:, 0].astype(np.float32)
+            np.testing.assert_array_equal(g["rgb"][:, 0], vis)
+            # whatever id the GPU reports is an accepted valid candidate
+            for i in np.nonzero(occl_g[:, 0])[0][:100]:
+                gid = int(g["hit_gid"][i, 0])
+                ok, t, q, a = oracle.isect_one(rec, gid, o[i], d[i], tmin[i], tmax[i])
+                assert ok and gid != ign[i]
+                assert oracle.accept_u(77, int(rid[i]), int(sid[i]), gid, purpose) < a
+        else:
+            compare_ids(g["hit_gid"], ora["hit_gid"], ora["flags"])
+            compare_rgb(g["rgb"], ora["rgb"], ora["flags"])
+            assert np.all(g["hit_gid"][:20] == -1)
+
+
+def test_edge_cases(srt):
+    say("edge cases: no rays, no Gaussians, one Gaussian, one leaf")
+    sc = tiny_scene(16, 500)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    z = np.zeros((0, 3), np.float32)
+    g = _trace(srt, bvh, z, z, spp=2)
+    assert g["rgb"].shape == (0, 3)
+    cam = si.look_at((0, 0, 3), (0, 0, 0), 16, 16)
+    o, d = si.camera_rays(cam)
+    for n in (0, 1, 3):
+        say(f"  scene of {n} Gaussians")
+        s = sc.subset(np.arange(n))
+        s.log_scales[:] = np.log(0.5)
+        b = srt.srt_build_bvh(device_scene(s), 4, 4)
+        g = _trace(srt, b, o, d, seed=4, spp=3, n_per_traversal=1, bg=(0.25, 0.5, 0.75))
+        if n == 0:
+            assert np.all(g["hit_gid"] == -1)
+            np.testing.assert_allclose(g["rgb"], np.tile([0.25, 0.5, 0.75], (256, 1)))
+        else:
+            ora = oracle.trace(oracle.Records(s), oracle.Rays(o, d), spp=3, seed=4,
+                               bg=(0.25, 0.5, 0.75))
+            compare_ids(g["hit_gid"], ora["hit_gid"], ora["flags"], max_flag_frac=0.01)
+            compare_rgb(g["rgb"], ora["rgb"], ora["flags"])
+
+
+def test_error_codes(srt):
+    sc = tiny_scene(17, 100)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    o = torch.zeros((10, 3), device="cuda")
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_trace_forward(bvh, o, o, n_per_traversal=3)
+    assert e.value.code == 1
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_trace_forward(bvh, o, o, any_hit=True, n_per_traversal=4, spp=4)
+    assert e.value.code == 1
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    lib = srt._lib.load()
+    import ctypes as C
+    rays = srt._lib.SrtRays(10, o.data_ptr(), o.data_ptr(), None, None, None, None, None, 0)
+    opts = srt._opts(0, 1, 1, 0, (0, 0, 0), False, 0)
+    assert lib.srt_trace_forward(bvh.handle, C.byref(rays), C.byref(opts), None, None, None,
+                                 None, ws.data_ptr(), 16, None) == 5
+    with pytest.raises(srt.SrtError):
+        srt.srt_build_bvh(device_scene(sc), 3, 4)
+
+
+def test_counters(srt):
+    sc = tiny_scene(18, 2000)
+    cam = si.look_at((0, 0, 3), (0, 0, 0), 32, 32)
+    o, d = si.camera_rays(cam)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    cnt = srt.new_counters()
+    _trace(srt, bvh, o, d, spp=4, n_per_traversal=2, counters=cnt)
+    c = srt.counters_dict(cnt)
+    assert c["traversals"] == 1024 * 2
+    assert c["ray_samples"] == 1024 * 4
+    assert c["nodes"] >= c["traversals"]
+    assert c["prims"] >= c["candidates"] > 0
+    assert c["philox"] > 0 and c["deep"] == 0 and c["lost"] == 0

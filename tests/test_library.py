@@ -1,0 +1,90 @@
+"""Host-side checks of libsrt that need no GPU: the shared library loads, it
+exports every entry point include/srt.h declares, and argument validation
+returns status codes before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import srt_inputs as si
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "srt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(srt_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2504_06598_amd import _lib
+    return _lib.load()
+
+
+def test_exports_every_declared_entry_point(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2504_06598_amd import _lib
+    assert set(names) == set(_lib.PROTOTYPES), "binding and header disagree"
+
+
+def test_status_strings_and_version(lib):
+    assert lib.srt_status_str(0) == b"SRT_OK"
+    assert lib.srt_status_str(1) == b"SRT_ERR_INVALID_ARG"
+    assert lib.srt_status_str(5) == b"SRT_ERR_WORKSPACE"
+    assert lib.srt_version() >= 10000
+
+
+def test_validation_happens_before_any_device_work(lib):
+    from paper_2504_06598_amd import _lib
+    h = C.c_void_p()
+    sc = _lib.SrtScene(10, 0, None, None, None, None, None)
+    opts = _lib.SrtBuildOpts(4, 4)
+    assert lib.srt_build_bvh(None, C.byref(opts), None, C.byref(h)) == 1
+    assert lib.srt_build_bvh(C.byref(sc), C.byref(opts), None, C.byref(h)) == 1  # null arrays
+    for w, l, deg in [(3, 4, 0), (4, 0, 0), (4, 9, 0), (2, 4, 4), (16, 1, 0)]:
+        sc2 = _lib.SrtScene(0, deg, None, None, None, None, None)
+        assert lib.srt_build_bvh(C.byref(sc2), C.byref(_lib.SrtBuildOpts(w, l)), None,
+                                 C.byref(h)) == 1
+    assert lib.srt_trace_workspace_size(None, 10) == 0
+    assert lib.srt_bvh_get_info(None, None) == 1
+    lib.srt_destroy_bvh(None)
+    cam = _lib.SrtCamera()
+    assert lib.srt_camera_rays(C.byref(cam), None, None, None) == 1
+
+
+def test_camera_generator_geometry():
+    cam = si.look_at((0, 0, 3), (0, 0, 0), 65, 33)
+    o, d = si.camera_rays(cam)
+    assert o.dtype == np.float32 and d.dtype == np.float32
+    n = np.linalg.norm(d.astype(np.float64), axis=1)
+    assert np.all(np.abs(n - 1) < 1e-6)
+    # the centre pixel of an odd-sized image looks straight ahead
+    c = d[16 * 65 + 32]
+    np.testing.assert_allclose(c, [0, 0, -1], atol=1e-7)
+    # row 0 is the top (+y), column 0 is the left (-x)
+    assert d[0, 1] > 0 and d[0, 0] < 0
+    # vertical field of view is 60 degrees (pixel centres just inside)
+    top = d[32]
+    assert abs(np.degrees(np.arctan2(top[1], -top[2])) - 30 * (32.5 / 33) / 1.0) < 0.5
+
+
+def test_workload_recipes():
+    w = si.workload(2, small=True)
+    sc = w["scene"]
+    r = np.linalg.norm(sc.means.astype(np.float64), axis=1)
+    assert abs(r.mean() - 1) < 0.01 and 0.01 < r.std() < 0.03
+    assert sc.sh.shape[1:] == (16, 3)
+    op = 1 / (1 + np.exp(-sc.opacity_logits.astype(np.float64)))
+    assert op.min() >= 0.0099 and op.max() <= 0.9901
+    w5 = si.workload(5, small=True)
+    assert set(w5["spp"]) <= {1, 2, 4, 8, 16, 32, 64}
+    sc3 = si.workload(3, small=True)["scene"]
+    r3 = np.linalg.norm(sc3.means.astype(np.float64), axis=1)
+    assert np.allclose(np.sort(np.unique(np.round(r3, 4))), [0.5, 1.0, 1.5, 2.0])
