@@ -211,6 +211,40 @@ srt_status srt_trace_forward(const srt_bvh* bvh, const srt_rays* rays,
                              size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Backward: gradients of the expected colour (the exact composite of eqn
+ * "accumulated") with respect to the raw parameters. The paper names
+ * differentiable rendering as future work (Sec. 7); the estimator here is,
+ * per sample with result a (colour X, or bg on a miss): every valid candidate
+ * k in front of a receives <g, c_k - X> / (1 - alpha_k) on alpha_k, and a
+ * receives the colour gradient g, each weighted 1/spp; its expectation is the
+ * exact gradient T_k (c_k - B_k) on alpha_k and T_k alpha_k on c_k. Each ray
+ * is re-traversed once per pass of N samples; no hit lists are stored.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace srt_trace_backward needs for `num_rays` rays. */
+size_t srt_backward_workspace_size(const srt_bvh* bvh, int64_t num_rays);
+
+/* scene     the scene the handle was built from (log_scales and quats are read).
+ * rays/opts as for the forward call whose result is being differentiated
+ *           (same seed, spp, sample offset; any_hit must be 0).
+ * grad_rgb  [R,3] device: d loss / d rgb of each ray's pixel value.
+ * hit_gid, hit_t [R,spp] device: the forward's per-sample results; both null
+ *           to recompute them inside the kernel.
+ * g_*       device gradient buffers shaped like the scene arrays; gradients
+ *           are ADDED (+=), so zero them first. g_sh receives the colour
+ *           gradient, the others the opacity gradient chained through
+ *           alpha = o exp(-q/2) at the 1D mean (envelope: dq/dt = 0).
+ * Atomic FP32 accumulation: results are reproducible up to summation order.
+ * Errors: INVALID_ARG (mismatched scene, N not in {1,2,4,8}, any_hit, one of
+ * hit_gid/hit_t null), WORKSPACE, HIP. */
+srt_status srt_trace_backward(const srt_bvh* bvh, const srt_scene* scene, const srt_rays* rays,
+                              const srt_trace_opts* opts, const float* grad_rgb,
+                              const int32_t* hit_gid, const float* hit_t, float* g_means,
+                              float* g_log_scales, float* g_quats, float* g_opacity_logits,
+                              float* g_sh, uint64_t* counters, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Cameras: pinhole rays through pixel centres, row 0 at the top, FP32 with
  * single correctly rounded operations in this order (no contraction):
  *   px = (x + 0.5) / W; sx = ((px * 2) - 1) * tan_half * (W / H)

@@ -14,8 +14,9 @@ import torch
 from . import _lib
 from ._lib import COUNTER_NAMES, SRT_NUM_COUNTERS, SrtError
 
-__all__ = ["DeviceScene", "Bvh", "srt_build_bvh", "srt_trace_forward", "srt_camera_rays",
-           "srt_trace_pathmix", "counters_dict", "new_counters", "COUNTER_NAMES"]
+__all__ = ["DeviceScene", "Bvh", "srt_build_bvh", "srt_trace_forward", "srt_trace_backward",
+           "srt_camera_rays", "srt_trace_pathmix", "TraceFn", "render", "counters_dict",
+           "new_counters", "COUNTER_NAMES"]
 
 
 def _ptr(t):
@@ -167,6 +168,75 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
         bvh.handle, C.byref(rays), C.byref(opts), _ptr(res.get("rgb")), _ptr(res.get("hit_gid")),
         _ptr(res.get("hit_t")), _ptr(counters), _ptr(workspace), need, _stream()))
     return res
+
+
+def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t=None,
+                       tmin=None, tmax=None, ignore_gid=None, ray_ids=None, sample_ids=None,
+                       purpose=0, seed=0, spp=1, n_per_traversal=1, sample_offset=0,
+                       bg=(0.0, 0.0, 0.0), grads=None, counters=None, workspace=None):
+    """Accumulate gradients of sum(grad_rgb * E[rgb]) into `grads` (a dict of
+    tensors shaped like the scene's; zeros are allocated when absent)."""
+    lib = _lib.load()
+    sc = bvh.scene
+    R = int(origins.shape[0])
+    dev = origins.device
+    if grads is None:
+        grads = {k: torch.zeros_like(getattr(sc, k)) for k in
+                 ("means", "log_scales", "quats", "opacity_logits", "sh")}
+    rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
+                        _ptr(ray_ids), _ptr(sample_ids), int(purpose))
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0)
+    need = lib.srt_backward_workspace_size(bvh.handle, R)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    scs = sc.c_struct()
+    _lib.check("srt_trace_backward", lib.srt_trace_backward(
+        bvh.handle, C.byref(scs), C.byref(rays), C.byref(opts), _ptr(grad_rgb), _ptr(hit_gid),
+        _ptr(hit_t), _ptr(grads["means"]), _ptr(grads["log_scales"]), _ptr(grads["quats"]),
+        _ptr(grads["opacity_logits"]), _ptr(grads["sh"]), _ptr(counters), _ptr(workspace), need,
+        _stream()))
+    return grads
+
+
+class TraceFn(torch.autograd.Function):
+    """rgb = E-estimate of the pixel colours of `origins`/`dirs` through the
+    Gaussians (means, log_scales, quats, opacity_logits, sh). The forward
+    builds the BVH from the current parameters and saves each sample's
+    (id, depth); the backward re-traverses and returns the estimator's
+    gradients for the five parameter tensors."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, origins, dirs, cfg):
+        scene = DeviceScene(means.detach().contiguous(), log_scales.detach().contiguous(),
+                            quats.detach().contiguous(), opacity_logits.detach().contiguous(),
+                            sh.detach().contiguous(), cfg["sh_degree"])
+        bvh = srt_build_bvh(scene, cfg.get("width", 4), cfg.get("leaf_size", 4))
+        res = srt_trace_forward(bvh, origins, dirs, seed=cfg.get("seed", 0), spp=cfg["spp"],
+                                n_per_traversal=cfg.get("n_per_traversal", 1),
+                                sample_offset=cfg.get("sample_offset", 0),
+                                bg=cfg.get("bg", (0.0, 0.0, 0.0)))
+        ctx.bvh = bvh
+        ctx.cfg = cfg
+        ctx.save_for_backward(origins, dirs, res["hit_gid"], res["hit_t"])
+        return res["rgb"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        origins, dirs, hit_gid, hit_t = ctx.saved_tensors
+        cfg = ctx.cfg
+        g = srt_trace_backward(ctx.bvh, origins, dirs, grad_rgb.contiguous(), hit_gid=hit_gid,
+                               hit_t=hit_t, seed=cfg.get("seed", 0), spp=cfg["spp"],
+                               n_per_traversal=cfg.get("n_per_traversal", 1),
+                               sample_offset=cfg.get("sample_offset", 0),
+                               bg=cfg.get("bg", (0.0, 0.0, 0.0)))
+        return (g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None, None,
+                None)
+
+
+def render(means, log_scales, quats, opacity_logits, sh, origins, dirs, **cfg):
+    """Differentiable stochastic render (see TraceFn); cfg keys: sh_degree, spp,
+    n_per_traversal, seed, sample_offset, bg, width, leaf_size."""
+    return TraceFn.apply(means, log_scales, quats, opacity_logits, sh, origins, dirs, cfg)
 
 
 def _camera(cam):

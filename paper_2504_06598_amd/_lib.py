@@ -65,6 +65,12 @@ PROTOTYPES = {
     "srt_trace_forward": (C.c_int, [C.c_void_p, C.POINTER(SrtRays), C.POINTER(SrtTraceOpts),
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_size_t, C.c_void_p]),
+    "srt_backward_workspace_size": (C.c_size_t, [C.c_void_p, C.c_int64]),
+    "srt_trace_backward": (C.c_int, [C.c_void_p, C.POINTER(SrtScene), C.POINTER(SrtRays),
+                                     C.POINTER(SrtTraceOpts), C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                     C.c_void_p]),
     "srt_camera_rays": (C.c_int, [C.POINTER(SrtCamera), C.c_void_p, C.c_void_p, C.c_void_p]),
     "srt_pathmix_workspace_size": (C.c_size_t, [C.c_void_p, C.POINTER(SrtCamera), C.c_int32]),
     "srt_trace_pathmix": (C.c_int, [C.c_void_p, C.POINTER(SrtCamera), C.c_uint32,

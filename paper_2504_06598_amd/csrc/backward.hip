@@ -1,0 +1,485 @@
+// Backward pass: gradients of the expected pixel colour.
+//
+// The paper leaves differentiable rendering to future work (Sec. 7) and only
+// notes that a gradient applied to the selected Gaussian alone is easy but
+// not the whole story. The expected colour is the exact composite
+// L = sum_k T_k alpha_k c_k + T_end bg (eqn "accumulated"), whose partials are
+// dL/dalpha_k = T_k (c_k - B_k) (B_k: expected colour behind k) and
+// dL/dc_k = T_k alpha_k. Per sample with result a (colour X = c_a, or bg on a
+// miss), every valid candidate k in front of a was rejected, which happens
+// with probability T_k (1 - alpha_k) and leaves E[X | that] = B_k; so the
+// estimate <g, c_k - X> / (1 - alpha_k) for alpha_k is unbiased, and the
+// result a receives the colour gradient g. Each sample weighs 1/spp
+// (eqn "multisample").
+//
+// Kernel 1 re-traverses every ray with the depth cut at the farthest of the
+// pass's accepted hits (no per-ray hit lists are stored) and evaluates each
+// front candidate in FP64. With alpha = o exp(-q/2), q = |p|^2 and
+// p = M (x* - mu) = S^-1 R^T (x* - mu) at the 1D mean x* (dq/dt* = 0), a
+// candidate's opacity weight s contributes through sa = s * alpha only via
+//   dloss/dlogit = (1 - o) sa,  dloss/dmu = M^T (sa p),
+//   dloss/dlog_s_i = sa p_i^2,  dloss/dR_ji = -(1/s_i) sum_k R_jk s_k sa p_i p_k,
+// so each Gaussian accumulates ten numbers: sum sa, sum sa p, sum sa p p^T.
+// A workgroup walks tiles of 128 neighbouring rays and pre-sums these in an
+// LDS hash table keyed by Gaussian id, flushed to a 64-B global slot per
+// Gaussian with FP32 atomics after each tile (coherent rays share most
+// Gaussians, so this removes most global atomic traffic). SH colour gradients
+// go straight to the caller's buffer. Kernel 2 maps each Gaussian's sums to
+// the raw parameters.
+#include <algorithm>
+#include <climits>
+
+#include "srt_internal.hpp"
+#include "srt_walk.hpp"
+
+using namespace srt;
+
+namespace {
+
+constexpr int kBlock = 128;
+constexpr int kLdsEntries = 32;
+constexpr int kAccStride = 16;  // floats per Gaussian: sa, sa p (3), sa p p^T (6), pad (6)
+constexpr int kAccVals = 10;
+constexpr int kTableSlots = 512;  // LDS hash table entries per workgroup
+constexpr int kProbes = 8;
+
+struct BwdArgs {
+    const void* nodes;
+    const Record* recs;
+    const float* sh;
+    int32_t deg;
+    int64_t R;
+    const float* o;
+    const float* d;
+    const float* tmin;
+    const float* tmax;
+    const int32_t* ign;
+    const uint32_t* rid;
+    const uint32_t* sid;
+    uint32_t purpose, k0, k1;
+    int32_t spp;
+    uint32_t soff;
+    float bg[3];
+    const float* grad_rgb;
+    const int32_t* hit_gid;
+    const float* hit_t;
+    float* acc;
+    float* g_sh;
+    int32_t* glb_stack;
+    int32_t glb_stride;
+    int32_t cap;
+    int64_t max_steps;
+    unsigned long long* counters;
+};
+
+__device__ __forceinline__ void atomic_add_f32(float* p, float v)
+{
+    if (v != 0.0f) atomicAdd(p, v);
+}
+
+struct Table {
+    int32_t* keys;  // [kTableSlots], -1 = empty
+    float* vals;    // [kAccVals][kTableSlots]
+};
+
+// Add one candidate's ten sums to the workgroup table (global atomics when
+// the table has no room within kProbes probes).
+__device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, const float v[kAccVals])
+{
+    uint32_t h = ((uint32_t)gid * 2654435761u) >> (32 - 9);
+    int slot = -1;
+#pragma unroll 1
+    for (int p = 0; p < kProbes; ++p) {
+        const int32_t k = t.keys[h];
+        if (k == gid) {
+            slot = (int)h;
+            break;
+        }
+        if (k == -1) {
+            const int32_t old = atomicCAS(&t.keys[h], -1, gid);
+            if (old == -1 || old == gid) {
+                slot = (int)h;
+                break;
+            }
+        }
+        h = (h + 1) & (kTableSlots - 1);
+    }
+    if (slot >= 0) {
+#pragma unroll
+        for (int c = 0; c < kAccVals; ++c) atomicAdd(&t.vals[c * kTableSlots + slot], v[c]);
+    } else {
+        float* g = acc + (size_t)gid * kAccStride;
+#pragma unroll
+        for (int c = 0; c < kAccVals; ++c) atomic_add_f32(g + c, v[c]);
+    }
+}
+
+template <int W, int N>
+__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
+{
+    __shared__ int32_t lds[kLdsEntries * kBlock];
+    __shared__ int32_t tkeys[kTableSlots];
+    __shared__ float tvals[kAccVals * kTableSlots];
+    Table table{tkeys, tvals};
+    for (int i = threadIdx.x; i < kTableSlots; i += kBlock) {
+        tkeys[i] = -1;
+        for (int c = 0; c < kAccVals; ++c) tvals[c * kTableSlots + i] = 0.0f;
+    }
+    __syncthreads();
+    const int64_t gt = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    TwoTierStack stk{lds + threadIdx.x, kBlock, kLdsEntries, a.glb_stack + gt, a.glb_stride, a.cap};
+    const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
+    const int K = (a.deg + 1) * (a.deg + 1);
+    const float inv_spp = 1.0f / (float)a.spp;
+    uint32_t n_trav = 0, n_nodes = 0, n_prims = 0, n_front = 0, n_samples = 0, n_lost = 0,
+             n_philox = 0, n_fwd_cands = 0;
+    const int64_t n_tiles = (a.R + kBlock - 1) / kBlock;
+
+    // every thread of the workgroup runs the same tiles (the loop bound is
+    // per workgroup), so the barriers below are reached by all of them
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t ray = tile * kBlock + threadIdx.x;
+        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+        float tmin_f = 0.0f, tmax_f = 0.0f;
+        if (ray < a.R) {
+            g0 = a.grad_rgb[3 * ray];
+            g1 = a.grad_rgb[3 * ray + 1];
+            g2 = a.grad_rgb[3 * ray + 2];
+            tmin_f = a.tmin ? a.tmin[ray] : 0.0f;
+            tmax_f = a.tmax ? a.tmax[ray] : INFINITY;
+        }
+        const bool work = ray < a.R && (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f) && tmax_f > tmin_f;
+        if (work) {
+            const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
+            const float dx = a.d[3 * ray], dy = a.d[3 * ray + 1], dz = a.d[3 * ray + 2];
+            const int32_t ign = a.ign ? a.ign[ray] : -1;
+            const uint32_t rid = a.rid ? a.rid[ray] : (uint32_t)ray;
+            const uint32_t sbase = (a.sid ? a.sid[ray] : 0u) + a.soff;
+            const RayF rf = make_rayf(ox, oy, oz, dx, dy, dz, tmin_f);
+            const RayD rd{ox, oy, oz, dx, dy, dz};
+            const double tmin = tmin_f, tmax = tmax_f;
+            float Y[16];
+            {
+                const float n = sqrtf(dx * dx + dy * dy + dz * dz);
+                sh_eval(a.deg, dx / n, dy / n, dz / n, Y);
+            }
+            for (int pass = 0; pass * N < a.spp; ++pass) {
+                const int n_act = min(N, a.spp - pass * N);
+                float ta[N];
+                int32_t ga[N];
+                if (a.hit_gid) {
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        if (k < n_act) {
+                            const int64_t o = ray * a.spp + pass * N + k;
+                            const int32_t g = a.hit_gid[o];
+                            ga[k] = g >= 0 ? g : 0x7FFFFFFF;
+                            ta[k] = g >= 0 ? a.hit_t[o] : INFINITY;
+                        } else {
+                            ga[k] = 0x7FFFFFFF;
+                            ta[k] = -INFINITY;
+                        }
+                    }
+                } else {
+                    const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
+                    uint32_t dummy_nodes = 0, dummy_prims = 0;
+                    const int res = resolve_samples<W, N, false>(
+                        nodes, fc, rf, rd, tmin, tmax, ign, rid, sbase + (uint32_t)(pass * N),
+                        n_act, stk, a.max_steps, ta, ga, dummy_nodes, dummy_prims, n_fwd_cands,
+                        n_philox);
+                    if (res == kWalkOverflow) {
+                        ++n_lost;
+                        continue;
+                    }
+                }
+                // colour of each sample's result (X) and the farthest result key
+                float X[N][3];
+                float wt = -INFINITY;
+                int32_t wg = INT_MIN;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    if (k >= n_act) {
+                        X[k][0] = X[k][1] = X[k][2] = 0.0f;
+                        continue;
+                    }
+                    if (ga[k] != 0x7FFFFFFF) {
+                        const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, ga[k], Y));
+                        X[k][0] = c.x; X[k][1] = c.y; X[k][2] = c.z;
+                    } else {
+                        X[k][0] = a.bg[0]; X[k][1] = a.bg[1]; X[k][2] = a.bg[2];
+                    }
+                    if (key_less(wt, wg, ta[k], ga[k])) {
+                        wt = ta[k];
+                        wg = ga[k];
+                    }
+                }
+                n_samples += (uint32_t)n_act;
+                ++n_trav;
+                float tcut = fminf(cut_after(wt), tmax_f);
+                auto visit = [&](uint32_t ri) -> bool {
+                    const Record r = load_record(a.recs, ri);
+                    double t, q, p[3];
+                    isect_tqp(r, rd, t, q, p);
+                    if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
+                    const float t32 = (float)t;
+                    if (!key_less(t32, r.gid, wt, wg)) return false;
+                    int nf = 0;
+                    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < N; ++k)
+                        if (k < n_act && key_less(t32, r.gid, ta[k], ga[k])) {
+                            ++nf;
+                            x0 += X[k][0];
+                            x1 += X[k][1];
+                            x2 += X[k][2];
+                        }
+                    if (nf == 0) return false;
+                    ++n_front;
+                    const float alpha = (float)((double)r.opacity * exp(-0.5 * q));
+                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, r.gid, Y));
+                    const float fn = (float)nf;
+                    const float s_alpha = (g0 * (fn * c.x - x0) + g1 * (fn * c.y - x1) +
+                                           g2 * (fn * c.z - x2)) * inv_spp / (1.0f - alpha);
+                    const float sa = s_alpha * alpha;
+                    const float p0 = (float)p[0], p1 = (float)p[1], p2 = (float)p[2];
+                    const float v[kAccVals] = {sa,           sa * p0,      sa * p1,
+                                               sa * p2,      sa * p0 * p0, sa * p1 * p1,
+                                               sa * p2 * p2, sa * p0 * p1, sa * p0 * p2,
+                                               sa * p1 * p2};
+                    table_add(table, a.acc, r.gid, v);
+                    return false;
+                };
+                const int res = walk<W>(nodes, rf, tcut, stk, a.max_steps, n_nodes, n_prims, visit);
+                if (res == kWalkOverflow) ++n_lost;
+                // colour gradient of each accepted result, samples sharing a Gaussian merged
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    if (k >= n_act || ga[k] == 0x7FFFFFFF) continue;
+                    bool first = true;
+                    int mult = 0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {
+                        if (j >= n_act || ga[j] != ga[k]) continue;
+                        if (j < k) first = false;
+                        ++mult;
+                    }
+                    if (!first) continue;
+                    const float3 pre = sh_colour_pre(a.sh, a.deg, ga[k], Y);
+                    const float f = (float)mult * inv_spp;
+                    float* gs = a.g_sh + (size_t)ga[k] * (size_t)(3 * K);
+                    for (int j = 0; j < K; ++j) {
+                        if (pre.x > 0.0f) atomic_add_f32(gs + 3 * j + 0, Y[j] * g0 * f);
+                        if (pre.y > 0.0f) atomic_add_f32(gs + 3 * j + 1, Y[j] * g1 * f);
+                        if (pre.z > 0.0f) atomic_add_f32(gs + 3 * j + 2, Y[j] * g2 * f);
+                    }
+                }
+            }
+        }
+        // flush the tile's sums and clear the table
+        __syncthreads();
+        for (int i = threadIdx.x; i < kTableSlots; i += kBlock) {
+            const int32_t gid = tkeys[i];
+            if (gid >= 0) {
+                float* g = a.acc + (size_t)gid * kAccStride;
+                for (int c = 0; c < kAccVals; ++c) {
+                    atomic_add_f32(g + c, tvals[c * kTableSlots + i]);
+                    tvals[c * kTableSlots + i] = 0.0f;
+                }
+                tkeys[i] = -1;
+            }
+        }
+        __syncthreads();
+    }
+    if (a.counters) {
+        wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, n_trav);
+        wave_add_u64(a.counters + SRT_CNT_NODES, n_nodes);
+        wave_add_u64(a.counters + SRT_CNT_PRIMS, n_prims);
+        wave_add_u64(a.counters + SRT_CNT_CANDIDATES, n_front + n_fwd_cands);
+        wave_add_u64(a.counters + SRT_CNT_PHILOX, n_philox);
+        wave_add_u64(a.counters + SRT_CNT_RAY_SAMPLES, n_samples);
+        wave_add_u64(a.counters + SRT_CNT_LOST, n_lost);
+    }
+}
+
+// Per Gaussian: the ten sums -> gradients of the raw parameters, added to the
+// caller's buffers. With A = sum sa, v = sum sa p, P = sum sa p p^T:
+//   dlogit = (1 - o) A,  dmu = M^T v = R S^-1 v,  dlog_s_i = P_ii,
+//   dR_ji = -(1/s_i) sum_k R_jk s_k P_ik, then through R(q / |q|).
+__global__ void k_chain(int64_t G, const float* __restrict__ acc, const float* __restrict__ ls,
+                        const float* __restrict__ quats, const float* __restrict__ logits,
+                        float* g_means, float* g_ls, float* g_quats, float* g_logits)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const float4* p4 = reinterpret_cast<const float4*>(acc + g * kAccStride);
+    const float4 u0 = p4[0], u1 = p4[1], u2 = p4[2];
+    const double A = u0.x;
+    const double v[3] = {u0.y, u0.z, u0.w};
+    const double P[9] = {u1.x, u1.w, u2.x, u1.w, u1.y, u2.y, u2.x, u2.y, u1.z};
+    if (A == 0.0 && v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0 && P[0] == 0.0 && P[4] == 0.0 &&
+        P[8] == 0.0 && P[1] == 0.0 && P[2] == 0.0 && P[5] == 0.0)
+        return;
+    double w = quats[4 * g], x = quats[4 * g + 1], y = quats[4 * g + 2], z = quats[4 * g + 3];
+    const double qn = sqrt(w * w + x * x + y * y + z * z);
+    if (!(qn > 0.0)) return;
+    w /= qn; x /= qn; y /= qn; z /= qn;
+    const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                         2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                         2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+    double s[3];
+    for (int i = 0; i < 3; ++i) s[i] = exp((double)ls[3 * g + i]);
+    const double o = 1.0 / (1.0 + exp(-(double)logits[g]));
+    double GR[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc_ji = 0.0;
+            for (int k = 0; k < 3; ++k) acc_ji += R[3 * j + k] * s[k] * P[3 * i + k];
+            GR[3 * j + i] = -acc_ji / s[i];
+        }
+    // dR/dq of the unit quaternion contracted with GR (row-major R)
+    const double dw = 2.0 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+    const double dx = 2.0 * (y * GR[1] + z * GR[2] + y * GR[3] - 2.0 * x * GR[4] - w * GR[5] +
+                             z * GR[6] + w * GR[7] - 2.0 * x * GR[8]);
+    const double dy = 2.0 * (-2.0 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] -
+                             w * GR[6] + z * GR[7] - 2.0 * y * GR[8]);
+    const double dz = 2.0 * (-2.0 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2.0 * z * GR[4] +
+                             y * GR[5] + x * GR[6] + y * GR[7]);
+    const double dot = dw * w + dx * x + dy * y + dz * z;
+    g_quats[4 * g + 0] += (float)((dw - w * dot) / qn);
+    g_quats[4 * g + 1] += (float)((dx - x * dot) / qn);
+    g_quats[4 * g + 2] += (float)((dy - y * dot) / qn);
+    g_quats[4 * g + 3] += (float)((dz - z * dot) / qn);
+    for (int j = 0; j < 3; ++j) {
+        double mu_j = 0.0;
+        for (int i = 0; i < 3; ++i) mu_j += R[3 * j + i] * v[i] / s[i];
+        g_means[3 * g + j] += (float)mu_j;
+    }
+    for (int i = 0; i < 3; ++i) g_ls[3 * g + i] += (float)P[4 * i];
+    g_logits[g] += (float)((1.0 - o) * A);
+}
+
+using BwdFn = void (*)(BwdArgs);
+
+template <int W>
+BwdFn pick_n(int N)
+{
+    switch (N) {
+    case 1: return k_backward<W, 1>;
+    case 2: return k_backward<W, 2>;
+    case 4: return k_backward<W, 4>;
+    case 8: return k_backward<W, 8>;
+    }
+    return nullptr;
+}
+
+BwdFn pick(int W, int N)
+{
+    switch (W) {
+    case 2: return pick_n<2>(N);
+    case 4: return pick_n<4>(N);
+    case 8: return pick_n<8>(N);
+    }
+    return nullptr;
+}
+
+constexpr int64_t kMaxBwdBlocks = 2048;
+
+struct BwdWs {
+    float* acc;
+    int32_t* stack;
+    int32_t threads;
+    size_t bytes;
+};
+
+BwdWs bwd_ws(const srt_bvh* b, int64_t R, void* base)
+{
+    BwdWs w{};
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((R + kBlock - 1) / kBlock,
+                                                                  kMaxBwdBlocks));
+    w.threads = (int32_t)(blocks * kBlock);
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    w.acc = reinterpret_cast<float*>(p ? p + off : nullptr);
+    off = align_up(off + sizeof(float) * kAccStride * (size_t)std::max<int64_t>(b->G, 1), 256);
+    const int32_t extra = std::max(0, deep_stack_cap(b) - kLdsEntries);
+    w.stack = reinterpret_cast<int32_t*>(p ? p + off : nullptr);
+    off = align_up(off + sizeof(int32_t) * (size_t)w.threads * (size_t)std::max(extra, 1), 256);
+    w.bytes = off;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t srt_backward_workspace_size(const srt_bvh* b, int64_t num_rays)
+{
+    if (!b || num_rays < 0) return 0;
+    return bwd_ws(b, num_rays, nullptr).bytes;
+}
+
+srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const srt_rays* rays,
+                              const srt_trace_opts* opts, const float* grad_rgb,
+                              const int32_t* hit_gid, const float* hit_t, float* g_means,
+                              float* g_log_scales, float* g_quats, float* g_opacity_logits,
+                              float* g_sh, uint64_t* counters, void* workspace,
+                              size_t workspace_bytes, void* stream)
+{
+    if (!b || !rays || !opts || !scene) return SRT_ERR_INVALID_ARG;
+    if (opts->spp < 1 || opts->any_hit) return SRT_ERR_INVALID_ARG;
+    const int N = opts->n_per_traversal;
+    if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
+    if (rays->count < 0 || rays->count > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;
+    if (rays->count > 0 && (!rays->origins || !rays->dirs || !grad_rgb)) return SRT_ERR_INVALID_ARG;
+    if ((hit_gid == nullptr) != (hit_t == nullptr)) return SRT_ERR_INVALID_ARG;
+    if (scene->num_gaussians != b->G || scene->sh_degree != b->deg) return SRT_ERR_INVALID_ARG;
+    if (b->G > 0 && (!g_means || !g_log_scales || !g_quats || !g_opacity_logits || !g_sh ||
+                     !scene->log_scales || !scene->quats || !scene->opacity_logits))
+        return SRT_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < srt_backward_workspace_size(b, rays->count))
+        return SRT_ERR_WORKSPACE;
+    if (b->G == 0 || rays->count == 0) return SRT_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const BwdWs ws = bwd_ws(b, rays->count, workspace);
+    fill_u32(reinterpret_cast<uint32_t*>(ws.acc), 0u, (size_t)kAccStride * (size_t)b->G, s);
+    BwdArgs a{};
+    a.nodes = b->nodes;
+    a.recs = b->recs;
+    a.sh = b->sh;
+    a.deg = b->deg;
+    a.R = rays->count;
+    a.o = rays->origins;
+    a.d = rays->dirs;
+    a.tmin = rays->tmin;
+    a.tmax = rays->tmax;
+    a.ign = rays->ignore_gid;
+    a.rid = rays->ray_ids;
+    a.sid = rays->sample_ids;
+    a.purpose = rays->purpose;
+    a.k0 = (uint32_t)opts->seed;
+    a.k1 = (uint32_t)(opts->seed >> 32);
+    a.spp = opts->spp;
+    a.soff = opts->sample_offset;
+    for (int i = 0; i < 3; ++i) a.bg[i] = opts->bg[i];
+    a.grad_rgb = grad_rgb;
+    a.hit_gid = hit_gid;
+    a.hit_t = hit_t;
+    a.acc = ws.acc;
+    a.g_sh = g_sh;
+    a.glb_stack = ws.stack;
+    a.glb_stride = ws.threads;
+    a.cap = kLdsEntries + std::max(0, deep_stack_cap(b) - kLdsEntries);
+    a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
+    a.counters = reinterpret_cast<unsigned long long*>(counters);
+    BwdFn fn = pick(b->W, N);
+    if (!fn) return SRT_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(fn, dim3(ws.threads / kBlock), dim3(kBlock), 0, s, a);
+    SRT_HIP_TRY(hipGetLastError());
+    k_chain<<<(unsigned)((b->G + 255) / 256), 256, 0, s>>>(
+        b->G, ws.acc, scene->log_scales, scene->quats, scene->opacity_logits, g_means, g_log_scales,
+        g_quats, g_opacity_logits);
+    SRT_HIP_TRY(hipGetLastError());
+    return SRT_OK;
+}
+
+}  // extern "C"

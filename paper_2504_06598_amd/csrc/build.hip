@@ -4,9 +4,10 @@
 // k-sigma ellipsoid (eqn "cuboid") and a BVH is built over the boxes. The
 // paper used Embree / OptiX builders; here the build is a GPU LBVH
 // (63-bit Morton codes of box centres, radix sort, Karras' 2012 parallel
-// binary hierarchy, bottom-up box refit) collapsed top-down into W-wide nodes
-// by greedily opening the child of largest surface area, with subtrees of at
-// most L Gaussians turned into leaves. Records are then stored in leaf order
+// binary hierarchy) collapsed top-down into W-wide nodes by greedily opening
+// the child holding the most Gaussians, with subtrees of at most L Gaussians
+// turned into leaves; wide-node boxes are then filled bottom-up, one level
+// per launch, so no kernel needs cross-workgroup ordering of its writes. Records are then stored in leaf order
 // so a leaf is one contiguous run of 64-B records.
 #include <hipcub/hipcub.hpp>
 
@@ -203,54 +204,6 @@ __global__ void k_karras(int n, const uint64_t* __restrict__ keys, int32_t* __re
     if (i == 0) parent[0] = -1;
 }
 
-__device__ __forceinline__ float load_coherent(const float* p)
-{
-    return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT));
-}
-
-// Bottom-up refit: the second thread to reach a node unions its children.
-__global__ void k_refit(int n, const int32_t* __restrict__ leaf_parent,
-                        const int32_t* __restrict__ parent, const int32_t* __restrict__ left,
-                        const int32_t* __restrict__ right, const uint32_t* __restrict__ order,
-                        const float* __restrict__ lo, const float* __restrict__ hi, float* blo,
-                        float* bhi, uint32_t* flags)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    int node = leaf_parent[k];
-    while (node >= 0) {
-        __threadfence();
-        if (atomicAdd(&flags[node], 1u) == 0u) return;
-        __threadfence();
-        float l[3], h[3];
-        for (int i = 0; i < 3; ++i) {
-            l[i] = INFINITY;
-            h[i] = -INFINITY;
-        }
-        const int32_t ch[2] = {left[node], right[node]};
-        for (int c = 0; c < 2; ++c) {
-            if (ch[c] < 0) {
-                const uint32_t g = order[~ch[c]];
-                for (int i = 0; i < 3; ++i) {
-                    l[i] = fminf(l[i], lo[3 * g + i]);
-                    h[i] = fmaxf(h[i], hi[3 * g + i]);
-                }
-            } else {
-                for (int i = 0; i < 3; ++i) {
-                    l[i] = fminf(l[i], load_coherent(&blo[3 * ch[c] + i]));
-                    h[i] = fmaxf(h[i], load_coherent(&bhi[3 * ch[c] + i]));
-                }
-            }
-        }
-        for (int i = 0; i < 3; ++i) {
-            blo[3 * node + i] = l[i];
-            bhi[3 * node + i] = h[i];
-        }
-        node = parent[node];
-    }
-}
-
 struct Task {
     int32_t bin;
     int32_t node;
@@ -258,103 +211,113 @@ struct Task {
 
 struct BinTree {
     const int32_t *left, *right, *first, *last;
-    const float *blo, *bhi;  // internal boxes
-    const float *lo, *hi;    // Gaussian boxes (id order)
-    const uint32_t* order;   // leaf position -> id
 };
-
-__device__ __forceinline__ void bin_box(const BinTree& t, int32_t c, float l[3], float h[3])
-{
-    if (c < 0) {
-        const uint32_t g = t.order[~c];
-        for (int i = 0; i < 3; ++i) {
-            l[i] = t.lo[3 * g + i];
-            h[i] = t.hi[3 * g + i];
-        }
-    } else {
-        for (int i = 0; i < 3; ++i) {
-            l[i] = t.blo[3 * c + i];
-            h[i] = t.bhi[3 * c + i];
-        }
-    }
-}
 
 __device__ __forceinline__ int32_t bin_size(const BinTree& t, int32_t c)
 {
     return c < 0 ? 1 : t.last[c] - t.first[c] + 1;
 }
 
-// One level of the top-down collapse into W-wide nodes.
+// One level of the top-down collapse into W-wide nodes: starting from the
+// two children of the task's binary node, repeatedly open the child holding
+// the most Gaussians until W children are collected or every child holds at
+// most L (those become leaves). Internal children become the next level's
+// tasks. Boxes are filled in afterwards, bottom-up (k_wide_boxes).
 template <int W>
 __global__ void k_collapse(BinTree t, int L, const Task* __restrict__ in,
                            const uint32_t* __restrict__ n_in, Task* __restrict__ out,
-                           uint32_t* n_out, uint32_t* node_counter, WideNode<W>* nodes)
+                           uint32_t* n_out, uint32_t* node_counter, WideNode<W>* nodes,
+                           int32_t* __restrict__ level_nodes)
 {
     const uint32_t ti = blockIdx.x * blockDim.x + threadIdx.x;
     if (ti >= *n_in) return;
     const Task tk = in[ti];
+    level_nodes[ti] = tk.node;
     int32_t C[W];
-    float area[W];
+    int32_t sz[W];
     int nc = 2;
     C[0] = t.left[tk.bin];
     C[1] = t.right[tk.bin];
-    for (int j = 0; j < 2; ++j) {
-        float l[3], h[3];
-        bin_box(t, C[j], l, h);
-        const float dx = h[0] - l[0], dy = h[1] - l[1], dz = h[2] - l[2];
-        area[j] = (C[j] >= 0 && bin_size(t, C[j]) > L) ? dx * dy + dy * dz + dz * dx : -1.0f;
-    }
+    sz[0] = bin_size(t, C[0]);
+    sz[1] = bin_size(t, C[1]);
     while (nc < W) {
         int best = -1;
-        float ba = -1.0f;
+        int32_t bs = L;
         for (int j = 0; j < nc; ++j)
-            if (area[j] > ba) {
-                ba = area[j];
+            if (sz[j] > bs) {
+                bs = sz[j];
                 best = j;
             }
-        if (best < 0 || ba < 0.0f) break;
+        if (best < 0) break;
         const int32_t c = C[best];
         C[best] = t.left[c];
         C[nc] = t.right[c];
-        for (int r = 0; r < 2; ++r) {
-            const int j = r == 0 ? best : nc;
-            float l[3], h[3];
-            bin_box(t, C[j], l, h);
-            const float dx = h[0] - l[0], dy = h[1] - l[1], dz = h[2] - l[2];
-            area[j] = (C[j] >= 0 && bin_size(t, C[j]) > L) ? dx * dy + dy * dz + dz * dx : -1.0f;
-        }
+        sz[best] = bin_size(t, C[best]);
+        sz[nc] = bin_size(t, C[nc]);
         ++nc;
     }
     WideNode<W> nd;
     for (int s = 0; s < W; ++s) {
+        for (int i = 0; i < 3; ++i) {
+            nd.lo[i][s] = INFINITY;
+            nd.hi[i][s] = -INFINITY;
+        }
+        nd.pad[s] = 0;
         if (s < nc) {
             const int32_t c = C[s];
-            float l[3], h[3];
-            bin_box(t, c, l, h);
-            for (int i = 0; i < 3; ++i) {
-                nd.lo[i][s] = l[i];
-                nd.hi[i][s] = h[i];
-            }
-            const int32_t sz = bin_size(t, c);
             if (c < 0) {
                 nd.child[s] = make_leaf((uint32_t)~c, 1u);
-            } else if (sz <= L) {
-                nd.child[s] = make_leaf((uint32_t)t.first[c], (uint32_t)sz);
+            } else if (sz[s] <= L) {
+                nd.child[s] = make_leaf((uint32_t)t.first[c], (uint32_t)sz[s]);
             } else {
                 const uint32_t idx = atomicAdd(node_counter, 1u);
                 nd.child[s] = (int32_t)idx;
                 out[atomicAdd(n_out, 1u)] = Task{c, (int32_t)idx};
             }
         } else {
-            for (int i = 0; i < 3; ++i) {
-                nd.lo[i][s] = INFINITY;
-                nd.hi[i][s] = -INFINITY;
-            }
             nd.child[s] = kEmptyChild;
         }
-        nd.pad[s] = 0;
     }
     nodes[tk.node] = nd;
+}
+
+// Boxes of the wide nodes of one level, once the level below is complete:
+// a leaf slot bounds its Gaussians' boxes, an internal slot bounds the slot
+// boxes of its child node.
+template <int W>
+__global__ void k_wide_boxes(const int32_t* __restrict__ level_nodes, uint32_t count,
+                             const uint32_t* __restrict__ order, const float* __restrict__ lo,
+                             const float* __restrict__ hi, WideNode<W>* nodes)
+{
+    const uint32_t ti = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ti >= count) return;
+    WideNode<W>& nd = nodes[level_nodes[ti]];
+    for (int s = 0; s < W; ++s) {
+        const int32_t c = nd.child[s];
+        if (c == kEmptyChild) continue;
+        float l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (c < 0) {
+            const uint32_t f = leaf_first(c), n = leaf_count(c);
+            for (uint32_t p = f; p < f + n; ++p) {
+                const uint32_t g = order[p];
+                for (int i = 0; i < 3; ++i) {
+                    l[i] = fminf(l[i], lo[3 * g + i]);
+                    h[i] = fmaxf(h[i], hi[3 * g + i]);
+                }
+            }
+        } else {
+            const WideNode<W>& ch = nodes[c];
+            for (int j = 0; j < W; ++j)
+                for (int i = 0; i < 3; ++i) {
+                    l[i] = fminf(l[i], ch.lo[i][j]);
+                    h[i] = fmaxf(h[i], ch.hi[i][j]);
+                }
+        }
+        for (int i = 0; i < 3; ++i) {
+            nd.lo[i][s] = l[i];
+            nd.hi[i][s] = h[i];
+        }
+    }
 }
 
 // A scene of at most L Gaussians: one root with a single leaf.
@@ -431,35 +394,45 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)std::max<int64_
 
 template <int W>
 srt_status collapse_all(hipStream_t s, DevAlloc& tmp, const BinTree& t, int64_t n, int L,
+                        const uint32_t* order, const float* lo, const float* hi,
                         WideNode<W>* nodes, int64_t* num_nodes, int32_t* depth)
 {
     Task *qa = nullptr, *qb = nullptr;
     uint32_t* ctr = nullptr;  // [0] n_in, [1] n_out, [2] node counter
+    int32_t* level_nodes = nullptr;
     SRT_HIP_TRY(tmp.get(&qa, sizeof(Task) * (size_t)n));
     SRT_HIP_TRY(tmp.get(&qb, sizeof(Task) * (size_t)n));
     SRT_HIP_TRY(tmp.get(&ctr, 4 * sizeof(uint32_t)));
+    SRT_HIP_TRY(tmp.get(&level_nodes, sizeof(int32_t) * (size_t)n));
     const Task root{0, 0};
     const uint32_t init[4] = {1u, 0u, 1u, 0u};
     SRT_HIP_TRY(hipMemcpyAsync(qa, &root, sizeof(Task), hipMemcpyHostToDevice, s));
     SRT_HIP_TRY(hipMemcpyAsync(ctr, init, sizeof(init), hipMemcpyHostToDevice, s));
-    uint32_t n_level = 1;
-    int32_t levels = 0;
+    std::vector<uint32_t> level_off, level_cnt;
+    uint32_t n_level = 1, off = 0;
     while (n_level > 0) {
+        if (level_off.size() > 4096) return SRT_ERR_HIP;  // cannot happen for a valid tree
+        level_off.push_back(off);
+        level_cnt.push_back(n_level);
         k_fill_u32<<<1, 1, 0, s>>>(ctr + 1, 0u, 1);
         k_collapse<W><<<blocks_for(n_level, 128), 128, 0, s>>>(t, L, qa, ctr, qb, ctr + 1, ctr + 2,
-                                                                nodes);
+                                                                nodes, level_nodes + off);
         SRT_HIP_TRY(hipGetLastError());
         SRT_HIP_TRY(hipMemcpyAsync(ctr, ctr + 1, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
         uint32_t host[3];
         SRT_HIP_TRY(hipMemcpyAsync(host, ctr, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         SRT_HIP_TRY(hipStreamSynchronize(s));
+        off += n_level;
         n_level = host[0];
         *num_nodes = host[2];
         std::swap(qa, qb);
-        ++levels;
-        if (levels > 4096) return SRT_ERR_HIP;  // cannot happen for a valid tree
     }
-    *depth = levels;
+    for (size_t lv = level_off.size(); lv-- > 0;) {
+        k_wide_boxes<W><<<blocks_for(level_cnt[lv], 128), 128, 0, s>>>(
+            level_nodes + level_off[lv], level_cnt[lv], order, lo, hi, nodes);
+        SRT_HIP_TRY(hipGetLastError());
+    }
+    *depth = (int32_t)level_off.size();
     return SRT_OK;
 }
 
@@ -530,27 +503,19 @@ srt_status build_impl(const srt_scene* sc, int L, hipStream_t s, srt_bvh* b)
     } else {
         const int n = (int)G;
         int32_t *left, *right, *parent, *leaf_parent, *first, *last;
-        float *blo, *bhi;
-        uint32_t* flags;
         SRT_HIP_TRY(tmp.get(&left, sizeof(int32_t) * (n - 1)));
         SRT_HIP_TRY(tmp.get(&right, sizeof(int32_t) * (n - 1)));
         SRT_HIP_TRY(tmp.get(&parent, sizeof(int32_t) * (n - 1)));
         SRT_HIP_TRY(tmp.get(&first, sizeof(int32_t) * (n - 1)));
         SRT_HIP_TRY(tmp.get(&last, sizeof(int32_t) * (n - 1)));
         SRT_HIP_TRY(tmp.get(&leaf_parent, sizeof(int32_t) * n));
-        SRT_HIP_TRY(tmp.get(&blo, sizeof(float) * 3 * (n - 1)));
-        SRT_HIP_TRY(tmp.get(&bhi, sizeof(float) * 3 * (n - 1)));
-        SRT_HIP_TRY(tmp.get(&flags, sizeof(uint32_t) * (n - 1)));
         k_karras<<<blocks_for(n - 1, 256), 256, 0, s>>>(n, keys_sorted, left, right, parent,
                                                         leaf_parent, first, last);
         SRT_HIP_TRY(hipGetLastError());
-        k_fill_u32<<<blocks_for(n - 1, 256), 256, 0, s>>>(flags, 0u, (size_t)(n - 1));
-        k_refit<<<blocks_for(n, 256), 256, 0, s>>>(n, leaf_parent, parent, left, right, order,
-                                                   b->box_lo, b->box_hi, blo, bhi, flags);
-        SRT_HIP_TRY(hipGetLastError());
         SRT_HIP_TRY(tmp.get(&nodes_max, sizeof(WideNode<W>) * (size_t)(n - 1)));
-        const BinTree t{left, right, first, last, blo, bhi, b->box_lo, b->box_hi, order};
-        const srt_status st = collapse_all<W>(s, tmp, t, n, L, nodes_max, &num_nodes, &depth);
+        const BinTree t{left, right, first, last};
+        const srt_status st = collapse_all<W>(s, tmp, t, n, L, order, b->box_lo, b->box_hi,
+                                              nodes_max, &num_nodes, &depth);
         if (st != SRT_OK) return st;
     }
     WideNode<W>* nodes = nullptr;

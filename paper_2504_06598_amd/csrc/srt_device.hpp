@@ -316,6 +316,29 @@ __device__ __forceinline__ void isect_tq(const Record& r, const RayD& ray, doubl
     q_out = fma(p2, p2, fma(p1, p1, p0 * p0));
 }
 
+// t, q and the whitened position p (the backward's needs).
+__device__ __forceinline__ void isect_tqp(const Record& r, const RayD& ray, double& t_out,
+                                          double& q_out, double p[3])
+{
+    const double wx = ray.ox - (double)r.mu[0];
+    const double wy = ray.oy - (double)r.mu[1];
+    const double wz = ray.oz - (double)r.mu[2];
+    double op[3], dp[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double m0 = r.M[3 * i], m1 = r.M[3 * i + 1], m2 = r.M[3 * i + 2];
+        op[i] = fma(m2, wz, fma(m1, wy, m0 * wx));
+        dp[i] = fma(m2, ray.dz, fma(m1, ray.dy, m0 * ray.dx));
+    }
+    const double dd = fma(dp[2], dp[2], fma(dp[1], dp[1], dp[0] * dp[0]));
+    const double od = fma(op[2], dp[2], fma(op[1], dp[1], op[0] * dp[0]));
+    const double t = -od / dd;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] = fma(t, dp[i], op[i]);
+    t_out = t;
+    q_out = fma(p[2], p[2], fma(p[1], p[1], p[0] * p[0]));
+}
+
 __device__ __forceinline__ Record load_record(const Record* recs, uint32_t i)
 {
     const float4* p = reinterpret_cast<const float4*>(recs + i);

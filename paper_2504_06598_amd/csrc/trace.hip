@@ -15,6 +15,7 @@
 #include <climits>
 
 #include "srt_internal.hpp"
+#include "srt_walk.hpp"
 
 using namespace srt;
 
@@ -62,108 +63,6 @@ struct Counts {
     uint32_t trav = 0, nodes = 0, prims = 0, cands = 0, philox = 0, samples = 0;
 };
 
-// Traverse once for samples s0 .. s0 + n_act - 1 of one ray. Returns false if
-// the stack would overflow (the results are then incomplete).
-template <int W, int N, bool ANY>
-__device__ __forceinline__ bool traverse(const TraceArgs& a, const RayF& rf, const RayD& rd,
-                                         double tmin, double tmax, int32_t ign, uint32_t rid,
-                                         uint32_t s0, int n_act, int32_t* stk, int stride, int cap,
-                                         float (&bt)[N], int32_t (&bgid)[N], Counts& cnt)
-{
-    const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        bt[k] = k < n_act ? INFINITY : -INFINITY;
-        bgid[k] = INT_MAX;
-    }
-    const float tmax_f = (float)tmax;
-    float tcut = tmax_f;
-    float wt = INFINITY;
-    int32_t wg = INT_MAX;
-    int sp = 0;
-    int32_t node = 0;
-    ++cnt.trav;
-    for (int64_t step = 0;; ++step) {
-        if (step > a.max_steps) return false;
-        if (node >= 0) {
-            ++cnt.nodes;
-            NodeBuf<W> b;
-            load_node<W>(nodes, node, b);
-            uint32_t key[W];
-            slab_keys<W>(b, rf, tcut, key);
-            sort_keys<W>(key);
-            int nh = 0;
-#pragma unroll
-            for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
-            if (nh > 0) {
-                if (sp + nh - 1 > cap) return false;
-#pragma unroll
-                for (int c = W - 1; c >= 1; --c)
-                    if (key[c] != 0xFFFFFFFFu) {
-                        stk[sp * stride] = child_at<W>(b, key[c] & 7u);
-                        ++sp;
-                    }
-                node = child_at<W>(b, key[0] & 7u);
-                continue;
-            }
-        } else {
-            const uint32_t first = leaf_first(node), count = leaf_count(node);
-            bool any_accept = false;
-            for (uint32_t i = 0; i < count; ++i) {
-                ++cnt.prims;
-                const Record r = load_record(a.recs, first + i);
-                double t, q;
-                isect_tq(r, rd, t, q);
-                if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) continue;
-                ++cnt.cands;
-                const float t32 = (float)t;
-                if (!key_less(t32, r.gid, wt, wg)) continue;
-                const double alpha = (double)r.opacity * exp(-0.5 * q);
-                uint4 w = make_uint4(0, 0, 0, 0);
-                uint32_t grp = 0xFFFFFFFFu;
-                bool changed = false;
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    if (k < n_act && key_less(t32, r.gid, bt[k], bgid[k])) {
-                        const uint32_t s = s0 + (uint32_t)k;
-                        if ((s >> 2) != grp) {
-                            grp = s >> 2;
-                            w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, a.purpose), a.k0,
-                                              a.k1);
-                            ++cnt.philox;
-                        }
-                        if (u_of_word(word_of(w, s & 3u)) < alpha) {
-                            bt[k] = t32;
-                            bgid[k] = r.gid;
-                            changed = true;
-                        }
-                    }
-                }
-                if (changed) {
-                    if (ANY) {
-                        any_accept = true;
-                        break;
-                    }
-                    wt = -INFINITY;
-                    wg = INT_MIN;
-#pragma unroll
-                    for (int k = 0; k < N; ++k)
-                        if (k < n_act && key_less(wt, wg, bt[k], bgid[k])) {
-                            wt = bt[k];
-                            wg = bgid[k];
-                        }
-                    tcut = fminf(wt + fabsf(wt) * 0x1p-20f + 1e-30f, tmax_f);
-                }
-            }
-            if (ANY && any_accept) return true;
-        }
-        if (sp == 0) break;
-        --sp;
-        node = stk[sp * stride];
-    }
-    return true;
-}
-
 // Trace every pass of one ray, shade and write its outputs. Returns false on
 // a stack overflow (nothing is written then).
 template <int W, int N, bool ANY>
@@ -179,11 +78,11 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
     const uint32_t sbase = (a.sid ? a.sid[ray] : 0u) + a.soff;
     const bool live = tmax_f > tmin_f;
 
-    RayF rf;
-    rf.ox = ox; rf.oy = oy; rf.oz = oz;
-    rf.ix = safe_inv(dx); rf.iy = safe_inv(dy); rf.iz = safe_inv(dz);
-    rf.tmin = tmin_f;
-    RayD rd{ox, oy, oz, dx, dy, dz};
+    const RayF rf = make_rayf(ox, oy, oz, dx, dy, dz, tmin_f);
+    const RayD rd{ox, oy, oz, dx, dy, dz};
+    const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
+    const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
+    FlatStack stack{stk, stride, cap};
 
     const bool shade = a.rgb != nullptr && !ANY;
     float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
@@ -192,10 +91,12 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
         float bt[N];
         int32_t bgid[N];
         if (live) {
-            if (!traverse<W, N, ANY>(a, rf, rd, (double)tmin_f, (double)tmax_f, ign, rid,
-                                     sbase + (uint32_t)(pass * N), n_act, stk, stride, cap, bt,
-                                     bgid, cnt))
-                return false;
+            ++cnt.trav;
+            const int res = resolve_samples<W, N, ANY>(
+                nodes, fc, rf, rd, (double)tmin_f, (double)tmax_f, ign, rid,
+                sbase + (uint32_t)(pass * N), n_act, stack, a.max_steps, bt, bgid, cnt.nodes,
+                cnt.prims, cnt.cands, cnt.philox);
+            if (res == kWalkOverflow) return false;
             cnt.samples += (uint32_t)n_act;
         } else {
 #pragma unroll
