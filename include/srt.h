@@ -300,6 +300,63 @@ srt_status srt_trace_pathmix(const srt_bvh* bvh, const srt_camera* cam, uint32_t
                              int32_t* mirror_gid, uint64_t* counters, void* workspace,
                              size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched forward: many views with uneven samples per pixel plus extra rays
+ * (e.g. incoherent secondary rays) in one graph-captured launch. The
+ * per-sample results equal srt_trace_forward's on the same rays, ray ids and
+ * samples (N samples per traversal, Philox keyed as above).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t num_views;
+    const srt_camera* cameras;  /* host [num_views]; copied at plan creation */
+    const int32_t* spp;         /* host [num_views]: samples per pixel of each view */
+    srt_rays extra;             /* device arrays (count may be 0); ignore_gid and
+                                   sample_ids must be null; ray_ids null means
+                                   ray_id_base + row */
+    int32_t extra_spp;          /* samples per extra ray (>= 1 when extra.count > 0) */
+    uint32_t ray_id_base;       /* camera ray id = ray_id_base + output row */
+} srt_batch;
+
+/* Launch shape. persistent = 1: the work-stealing kernel (a grid of
+ * waves_per_cu one-wave workgroups per compute unit; a wave claims new items
+ * once at least refill_threshold of its 64 lanes are idle); persistent = 0:
+ * the plain kernel, one lane per ray. */
+typedef struct {
+    int32_t persistent;
+    int32_t refill_threshold;  /* 1..64 */
+    int32_t waves_per_cu;      /* >= 1 */
+} srt_tuning;
+
+typedef struct srt_batch_plan srt_batch_plan; /* opaque, library-owned */
+
+/* Output rows: the views' pixels (view by view, y*W + x), then the extra
+ * rays. Per-sample outputs follow the same order, spp entries per row.
+ * Copies the view table to the device and allocates the plan's work counter,
+ * overflow queue and deep stacks; synchronises `stream`. The handle and the
+ * extra-ray arrays must outlive the plan. Errors: INVALID_ARG, OOM, HIP. */
+srt_status srt_batch_plan_create(const srt_bvh* bvh, const srt_batch* batch,
+                                 const srt_trace_opts* opts, const srt_tuning* tuning,
+                                 void* stream, srt_batch_plan** out);
+
+void srt_batch_plan_destroy(srt_batch_plan* plan);
+
+/* rows: output rows; samples: per-sample outputs; items: work items (passes
+ * of N samples for the persistent kernel, rays for the plain one). */
+srt_status srt_batch_plan_info(const srt_batch_plan* plan, int64_t* rows, int64_t* samples,
+                               int64_t* items);
+
+/* Run the plan: rgb [rows,3] device (mean over each row's samples),
+ * hit_gid [samples] device or null, counters as srt_trace_forward. The first
+ * call (and any call with different output pointers) captures the launch
+ * sequence into a HIP graph on a private stream; every call then launches
+ * the graph on `stream`. Calls on one plan must not overlap. */
+srt_status srt_batch_plan_execute(srt_batch_plan* plan, float* rgb, int32_t* hit_gid,
+                                  uint64_t* counters, void* stream);
+
+/* The same launch sequence without the graph (for checking graph replays). */
+srt_status srt_batch_plan_execute_eager(srt_batch_plan* plan, float* rgb, int32_t* hit_gid,
+                                        uint64_t* counters, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

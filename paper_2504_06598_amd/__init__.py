@@ -14,9 +14,9 @@ import torch
 from . import _lib
 from ._lib import COUNTER_NAMES, SRT_NUM_COUNTERS, SrtError
 
-__all__ = ["DeviceScene", "Bvh", "srt_build_bvh", "srt_trace_forward", "srt_trace_backward",
-           "srt_camera_rays", "srt_trace_pathmix", "TraceFn", "render", "counters_dict",
-           "new_counters", "COUNTER_NAMES"]
+__all__ = ["DeviceScene", "Bvh", "BatchPlan", "srt_build_bvh", "srt_trace_forward",
+           "srt_trace_backward", "srt_camera_rays", "srt_trace_pathmix", "srt_batch_plan_create",
+           "TraceFn", "render", "counters_dict", "new_counters", "COUNTER_NAMES"]
 
 
 def _ptr(t):
@@ -295,3 +295,58 @@ def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_trav
         _ptr(res.get("cam_gid")), _ptr(res.get("cam_t")), _ptr(res.get("shadow_vis")),
         _ptr(res.get("mirror_gid")), _ptr(counters), _ptr(workspace), need, _stream()))
     return res
+
+
+class BatchPlan:
+    """Owning wrapper of an srt_batch_plan (see srt_batch_plan_create)."""
+
+    def __init__(self, handle, bvh, keep):
+        self.handle = handle
+        self.bvh = bvh
+        self._keep = keep  # host/device objects the plan refers to
+        rows, samples, items = C.c_int64(), C.c_int64(), C.c_int64()
+        _lib.check("srt_batch_plan_info", _lib.load().srt_batch_plan_info(
+            handle, C.byref(rows), C.byref(samples), C.byref(items)))
+        self.rows, self.samples, self.items = rows.value, samples.value, items.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                torch.cuda.synchronize()
+            except Exception:
+                pass
+            _lib.load().srt_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def execute(self, rgb=None, hit_gid=None, counters=None, eager=False):
+        dev = self.bvh.scene.means.device
+        if rgb is None:
+            rgb = torch.empty((self.rows, 3), dtype=torch.float32, device=dev)
+        lib = _lib.load()
+        fn = lib.srt_batch_plan_execute_eager if eager else lib.srt_batch_plan_execute
+        _lib.check("srt_batch_plan_execute", fn(self.handle, _ptr(rgb), _ptr(hit_gid),
+                                                 _ptr(counters), _stream()))
+        return rgb
+
+
+def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_dirs=None,
+                          extra_tmin=None, extra_tmax=None, extra_ray_ids=None, extra_purpose=4,
+                          extra_spp=1, ray_id_base=0, seed=0, n_per_traversal=4,
+                          sample_offset=0, bg=(0.0, 0.0, 0.0), stack_limit=0, persistent=True,
+                          refill_threshold=16, waves_per_cu=8) -> BatchPlan:
+    lib = _lib.load()
+    nv = len(cameras)
+    cams = (_lib.SrtCamera * max(nv, 1))(*[_camera(c) for c in cameras])
+    spp_arr = (C.c_int32 * max(nv, 1))(*[int(x) for x in spp])
+    n_extra = 0 if extra_origins is None else int(extra_origins.shape[0])
+    extra = _lib.SrtRays(n_extra, _ptr(extra_origins), _ptr(extra_dirs), _ptr(extra_tmin),
+                         _ptr(extra_tmax), None, _ptr(extra_ray_ids), None, int(extra_purpose))
+    batch = _lib.SrtBatch(nv, C.cast(cams, C.c_void_p), C.cast(spp_arr, C.c_void_p), extra,
+                          int(extra_spp) if n_extra else 0, int(ray_id_base))
+    opts = _opts(seed, 1, n_per_traversal, sample_offset, bg, False, stack_limit)
+    tun = _lib.SrtTuning(1 if persistent else 0, int(refill_threshold), int(waves_per_cu))
+    h = C.c_void_p()
+    _lib.check("srt_batch_plan_create", lib.srt_batch_plan_create(
+        bvh.handle, C.byref(batch), C.byref(opts), C.byref(tun), _stream(), C.byref(h)))
+    return BatchPlan(h.value, bvh, (extra_origins, extra_dirs, extra_tmin, extra_tmax,
+                                    extra_ray_ids))

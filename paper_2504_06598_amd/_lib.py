@@ -50,6 +50,16 @@ class SrtPathmixOpts(C.Structure):
     _fields_ = [("light", C.c_float * 3), ("plane_y", C.c_float), ("tmin_secondary", C.c_float)]
 
 
+class SrtBatch(C.Structure):
+    _fields_ = [("num_views", C.c_int32), ("cameras", C.c_void_p), ("spp", C.c_void_p),
+                ("extra", SrtRays), ("extra_spp", C.c_int32), ("ray_id_base", C.c_uint32)]
+
+
+class SrtTuning(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("refill_threshold", C.c_int32),
+                ("waves_per_cu", C.c_int32)]
+
+
 # name -> (restype, argtypes)
 PROTOTYPES = {
     "srt_status_str": (C.c_char_p, [C.c_int]),
@@ -77,6 +87,16 @@ PROTOTYPES = {
                                     C.POINTER(SrtTraceOpts), C.POINTER(SrtPathmixOpts),
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "srt_batch_plan_create": (C.c_int, [C.c_void_p, C.POINTER(SrtBatch), C.POINTER(SrtTraceOpts),
+                                        C.POINTER(SrtTuning), C.c_void_p,
+                                        C.POINTER(C.c_void_p)]),
+    "srt_batch_plan_destroy": (None, [C.c_void_p]),
+    "srt_batch_plan_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]),
+    "srt_batch_plan_execute": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]),
+    "srt_batch_plan_execute_eager": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.c_void_p]),
 }
 
 _lib = None

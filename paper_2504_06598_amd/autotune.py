@@ -1,0 +1,112 @@
+"""Autotuner of the batched forward: BVH width and leaf size (a new BVH per
+pair) and the persistent kernel's refill threshold and waves per CU.
+
+Every candidate's per-sample hit ids must equal the reference launch's bit
+for bit (plain kernel on a W=4, L=4 tree): the accepted set does not depend
+on the tree or the launch shape, so any difference is a bug, and a candidate
+that differs is rejected. The best persistent and the best plain
+configuration (ray-samples per second) are returned and cached as JSON keyed
+by the GPU name and a signature of the workload.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import torch
+
+from . import BatchPlan, DeviceScene, srt_batch_plan_create, srt_build_bvh
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "srt_autotune.json")
+
+
+def _signature(scene: DeviceScene, cameras, spp, n_extra, n_per_traversal):
+    h = hashlib.sha1()
+    h.update(f"{scene.num_gaussians}:{scene.sh_degree}:{n_extra}:{n_per_traversal}".encode())
+    for c, s in zip(cameras, spp):
+        h.update(f"{c.width}x{c.height}@{s}".encode())
+    return h.hexdigest()[:16]
+
+
+def _time_plan(plan: BatchPlan, reps: int, hits=None):
+    rgb = torch.empty((plan.rows, 3), device=plan.bvh.scene.means.device)
+    plan.execute(rgb=rgb, hit_gid=hits)  # captures the graph, warms caches
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        plan.execute(rgb=rgb)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs=None,
+             extra_spp=1, seed=0, n_per_traversal=4, widths=(2, 4, 8), leaves=(1, 2, 4, 8),
+             thresholds=(8, 16, 32, 48), waves=(4, 8, 12), reps=2, cache_path=DEFAULT_CACHE,
+             use_cache=True, log=None):
+    """Sweep and return {"persistent": {...}, "plain": {...}, "table": [...]}."""
+    dev = scene.means.device
+    gpu = torch.cuda.get_device_name(dev)
+    n_extra = 0 if extra_origins is None else int(extra_origins.shape[0])
+    key = f"{gpu}|{_signature(scene, cameras, spp, n_extra, n_per_traversal)}"
+    if use_cache and cache_path and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+            if key in cache:
+                return cache[key]
+        except (OSError, ValueError):
+            pass
+
+    def plan_for(bvh, persistent, thr, wpc):
+        return srt_batch_plan_create(bvh, cameras, spp, extra_origins=extra_origins,
+                                     extra_dirs=extra_dirs, extra_spp=extra_spp, seed=seed,
+                                     n_per_traversal=n_per_traversal, persistent=persistent,
+                                     refill_threshold=thr, waves_per_cu=wpc)
+
+    ref_bvh = srt_build_bvh(scene, 4, 4)
+    ref_plan = plan_for(ref_bvh, False, 16, 8)
+    ref_hits = torch.empty(ref_plan.samples, dtype=torch.int32, device=dev)
+    ref_plan.execute(hit_gid=ref_hits)
+    torch.cuda.synchronize()
+    samples = ref_plan.samples
+    del ref_plan
+    table = []
+    for W in widths:
+        for L in leaves:
+            t0 = time.perf_counter()
+            bvh = srt_build_bvh(scene, W, L)
+            build_ms = (time.perf_counter() - t0) * 1e3
+            shapes = [(False, 16, 8)] + [(True, t, w) for t in thresholds for w in waves]
+            for persistent, thr, wpc in shapes:
+                plan = plan_for(bvh, persistent, thr, wpc)
+                hits = torch.empty(samples, dtype=torch.int32, device=dev)
+                ms = _time_plan(plan, reps, hits)
+                ok = bool(torch.equal(hits, ref_hits))
+                row = {"width": W, "leaf_size": L, "persistent": persistent,
+                       "refill_threshold": thr, "waves_per_cu": wpc, "ms": round(ms, 4),
+                       "mrays_per_s": round(samples / (ms * 1e-3) / 1e6, 2),
+                       "build_ms": round(build_ms, 2), "ids_equal": ok}
+                table.append(row)
+                if log:
+                    log(row)
+                del plan
+            del bvh
+    good = [r for r in table if r["ids_equal"]]
+    best_p = max((r for r in good if r["persistent"]), key=lambda r: r["mrays_per_s"], default=None)
+    best_plain = max((r for r in good if not r["persistent"]), key=lambda r: r["mrays_per_s"],
+                     default=None)
+    result = {"gpu": gpu, "samples": samples, "persistent": best_p, "plain": best_plain,
+              "rejected": sum(1 for r in table if not r["ids_equal"]), "table": table}
+    if cache_path:
+        try:
+            os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+            cache = json.load(open(cache_path)) if os.path.exists(cache_path) else {}
+            cache[key] = result
+            json.dump(cache, open(cache_path, "w"), indent=1)
+        except (OSError, ValueError):
+            pass
+    return result

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsrt.so")
 
-SOURCES = ["build.hip", "trace.hip", "backward.hip"]
+SOURCES = ["build.hip", "trace.hip", "backward.hip", "batched.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=off: the canonical FP32 ray constructions (camera, secondary

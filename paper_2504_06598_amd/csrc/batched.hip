@@ -1,0 +1,838 @@
+// Batched forward: many views with uneven samples per pixel plus extra
+// (incoherent) rays in one launch, captured in a HIP graph.
+//
+// Work is a flat list of items. A camera item is one pass of N samples of one
+// pixel of one view; pixels are enumerated in 8x8 tiles, so the 64 items a
+// wave fetches together are one tile at one pass (maximally coherent rays).
+// An extra-ray item is one pass of one extra ray. Item order: views in
+// order, then the extra rays.
+//
+// Two kernels compute the same per-sample results:
+//  * plain: one lane per ray (pixel or extra ray), looping over its passes;
+//  * persistent: a grid sized to the machine; every wave keeps stepping its
+//    lanes' traversals one node or leaf at a time, and whenever at least
+//    `refill_threshold` of its 64 lanes are idle it claims that many new items
+//    with a single atomic on a global counter (ballot + prefix count hand them
+//    out), so lanes whose rays finish early are refilled instead of idling
+//    until the longest ray of the wave is done. Colour accumulates into the
+//    image with FP32 atomics (each item adds its samples' colours / spp).
+// Both queue items whose on-chip stack overflows; a deep pass with a
+// global-memory stack reruns them (an item contributes only once complete).
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "srt_internal.hpp"
+#include "srt_walk.hpp"
+
+using namespace srt;
+
+namespace {
+
+constexpr int kTile = 8;
+constexpr int kPersistBlock = 64;  // one wave per workgroup
+constexpr int kPlainBlock = 128;
+
+struct Segment {
+    // a camera view (width > 0) or the extra rays (width == 0)
+    srt_camera cam;
+    int64_t item_begin;   // first item of the segment (persistent numbering)
+    int64_t enum_begin;   // first lane of the segment (plain numbering, tile-padded)
+    int64_t ray_begin;    // first output row (pixel or extra ray) in the outputs
+    int64_t sample_begin; // first sample index in the per-sample outputs
+    int32_t width, height, tiles_x;
+    int32_t spp, passes;
+    uint32_t ray_id_base;
+    int64_t rays;         // pixels or extra rays
+};
+
+struct BatchArgs {
+    const void* nodes;
+    const Record* recs;
+    const float* sh;
+    int32_t deg;
+    const Segment* segs;
+    int32_t n_segs;
+    int64_t n_items;      // total items (persistent) or rays (plain)
+    // extra rays
+    const float* eo;
+    const float* ed;
+    const float* etmin;
+    const float* etmax;
+    const uint32_t* erid;
+    uint32_t epurpose;
+    uint32_t k0, k1;
+    uint32_t soff;
+    float bg[3];
+    int32_t stack_cap;
+    float* rgb;           // [rows, 3]: views' pixels, then extra rays
+    int32_t* hit_gid;     // [samples] or null
+    unsigned long long* counters;
+    unsigned long long* work;  // persistent work counter
+    uint32_t* ctrl;       // [0] overflow count, [1] lost
+    uint64_t* ovf_list;   // queued items (persistent) or rays (plain)
+    int32_t* deep_stack;
+    int32_t deep_cap;
+    int32_t threshold;
+    int64_t max_steps;
+    int32_t N;
+};
+
+// Segment of an item (by_item) or plain lane index by binary search.
+__device__ __forceinline__ int find_seg(const BatchArgs& a, int64_t idx, bool by_item)
+{
+    int lo = 0, hi = a.n_segs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t b = by_item ? a.segs[mid].item_begin : a.segs[mid].enum_begin;
+        if (b <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Canonical camera ray (FP32, single rounded operations in a fixed order;
+// this translation unit is compiled without contraction).
+__device__ __forceinline__ void cam_ray(const srt_camera& c, int32_t x, int32_t y, float o[3], float d[3])
+{
+    const float aspect = (float)c.width / (float)c.height;
+    const float px = ((float)x + 0.5f) / (float)c.width;
+    const float sx = ((px * 2.0f) - 1.0f) * c.tan_half * aspect;
+    const float py = ((float)y + 0.5f) / (float)c.height;
+    const float sy = (1.0f - (py * 2.0f)) * c.tan_half;
+    float v[3];
+    for (int i = 0; i < 3; ++i) {
+        const float a = sx * c.right[i];
+        const float b = sy * c.up[i];
+        v[i] = (c.forward[i] + a) + b;
+    }
+    const float xx = v[0] * v[0];
+    const float yy = v[1] * v[1];
+    const float zz = v[2] * v[2];
+    const float n = sqrtf((xx + yy) + zz);
+    for (int i = 0; i < 3; ++i) {
+        d[i] = v[i] / n;
+        o[i] = c.eye[i];
+    }
+}
+
+// A ray of the batch: row (output index), geometry and Philox identity.
+struct BRay {
+    int64_t row;          // output row in rgb
+    int64_t sample0;      // per-sample output index of sample 0 of this ray
+    float o[3], d[3];
+    float tmin, tmax;
+    uint32_t rid, purpose;
+    int32_t spp;
+    bool valid;
+};
+
+// Ray number r (within segment s) of the batch.
+__device__ __forceinline__ BRay seg_ray(const BatchArgs& a, const Segment& S, int64_t r)
+{
+    BRay b;
+    b.spp = S.spp;
+    if (S.width > 0) {
+        // 8x8 tiles, row-major tiles; pixels outside the image are not rays
+        const int64_t tile = r / (kTile * kTile);
+        const int32_t in = (int32_t)(r % (kTile * kTile));
+        const int32_t x = (int32_t)(tile % S.tiles_x) * kTile + (in % kTile);
+        const int32_t y = (int32_t)(tile / S.tiles_x) * kTile + (in / kTile);
+        b.valid = x < S.width && y < S.height;
+        const int64_t pix = (int64_t)y * S.width + x;
+        b.row = S.ray_begin + pix;
+        b.sample0 = S.sample_begin + pix * S.spp;
+        b.rid = S.ray_id_base + (uint32_t)pix;
+        b.purpose = 0;
+        b.tmin = 0.0f;
+        b.tmax = INFINITY;
+        if (b.valid) cam_ray(S.cam, x, y, b.o, b.d);
+    } else {
+        b.valid = r < S.rays;
+        b.row = S.ray_begin + r;
+        b.sample0 = S.sample_begin + r * S.spp;
+        b.rid = a.erid ? a.erid[r] : S.ray_id_base + (uint32_t)r;
+        b.purpose = a.epurpose;
+        b.tmin = a.etmin ? a.etmin[r] : 0.0f;
+        b.tmax = a.etmax ? a.etmax[r] : INFINITY;
+        for (int i = 0; i < 3; ++i) {
+            b.o[i] = a.eo[3 * r + i];
+            b.d[i] = a.ed[3 * r + i];
+        }
+    }
+    return b;
+}
+
+// Rays a segment enumerates (camera views: whole 8x8 tiles).
+__host__ __device__ inline int64_t seg_rays_enumerated(const Segment& S)
+{
+    if (S.width > 0) {
+        const int64_t ty = (S.height + kTile - 1) / kTile;
+        return (int64_t)S.tiles_x * ty * kTile * kTile;
+    }
+    return S.rays;
+}
+
+struct LaneCounts {
+    uint32_t trav = 0, nodes = 0, prims = 0, cands = 0, philox = 0, samples = 0;
+};
+
+// Resolve samples [pass*N, pass*N + n_act) of ray b, shade them and add their
+// colours / spp to the output (atomically when `atomic`). Returns false on a
+// stack overflow (nothing was written).
+template <int W, int N, class Stack>
+__device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int pass, Stack& stk,
+                                         LaneCounts& cnt, bool atomic, float acc[3])
+{
+    const int n_act = min(N, b.spp - pass * N);
+    const RayF rf = make_rayf(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
+    const RayD rd{b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2]};
+    const ForwardCtx fc{a.recs, b.purpose, a.k0, a.k1};
+    float bt[N];
+    int32_t bg[N];
+    ++cnt.trav;
+    const int res = resolve_samples<W, N, false>(
+        static_cast<const WideNode<W>*>(a.nodes), fc, rf, rd, (double)b.tmin, (double)b.tmax, -1,
+        b.rid, a.soff + (uint32_t)(pass * N), n_act, stk, a.max_steps, bt, bg, cnt.nodes, cnt.prims,
+        cnt.cands, cnt.philox);
+    if (res == kWalkOverflow) return false;
+    cnt.samples += (uint32_t)n_act;
+    float Y[16];
+    const float n = sqrtf(b.d[0] * b.d[0] + b.d[1] * b.d[1] + b.d[2] * b.d[2]);
+    sh_eval(a.deg, b.d[0] / n, b.d[1] / n, b.d[2] / n, Y);
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if (k >= n_act) continue;
+        const bool hit = bg[k] != 0x7FFFFFFF;
+        if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? bg[k] : -1;
+        if (hit) {
+            const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, bg[k], Y));
+            c0 += c.x; c1 += c.y; c2 += c.z;
+        } else {
+            c0 += a.bg[0]; c1 += a.bg[1]; c2 += a.bg[2];
+        }
+    }
+    const float w = 1.0f / (float)b.spp;
+    if (atomic) {
+        atomicAdd(a.rgb + 3 * b.row, c0 * w);
+        atomicAdd(a.rgb + 3 * b.row + 1, c1 * w);
+        atomicAdd(a.rgb + 3 * b.row + 2, c2 * w);
+    } else {
+        acc[0] += c0; acc[1] += c1; acc[2] += c2;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void flush_counts(const BatchArgs& a, const LaneCounts& c, uint32_t deep,
+                                             uint32_t lost)
+{
+    if (!a.counters) return;
+    wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, c.trav);
+    wave_add_u64(a.counters + SRT_CNT_NODES, c.nodes);
+    wave_add_u64(a.counters + SRT_CNT_PRIMS, c.prims);
+    wave_add_u64(a.counters + SRT_CNT_CANDIDATES, c.cands);
+    wave_add_u64(a.counters + SRT_CNT_PHILOX, c.philox);
+    wave_add_u64(a.counters + SRT_CNT_DEEP, deep);
+    wave_add_u64(a.counters + SRT_CNT_RAY_SAMPLES, c.samples);
+    wave_add_u64(a.counters + SRT_CNT_LOST, lost);
+}
+
+// ---------------------------------------------------------------------------
+// Plain: one lane per ray.
+// ---------------------------------------------------------------------------
+template <int W, int N>
+__global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
+{
+    __shared__ int32_t lds[32 * kPlainBlock];
+    const int64_t r = blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
+    FlatStack stk{lds + threadIdx.x, kPlainBlock, min(32, a.stack_cap)};
+    LaneCounts cnt;
+    if (r < a.n_items) {
+        const Segment& S = a.segs[find_seg(a, r, false)];
+        const BRay b = seg_ray(a, S, r - S.enum_begin);
+        if (b.valid) {
+            float acc[3] = {0.0f, 0.0f, 0.0f};
+            bool ok = true;
+            for (int pass = 0; pass * N < b.spp && ok; ++pass)
+                ok = run_pass<W, N>(a, b, pass, stk, cnt, false, acc);
+            if (ok) {
+                const float w = 1.0f / (float)b.spp;
+                a.rgb[3 * b.row] = acc[0] * w;
+                a.rgb[3 * b.row + 1] = acc[1] * w;
+                a.rgb[3 * b.row + 2] = acc[2] * w;
+            } else {
+                const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+                a.ovf_list[slot] = (uint64_t)r;
+            }
+        }
+    }
+    flush_counts(a, cnt, 0, 0);
+}
+
+// Plain deep pass: queued rays with the global-memory stack.
+template <int W, int N>
+__global__ __launch_bounds__(kPlainBlock) void k_plain_deep(BatchArgs a)
+{
+    const int64_t gt = blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
+    FlatStack stk{a.deep_stack + gt, kDeepThreads, a.deep_cap};
+    LaneCounts cnt;
+    uint32_t deep = 0, lost = 0;
+    const int64_t n = a.ctrl[0];
+    for (int64_t it = gt; it < n; it += (int64_t)gridDim.x * kPlainBlock) {
+        const int64_t r = (int64_t)a.ovf_list[it];
+        const Segment& S = a.segs[find_seg(a, r, false)];
+        const BRay b = seg_ray(a, S, r - S.enum_begin);
+        float acc[3] = {0.0f, 0.0f, 0.0f};
+        bool ok = true;
+        ++deep;
+        for (int pass = 0; pass * N < b.spp && ok; ++pass)
+            ok = run_pass<W, N>(a, b, pass, stk, cnt, false, acc);
+        if (!ok) {
+            ++lost;
+            atomicAdd(&a.ctrl[1], 1u);
+            continue;
+        }
+        const float w = 1.0f / (float)b.spp;
+        a.rgb[3 * b.row] = acc[0] * w;
+        a.rgb[3 * b.row + 1] = acc[1] * w;
+        a.rgb[3 * b.row + 2] = acc[2] * w;
+    }
+    flush_counts(a, cnt, deep, lost);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent work stealing.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void decode_item(const BatchArgs& a, int64_t item, int32_t& seg,
+                                            int64_t& ray, int32_t& pass)
+{
+    seg = find_seg(a, item, true);
+    const Segment& S = a.segs[seg];
+    const int64_t local = item - S.item_begin;
+    if (S.width > 0) {
+        // tile-major: each tile runs its passes back to back, 64 items per pass
+        const int64_t per_tile = (int64_t)S.passes * kTile * kTile;
+        const int64_t tile = local / per_tile;
+        const int64_t rem = local % per_tile;
+        pass = (int32_t)(rem / (kTile * kTile));
+        ray = tile * kTile * kTile + rem % (kTile * kTile);
+    } else {
+        ray = local / S.passes;
+        pass = (int32_t)(local % S.passes);
+    }
+}
+
+template <int W, int N>
+__global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
+{
+    __shared__ int32_t lds[32 * kPersistBlock];
+    const int lane = threadIdx.x;
+    const int cap = min(32, a.stack_cap);
+    const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
+    LaneCounts cnt;
+
+    // lane state
+    bool active = false;
+    BRay b;
+    b.valid = false;
+    int32_t pass = 0, n_act = 0;
+    int64_t item_id = 0;
+    RayF rf;
+    RayD rd;
+    float bt[N];
+    int32_t bg[N];
+    float tcut = 0.0f, wt = 0.0f, tmax_f = 0.0f;
+    int32_t wg = 0;
+    int32_t node = 0;
+    int sp = 0;
+    int64_t steps = 0;
+    bool exhausted = false;
+
+    for (;;) {
+        // ---- refill idle lanes (wave-uniform decision) ----
+        const unsigned long long idle = __ballot(!active);
+        const int n_idle = __popcll(idle);
+        if (n_idle == 64 && exhausted) break;
+        if (!exhausted && (n_idle >= a.threshold || n_idle == 64)) {
+            const int leader = __ffsll((long long)idle) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(a.work, (unsigned long long)n_idle);
+            base = __shfl(base, leader, 64);
+            if (base + (unsigned long long)n_idle >= (unsigned long long)a.n_items) exhausted = true;
+            if (!active) {
+                const unsigned long long below = idle & ((1ull << lane) - 1ull);
+                const int64_t it = (int64_t)(base + (unsigned long long)__popcll(below));
+                if (it < a.n_items) {
+                    int32_t seg;
+                    int64_t ray;
+                    decode_item(a, it, seg, ray, pass);
+                    const Segment& S = a.segs[seg];
+                    b = seg_ray(a, S, ray);
+                    if (b.valid) {
+                        item_id = it;
+                        n_act = min(N, b.spp - pass * N);
+                        rf = make_rayf(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
+                        rd = RayD{b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2]};
+#pragma unroll
+                        for (int k = 0; k < N; ++k) {
+                            bt[k] = k < n_act ? INFINITY : -INFINITY;
+                            bg[k] = 0x7FFFFFFF;
+                        }
+                        tmax_f = b.tmax;
+                        tcut = tmax_f;
+                        wt = INFINITY;
+                        wg = 0x7FFFFFFF;
+                        node = 0;
+                        sp = 0;
+                        steps = 0;
+                        active = true;
+                        ++cnt.trav;
+                    }
+                }
+            }
+        }
+        if (!active) continue;
+
+        // ---- one traversal step: one node or one leaf ----
+        bool done = false, overflow = false;
+        if (++steps > a.max_steps) {
+            overflow = true;
+        } else if (node >= 0) {
+            ++cnt.nodes;
+            NodeBuf<W> nb;
+            load_node<W>(nodes, node, nb);
+            uint32_t key[W];
+            slab_keys<W>(nb, rf, tcut, key);
+            sort_keys<W>(key);
+            int nh = 0;
+#pragma unroll
+            for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
+            if (nh > 0) {
+                if (sp + nh - 1 > cap) {
+                    overflow = true;
+                } else {
+#pragma unroll
+                    for (int c = W - 1; c >= 1; --c)
+                        if (key[c] != 0xFFFFFFFFu) {
+                            lds[sp * kPersistBlock + lane] = child_at<W>(nb, key[c] & 7u);
+                            ++sp;
+                        }
+                    node = child_at<W>(nb, key[0] & 7u);
+                }
+            } else if (sp == 0) {
+                done = true;
+            } else {
+                --sp;
+                node = lds[sp * kPersistBlock + lane];
+            }
+        } else {
+            const uint32_t first = leaf_first(node), count = leaf_count(node);
+            const double tmin_d = b.tmin, tmax_d = b.tmax;
+            for (uint32_t i = 0; i < count; ++i) {
+                ++cnt.prims;
+                const Record r = load_record(a.recs, first + i);
+                double t, q;
+                isect_tq(r, rd, t, q);
+                if (!(q <= kEllipsoidQ && t > tmin_d && t < tmax_d)) continue;
+                ++cnt.cands;
+                const float t32 = (float)t;
+                if (!key_less(t32, r.gid, wt, wg)) continue;
+                const double alpha = (double)r.opacity * exp(-0.5 * q);
+                uint4 w = make_uint4(0, 0, 0, 0);
+                uint32_t grp = 0xFFFFFFFFu;
+                bool changed = false;
+                const uint32_t s0 = a.soff + (uint32_t)(pass * N);
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    if (k < n_act && key_less(t32, r.gid, bt[k], bg[k])) {
+                        const uint32_t s = s0 + (uint32_t)k;
+                        if ((s >> 2) != grp) {
+                            grp = s >> 2;
+                            w = philox4x32_10(make_uint4(b.rid, grp, (uint32_t)r.gid, b.purpose),
+                                              a.k0, a.k1);
+                            ++cnt.philox;
+                        }
+                        if (u_of_word(word_of(w, s & 3u)) < alpha) {
+                            bt[k] = t32;
+                            bg[k] = r.gid;
+                            changed = true;
+                        }
+                    }
+                }
+                if (changed) {
+                    wt = -INFINITY;
+                    wg = (int32_t)0x80000000;
+#pragma unroll
+                    for (int k = 0; k < N; ++k)
+                        if (k < n_act && key_less(wt, wg, bt[k], bg[k])) {
+                            wt = bt[k];
+                            wg = bg[k];
+                        }
+                    tcut = fminf(cut_after(wt), tmax_f);
+                }
+            }
+            if (sp == 0) {
+                done = true;
+            } else {
+                --sp;
+                node = lds[sp * kPersistBlock + lane];
+            }
+        }
+        if (overflow) {
+            const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+            a.ovf_list[slot] = (uint64_t)item_id;
+            active = false;
+        } else if (done) {
+            // shade and accumulate this item's samples
+            cnt.samples += (uint32_t)n_act;
+            float Y[16];
+            const float nn = sqrtf(b.d[0] * b.d[0] + b.d[1] * b.d[1] + b.d[2] * b.d[2]);
+            sh_eval(a.deg, b.d[0] / nn, b.d[1] / nn, b.d[2] / nn, Y);
+            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                if (k >= n_act) continue;
+                const bool hit = bg[k] != 0x7FFFFFFF;
+                if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? bg[k] : -1;
+                if (hit) {
+                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, bg[k], Y));
+                    c0 += c.x; c1 += c.y; c2 += c.z;
+                } else {
+                    c0 += a.bg[0]; c1 += a.bg[1]; c2 += a.bg[2];
+                }
+            }
+            const float wgt = 1.0f / (float)b.spp;
+            atomicAdd(a.rgb + 3 * b.row, c0 * wgt);
+            atomicAdd(a.rgb + 3 * b.row + 1, c1 * wgt);
+            atomicAdd(a.rgb + 3 * b.row + 2, c2 * wgt);
+            active = false;
+        }
+    }
+    flush_counts(a, cnt, 0, 0);
+}
+
+// Persistent deep pass: queued items with the global-memory stack.
+template <int W, int N>
+__global__ __launch_bounds__(kPlainBlock) void k_persistent_deep(BatchArgs a)
+{
+    const int64_t gt = blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
+    FlatStack stk{a.deep_stack + gt, kDeepThreads, a.deep_cap};
+    LaneCounts cnt;
+    uint32_t deep = 0, lost = 0;
+    const int64_t n = a.ctrl[0];
+    for (int64_t it = gt; it < n; it += (int64_t)gridDim.x * kPlainBlock) {
+        int32_t seg, pass;
+        int64_t ray;
+        decode_item(a, (int64_t)a.ovf_list[it], seg, ray, pass);
+        const BRay b = seg_ray(a, a.segs[seg], ray);
+        ++deep;
+        if (!run_pass<W, N>(a, b, pass, stk, cnt, true, nullptr)) {
+            ++lost;
+            atomicAdd(&a.ctrl[1], 1u);
+        }
+    }
+    flush_counts(a, cnt, deep, lost);
+}
+
+__global__ void k_zero_f32(float* p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+__global__ void k_reset(unsigned long long* work, uint32_t* ctrl)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *work = 0ull;
+        ctrl[0] = 0u;
+        ctrl[1] = 0u;
+    }
+}
+
+using BatchFn = void (*)(BatchArgs);
+
+template <int W>
+bool pick_w(int N, BatchFn k[4])
+{
+    switch (N) {
+    case 1: k[0] = k_plain<W, 1>; k[1] = k_plain_deep<W, 1>; k[2] = k_persistent<W, 1>; k[3] = k_persistent_deep<W, 1>; return true;
+    case 2: k[0] = k_plain<W, 2>; k[1] = k_plain_deep<W, 2>; k[2] = k_persistent<W, 2>; k[3] = k_persistent_deep<W, 2>; return true;
+    case 4: k[0] = k_plain<W, 4>; k[1] = k_plain_deep<W, 4>; k[2] = k_persistent<W, 4>; k[3] = k_persistent_deep<W, 4>; return true;
+    case 8: k[0] = k_plain<W, 8>; k[1] = k_plain_deep<W, 8>; k[2] = k_persistent<W, 8>; k[3] = k_persistent_deep<W, 8>; return true;
+    }
+    return false;
+}
+
+bool pick(int W, int N, BatchFn k[4])
+{
+    switch (W) {
+    case 2: return pick_w<2>(N, k);
+    case 4: return pick_w<4>(N, k);
+    case 8: return pick_w<8>(N, k);
+    }
+    return false;
+}
+
+}  // namespace
+
+struct srt_batch_plan {
+    const srt_bvh* bvh = nullptr;
+    srt_trace_opts opts{};
+    srt_tuning tuning{};
+    std::vector<Segment> segs;
+    Segment* d_segs = nullptr;
+    int64_t n_items = 0, n_rays = 0, n_samples = 0, rows = 0;
+    srt_rays extra{};
+    unsigned long long* work = nullptr;
+    uint32_t* ctrl = nullptr;
+    uint64_t* ovf = nullptr;
+    int32_t* deep_stack = nullptr;
+    int64_t ovf_cap = 0;
+    int32_t n_cu = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float* g_rgb = nullptr;
+    int32_t* g_hits = nullptr;
+    uint64_t* g_counters = nullptr;
+};
+
+namespace {
+
+void plan_free(srt_batch_plan* p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    (void)hipFree(p->d_segs);
+    (void)hipFree(p->work);
+    (void)hipFree(p->ctrl);
+    (void)hipFree(p->ovf);
+    (void)hipFree(p->deep_stack);
+    delete p;
+}
+
+srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* counters, hipStream_t s)
+{
+    const srt_bvh* b = p->bvh;
+    BatchFn k[4];
+    if (!pick(b->W, p->opts.n_per_traversal, k)) return SRT_ERR_UNSUPPORTED;
+    BatchArgs a{};
+    a.nodes = b->nodes;
+    a.recs = b->recs;
+    a.sh = b->sh;
+    a.deg = b->deg;
+    a.segs = p->d_segs;
+    a.n_segs = (int32_t)p->segs.size();
+    a.eo = p->extra.origins;
+    a.ed = p->extra.dirs;
+    a.etmin = p->extra.tmin;
+    a.etmax = p->extra.tmax;
+    a.erid = p->extra.ray_ids;
+    a.epurpose = p->extra.purpose;
+    a.k0 = (uint32_t)p->opts.seed;
+    a.k1 = (uint32_t)(p->opts.seed >> 32);
+    a.soff = p->opts.sample_offset;
+    for (int i = 0; i < 3; ++i) a.bg[i] = p->opts.bg[i];
+    a.stack_cap = p->opts.stack_limit > 0 ? p->opts.stack_limit : INT_MAX;
+    a.rgb = rgb;
+    a.hit_gid = hits;
+    a.counters = reinterpret_cast<unsigned long long*>(counters);
+    a.work = p->work;
+    a.ctrl = p->ctrl;
+    a.ovf_list = p->ovf;
+    a.deep_stack = p->deep_stack;
+    a.deep_cap = deep_stack_cap(b);
+    a.threshold = std::max(1, std::min(64, p->tuning.refill_threshold));
+    a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
+    a.N = p->opts.n_per_traversal;
+    k_reset<<<1, 64, 0, s>>>(p->work, p->ctrl);
+    SRT_HIP_TRY(hipGetLastError());
+    const bool persistent = p->tuning.persistent != 0;
+    if (persistent) {
+        k_zero_f32<<<1024, 256, 0, s>>>(rgb, 3 * p->rows);
+        SRT_HIP_TRY(hipGetLastError());
+        a.n_items = p->n_items;
+        const int wpc = std::max(1, p->tuning.waves_per_cu);
+        hipLaunchKernelGGL(k[2], dim3((unsigned)(p->n_cu * wpc)), dim3(kPersistBlock), 0, s, a);
+        SRT_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k[3], dim3(kDeepThreads / kPlainBlock), dim3(kPlainBlock), 0, s, a);
+        SRT_HIP_TRY(hipGetLastError());
+    } else {
+        a.n_items = p->n_rays;
+        if (p->n_rays > 0) {
+            hipLaunchKernelGGL(k[0], dim3((unsigned)((p->n_rays + kPlainBlock - 1) / kPlainBlock)),
+                               dim3(kPlainBlock), 0, s, a);
+            SRT_HIP_TRY(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k[1], dim3(kDeepThreads / kPlainBlock), dim3(kPlainBlock), 0, s, a);
+        SRT_HIP_TRY(hipGetLastError());
+    }
+    return SRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
+                                 const srt_trace_opts* opts, const srt_tuning* tuning, void* stream,
+                                 srt_batch_plan** out)
+{
+    if (!b || !batch || !opts || !tuning || !out) return SRT_ERR_INVALID_ARG;
+    *out = nullptr;
+    const int N = opts->n_per_traversal;
+    if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
+    if (opts->any_hit || opts->stack_limit < 0) return SRT_ERR_INVALID_ARG;
+    if (batch->num_views < 0 || (batch->num_views > 0 && (!batch->cameras || !batch->spp)))
+        return SRT_ERR_INVALID_ARG;
+    if (batch->extra.count < 0 || batch->extra_spp < 0) return SRT_ERR_INVALID_ARG;
+    if (batch->extra.count > 0 &&
+        (!batch->extra.origins || !batch->extra.dirs || batch->extra_spp < 1))
+        return SRT_ERR_INVALID_ARG;
+    if (tuning->refill_threshold < 1 || tuning->refill_threshold > 64 || tuning->waves_per_cu < 1)
+        return SRT_ERR_INVALID_ARG;
+    srt_batch_plan* p = new srt_batch_plan();
+    p->bvh = b;
+    p->opts = *opts;
+    p->tuning = *tuning;
+    p->extra = batch->extra;
+    int64_t items = 0, rows = 0, samples = 0, rays = 0;
+    for (int v = 0; v < batch->num_views; ++v) {
+        const srt_camera& c = batch->cameras[v];
+        const int32_t spp = batch->spp[v];
+        if (c.width < 1 || c.height < 1 || spp < 1) {
+            plan_free(p);
+            return SRT_ERR_INVALID_ARG;
+        }
+        Segment S{};
+        S.cam = c;
+        S.width = c.width;
+        S.height = c.height;
+        S.tiles_x = (c.width + kTile - 1) / kTile;
+        S.spp = spp;
+        S.passes = (spp + N - 1) / N;
+        S.rays = (int64_t)c.width * c.height;
+        S.item_begin = items;
+        S.enum_begin = rays;
+        S.ray_begin = rows;
+        S.sample_begin = samples;
+        S.ray_id_base = batch->ray_id_base + (uint32_t)rows;
+        const int64_t en = seg_rays_enumerated(S);
+        items += en * S.passes;
+        rows += S.rays;
+        samples += S.rays * spp;
+        rays += en;
+        p->segs.push_back(S);
+    }
+    if (batch->extra.count > 0) {
+        Segment S{};
+        S.width = 0;
+        S.spp = batch->extra_spp;
+        S.passes = (batch->extra_spp + N - 1) / N;
+        S.rays = batch->extra.count;
+        S.item_begin = items;
+        S.enum_begin = rays;
+        S.ray_begin = rows;
+        S.sample_begin = samples;
+        S.ray_id_base = batch->ray_id_base + (uint32_t)rows;
+        items += S.rays * S.passes;
+        rows += S.rays;
+        samples += S.rays * S.spp;
+        rays += S.rays;
+        p->segs.push_back(S);
+    }
+    p->n_items = items;
+    p->rows = rows;
+    p->n_samples = samples;
+    p->n_rays = rays;
+    srt_status st = SRT_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        plan_free(p);
+        return SRT_ERR_HIP;
+    }
+    p->n_cu = prop.multiProcessorCount;
+    p->ovf_cap = std::max<int64_t>(items, rays) + 1;
+    if (hipMalloc(&p->d_segs, sizeof(Segment) * std::max<size_t>(1, p->segs.size())) != hipSuccess ||
+        hipMalloc(&p->work, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&p->ctrl, 4 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&p->ovf, sizeof(uint64_t) * (size_t)p->ovf_cap) != hipSuccess ||
+        hipMalloc(&p->deep_stack, sizeof(int32_t) * (size_t)kDeepThreads * (size_t)deep_stack_cap(b)) !=
+            hipSuccess) {
+        plan_free(p);
+        return SRT_ERR_OOM;
+    }
+    if (!p->segs.empty() &&
+        hipMemcpyAsync(p->d_segs, p->segs.data(), sizeof(Segment) * p->segs.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        st = SRT_ERR_HIP;
+    if (st == SRT_OK && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        st = SRT_ERR_HIP;
+    if (st == SRT_OK && hipStreamSynchronize(s) != hipSuccess) st = SRT_ERR_HIP;
+    if (st != SRT_OK) {
+        plan_free(p);
+        return st;
+    }
+    *out = p;
+    return SRT_OK;
+}
+
+void srt_batch_plan_destroy(srt_batch_plan* p) { plan_free(p); }
+
+srt_status srt_batch_plan_info(const srt_batch_plan* p, int64_t* rows, int64_t* samples,
+                               int64_t* items)
+{
+    if (!p) return SRT_ERR_INVALID_ARG;
+    if (rows) *rows = p->rows;
+    if (samples) *samples = p->n_samples;
+    if (items) *items = p->tuning.persistent ? p->n_items : p->n_rays;
+    return SRT_OK;
+}
+
+srt_status srt_batch_plan_execute(srt_batch_plan* p, float* rgb, int32_t* hit_gid,
+                                  uint64_t* counters, void* stream)
+{
+    if (!p || (!rgb && p->rows > 0)) return SRT_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!p->exec || p->g_rgb != rgb || p->g_hits != hit_gid || p->g_counters != counters) {
+        // (re)capture: the graph holds the output pointers it was captured with
+        if (p->exec) {
+            (void)hipGraphExecDestroy(p->exec);
+            p->exec = nullptr;
+        }
+        if (p->graph) {
+            (void)hipGraphDestroy(p->graph);
+            p->graph = nullptr;
+        }
+        SRT_HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        const srt_status st = enqueue(p, rgb, hit_gid, counters, p->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        if (st != SRT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        SRT_HIP_TRY(e);
+        p->graph = g;
+        SRT_HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+        p->g_rgb = rgb;
+        p->g_hits = hit_gid;
+        p->g_counters = counters;
+    }
+    SRT_HIP_TRY(hipGraphLaunch(p->exec, s));
+    return SRT_OK;
+}
+
+srt_status srt_batch_plan_execute_eager(srt_batch_plan* p, float* rgb, int32_t* hit_gid,
+                                        uint64_t* counters, void* stream)
+{
+    if (!p || (!rgb && p->rows > 0)) return SRT_ERR_INVALID_ARG;
+    return enqueue(p, rgb, hit_gid, counters, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
