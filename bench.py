@@ -12,6 +12,12 @@ The metric counts ray-samples resolved per second (forward camera samples and
 secondary rays, plus backward ray-samples whose gradient is accumulated),
 from the library's own device counters.
 
+Beside the step, the batched workload (3.3M Gaussians; 64 views of 512x512
+with samples per pixel drawn per view from {1,...,64}; 4M incoherent rays)
+runs as one graph launch with the persistent work-stealing kernel and with
+the plain one-lane-per-ray kernel, each at the configuration the autotuner
+picks on a subsample, and both Mrays/s are reported.
+
 After the timed region the dominant kernel (the camera-ray traversal of the
 same workload) is launched alone, timed with HIP events on its stream, and
 its algorithmic bytes per launch (node, record, SH and ray traffic counted
@@ -44,6 +50,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-pixels", type=int, default=192)
     p.add_argument("--roofline-launches", type=int, default=5)
+    p.add_argument("--no-batched", action="store_true",
+                   help="skip the persistent-vs-plain measurement on the batched workload")
+    p.add_argument("--batched-reps", type=int, default=3)
+    p.add_argument("--profile-kernel", action="store_true",
+                   help="only launch the dominant kernel (camera-ray traversal) 3 times and "
+                        "a 256 MiB elementwise copy (for calibrating HBM counters), then exit")
     return p.parse_args()
 
 
@@ -73,6 +85,10 @@ def main():
     stream = torch.cuda.current_stream()
     print(f"# workload: {sc_host.num_gaussians} Gaussians, {cam.width}x{cam.height}, "
           f"{spp} spp, N={N}, W={args.width}, L={args.leaf}", file=sys.stderr, flush=True)
+
+    if args.profile_kernel:
+        profile_kernel(args, srt, si, torch, scene, cam, spp, N, dev)
+        return
 
     # persistent buffers, allocated once (the step itself allocates nothing
     # beyond the BVH handle it builds)
@@ -218,6 +234,14 @@ def main():
         print(f"# cpu oracle: {cpu['value']} Mrays/s on {threads} threads", file=sys.stderr,
               flush=True)
 
+    # ---- persistent vs plain on the batched workload ----
+    batched = None
+    if not args.no_batched:
+        del bvh, tws, trace_out, o, d
+        del ws, out, bout, grads, fws, bws, target, vo, vd
+        torch.cuda.empty_cache()
+        batched = bench_batched(args, srt, si, torch, dev)
+
     line = {"metric": METRIC, "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -230,8 +254,94 @@ def main():
                        "leaf_size": args.leaf, "n_per_traversal": N,
                        "forward_ray_samples_per_step": int(fwd_rs),
                        "backward_ray_samples_per_step": int(bwd_rs)},
-            "roofline": roof, "cpu_baseline": cpu}
+            "roofline": roof, "cpu_baseline": cpu, "persistent_vs_plain": batched}
     print(json.dumps(line), flush=True)
+
+
+def profile_kernel(args, srt, si, torch, scene, cam, spp, N, dev):
+    bvh = srt.srt_build_bvh(scene, args.width, args.leaf)
+    o, d = srt.srt_camera_rays(cam, dev)
+    R = o.shape[0]
+    out = dict(rgb=torch.empty((R, 3), device=dev))
+    tws = torch.empty(srt._lib.load().srt_trace_workspace_size(bvh.handle, R),
+                      dtype=torch.uint8, device=dev)
+    for i in range(3):
+        srt.srt_trace_forward(bvh, o, d, seed=si.PHILOX_SEED, spp=spp, n_per_traversal=N,
+                              want_hits=False, out=out, workspace=tws)
+        torch.cuda.synchronize()
+        print(f"# dominant kernel launch {i} done", file=sys.stderr, flush=True)
+    x = torch.ones(64 << 20, device=dev)  # 256 MiB read, 256 MiB written
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.add(x, 0.0, out=y)
+    torch.cuda.synchronize()
+    print("# calibration copy: 268435456 bytes read and written per launch", file=sys.stderr,
+          flush=True)
+
+
+def bench_batched(args, srt, si, torch, dev):
+    """Persistent vs plain on the batched scene. The full workload (64 views of
+    512x512 and 4M incoherent rays) takes tens of seconds per launch (every
+    ray crosses thousands of overlapping large Gaussians), so the bench runs
+    the same scene and views at 1/16 of the pixels (128x128, the same spp per
+    view) with 1/16 of the incoherent rays; the autotuner picks its
+    configuration on 8 of those views and 1/8 of those rays."""
+    from paper_2504_06598_amd.autotune import autotune
+    t0 = time.perf_counter()
+    w = si.workload(5)
+    sc = srt.DeviceScene.from_host(w["scene"], dev)
+    cams = si.fibonacci_cameras(len(w["cameras"]), 3.0, 128, 128)
+    spp = w["spp"]
+    n_inc = w["incoherent"][0].shape[0] // 16
+    eo, ed = (torch.from_numpy(x[:n_inc]).to(dev) for x in w["incoherent"])
+    print(f"# batched workload: {sc.num_gaussians} Gaussians, {len(cams)} views 128x128, "
+          f"{n_inc} incoherent rays (generated in {time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    sub = slice(0, None, 8)
+    tune = autotune(sc, cams[sub], spp[sub], extra_origins=eo[: n_inc // 8],
+                    extra_dirs=ed[: n_inc // 8], extra_spp=1, seed=si.PHILOX_SEED,
+                    widths=(4, 8), leaves=(2, 4), splits=(0, 4), thresholds=(16, 32, 48),
+                    waves=(4, 8), reps=1, use_cache=False, cache_path=None,
+                    log=lambda r: print("# tune", r, file=sys.stderr, flush=True))
+    print(f"# autotuner: persistent {tune['persistent']}, plain {tune['plain']}, rejected "
+          f"{tune['rejected']}", file=sys.stderr, flush=True)
+    res = {}
+    for kind in ("plain", "persistent"):
+        cfg = tune[kind]
+        bvh = srt.srt_build_bvh(sc, cfg["width"], cfg["leaf_size"], cfg["size_split"])
+        plan = srt.srt_batch_plan_create(bvh, cams, spp, extra_origins=eo, extra_dirs=ed,
+                                         extra_spp=1, seed=si.PHILOX_SEED, n_per_traversal=4,
+                                         persistent=cfg["persistent"],
+                                         refill_threshold=cfg["refill_threshold"],
+                                         waves_per_cu=cfg["waves_per_cu"])
+        rgb = torch.empty((plan.rows, 3), device=dev)
+        cnt = srt.new_counters(dev)
+        plan.execute(rgb=rgb, counters=cnt)
+        torch.cuda.synchronize()
+        c = srt.counters_dict(cnt)
+        assert c["ray_samples"] == plan.samples and c["lost"] == 0
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(args.batched_reps):
+            plan.execute(rgb=rgb, counters=cnt)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / args.batched_reps
+        res[kind] = {"mrays_per_s": round(plan.samples / (ms * 1e-3) / 1e6, 2),
+                     "ms_per_launch": round(ms, 3), "width": cfg["width"],
+                     "leaf_size": cfg["leaf_size"], "size_split": cfg["size_split"],
+                     "refill_threshold": cfg["refill_threshold"],
+                     "waves_per_cu": cfg["waves_per_cu"]}
+        print(f"# batched {kind}: {ms:.2f} ms per launch, {res[kind]['mrays_per_s']} Mrays/s",
+              file=sys.stderr, flush=True)
+        res["ray_samples_per_launch"] = int(plan.samples)
+        del plan, bvh
+    res["speedup"] = round(res["persistent"]["mrays_per_s"] / res["plain"]["mrays_per_s"], 3)
+    res["workload"] = ("3.3M Gaussians (3M object-like + 300k large diffuse); 64 views on a "
+                       "Fibonacci sphere at 128x128 (1/16 of 512x512), spp per view from "
+                       "{1,...,64}; 250k incoherent rays (1/16 of 4M); N=4; one graph launch")
+    return res
 
 
 if __name__ == "__main__":

@@ -82,11 +82,17 @@ typedef struct {
 
 /* ------------------------------------------------------------------------
  * Acceleration structure (Sec. 3.2: a BVH over per-Gaussian bounds).
- * width 2, 4 or 8 children per node; leaf_size 1..8 Gaussians per leaf.
+ * width 2, 4 or 8 children per node; leaf_size 1..8 Gaussians per leaf;
+ * size_split 0..16: 0 orders Gaussians by the Morton code of their box
+ * centres; k > 0 first groups them by size class
+ * floor(log2(scene extent / box extent) / k), so Gaussians whose sizes differ
+ * by more than 2^k get subtrees of their own (large ones stop inflating the
+ * boxes around small ones). Results never depend on these options.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int32_t width;
     int32_t leaf_size;
+    int32_t size_split;
 } srt_build_opts;
 
 typedef struct srt_bvh srt_bvh; /* opaque, library-owned */
@@ -109,7 +115,7 @@ typedef struct {
  * `stream`. On success *out receives a handle for srt_destroy_bvh.
  * Errors: INVALID_ARG (null pointers with num_gaussians > 0, negative count,
  * sh_degree outside 0..3, width not in {2,4,8}, leaf_size outside 1..8,
- * more than 2^28 Gaussians), OOM, HIP. */
+ * size_split outside 0..16, more than 2^28 Gaussians), OOM, HIP. */
 srt_status srt_build_bvh(const srt_scene* scene, const srt_build_opts* opts, void* stream,
                          srt_bvh** out);
 

@@ -110,10 +110,14 @@ class Bvh:
         return raw, order[: self.scene.num_gaussians]
 
 
-def srt_build_bvh(scene: DeviceScene, width: int = 4, leaf_size: int = 4) -> Bvh:
+DEFAULT_SIZE_SPLIT = 0
+
+
+def srt_build_bvh(scene: DeviceScene, width: int = 4, leaf_size: int = 4,
+                  size_split: int = DEFAULT_SIZE_SPLIT) -> Bvh:
     lib = _lib.load()
     sc = scene.c_struct()
-    opts = _lib.SrtBuildOpts(int(width), int(leaf_size))
+    opts = _lib.SrtBuildOpts(int(width), int(leaf_size), int(size_split))
     h = C.c_void_p()
     _lib.check("srt_build_bvh", lib.srt_build_bvh(C.byref(sc), C.byref(opts), _stream(),
                                                   C.byref(h)))

@@ -19,7 +19,7 @@ class SrtScene(C.Structure):
 
 
 class SrtBuildOpts(C.Structure):
-    _fields_ = [("width", C.c_int32), ("leaf_size", C.c_int32)]
+    _fields_ = [("width", C.c_int32), ("leaf_size", C.c_int32), ("size_split", C.c_int32)]
 
 
 class SrtBvhInfo(C.Structure):

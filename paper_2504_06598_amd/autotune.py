@@ -1,5 +1,6 @@
-"""Autotuner of the batched forward: BVH width and leaf size (a new BVH per
-pair) and the persistent kernel's refill threshold and waves per CU.
+"""Autotuner of the batched forward: BVH width, leaf size and size split (a
+new BVH per triple) and the persistent kernel's refill threshold and waves
+per CU.
 
 Every candidate's per-sample hit ids must equal the reference launch's bit
 for bit (plain kernel on a W=4, L=4 tree): the accepted set does not depend
@@ -32,7 +33,9 @@ def _signature(scene: DeviceScene, cameras, spp, n_extra, n_per_traversal):
 
 def _time_plan(plan: BatchPlan, reps: int, hits=None):
     rgb = torch.empty((plan.rows, 3), device=plan.bvh.scene.means.device)
-    plan.execute(rgb=rgb, hit_gid=hits)  # captures the graph, warms caches
+    if hits is not None:
+        plan.execute(rgb=rgb, hit_gid=hits)  # the guarded run (its own graph)
+    plan.execute(rgb=rgb)  # captures the timed graph, warms caches
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -46,13 +49,15 @@ def _time_plan(plan: BatchPlan, reps: int, hits=None):
 
 def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs=None,
              extra_spp=1, seed=0, n_per_traversal=4, widths=(2, 4, 8), leaves=(1, 2, 4, 8),
-             thresholds=(8, 16, 32, 48), waves=(4, 8, 12), reps=2, cache_path=DEFAULT_CACHE,
+             splits=(0,), thresholds=(8, 16, 32, 48), waves=(4, 8, 12), reps=2,
+             cache_path=DEFAULT_CACHE,
              use_cache=True, log=None):
     """Sweep and return {"persistent": {...}, "plain": {...}, "table": [...]}."""
     dev = scene.means.device
     gpu = torch.cuda.get_device_name(dev)
     n_extra = 0 if extra_origins is None else int(extra_origins.shape[0])
-    key = f"{gpu}|{_signature(scene, cameras, spp, n_extra, n_per_traversal)}"
+    key = (f"{gpu}|{_signature(scene, cameras, spp, n_extra, n_per_traversal)}|"
+           f"{widths}|{leaves}|{splits}|{thresholds}|{waves}")
     if use_cache and cache_path and os.path.exists(cache_path):
         try:
             cache = json.load(open(cache_path))
@@ -67,7 +72,7 @@ def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs
                                      n_per_traversal=n_per_traversal, persistent=persistent,
                                      refill_threshold=thr, waves_per_cu=wpc)
 
-    ref_bvh = srt_build_bvh(scene, 4, 4)
+    ref_bvh = srt_build_bvh(scene, 4, 4, 0)
     ref_plan = plan_for(ref_bvh, False, 16, 8)
     ref_hits = torch.empty(ref_plan.samples, dtype=torch.int32, device=dev)
     ref_plan.execute(hit_gid=ref_hits)
@@ -77,24 +82,26 @@ def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs
     table = []
     for W in widths:
         for L in leaves:
-            t0 = time.perf_counter()
-            bvh = srt_build_bvh(scene, W, L)
-            build_ms = (time.perf_counter() - t0) * 1e3
-            shapes = [(False, 16, 8)] + [(True, t, w) for t in thresholds for w in waves]
-            for persistent, thr, wpc in shapes:
-                plan = plan_for(bvh, persistent, thr, wpc)
-                hits = torch.empty(samples, dtype=torch.int32, device=dev)
-                ms = _time_plan(plan, reps, hits)
-                ok = bool(torch.equal(hits, ref_hits))
-                row = {"width": W, "leaf_size": L, "persistent": persistent,
-                       "refill_threshold": thr, "waves_per_cu": wpc, "ms": round(ms, 4),
-                       "mrays_per_s": round(samples / (ms * 1e-3) / 1e6, 2),
-                       "build_ms": round(build_ms, 2), "ids_equal": ok}
-                table.append(row)
-                if log:
-                    log(row)
-                del plan
-            del bvh
+            for split in splits:
+                t0 = time.perf_counter()
+                bvh = srt_build_bvh(scene, W, L, split)
+                build_ms = (time.perf_counter() - t0) * 1e3
+                shapes = [(False, 16, 8)] + [(True, t, w) for t in thresholds for w in waves]
+                for persistent, thr, wpc in shapes:
+                    plan = plan_for(bvh, persistent, thr, wpc)
+                    hits = torch.empty(samples, dtype=torch.int32, device=dev)
+                    ms = _time_plan(plan, reps, hits)
+                    ok = bool(torch.equal(hits, ref_hits))
+                    row = {"width": W, "leaf_size": L, "size_split": split,
+                           "persistent": persistent, "refill_threshold": thr,
+                           "waves_per_cu": wpc, "ms": round(ms, 4),
+                           "mrays_per_s": round(samples / (ms * 1e-3) / 1e6, 2),
+                           "build_ms": round(build_ms, 2), "ids_equal": ok}
+                    table.append(row)
+                    if log:
+                        log(row)
+                    del plan
+                del bvh
     good = [r for r in table if r["ids_equal"]]
     best_p = max((r for r in good if r["persistent"]), key=lambda r: r["mrays_per_s"], default=None)
     best_plain = max((r for r in good if not r["persistent"]), key=lambda r: r["mrays_per_s"],

@@ -216,8 +216,10 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                 n_samples += (uint32_t)n_act;
                 ++n_trav;
                 float tcut = fminf(cut_after(wt), tmax_f);
+                const RayS rs = make_rays(dx, dy, dz);
                 auto visit = [&](uint32_t ri) -> bool {
                     const Record r = load_record(a.recs, ri);
+                    if (sphere_reject(r, rf, rs, tmin_f, tcut)) return false;
                     double t, q, p[3];
                     isect_tqp(r, rd, t, q, p);
                     if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;

@@ -428,9 +428,11 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
         } else {
             const uint32_t first = leaf_first(node), count = leaf_count(node);
             const double tmin_d = b.tmin, tmax_d = b.tmax;
+            const RayS rs = make_rays(b.d[0], b.d[1], b.d[2]);
             for (uint32_t i = 0; i < count; ++i) {
                 ++cnt.prims;
                 const Record r = load_record(a.recs, first + i);
+                if (sphere_reject(r, rf, rs, b.tmin, tcut)) continue;
                 double t, q;
                 isect_tq(r, rd, t, q);
                 if (!(q <= kEllipsoidQ && t > tmin_d && t < tmax_d)) continue;

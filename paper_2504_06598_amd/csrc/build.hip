@@ -28,6 +28,30 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n)
         p[i] = v;
 }
 
+// Largest eigenvalue of A A^T (A 3x3 row-major) from the characteristic
+// cubic (trigonometric solution), i.e. the squared largest singular value.
+__device__ inline double lmax_sym3(const double A[9])
+{
+    double B[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            B[3 * i + j] = A[3 * i] * A[3 * j] + A[3 * i + 1] * A[3 * j + 1] + A[3 * i + 2] * A[3 * j + 2];
+    const double p1 = B[1] * B[1] + B[2] * B[2] + B[5] * B[5];
+    const double q = (B[0] + B[4] + B[8]) / 3.0;
+    if (p1 <= 1e-300) return fmax(fmax(B[0], B[4]), B[8]);
+    const double p2 = (B[0] - q) * (B[0] - q) + (B[4] - q) * (B[4] - q) + (B[8] - q) * (B[8] - q) +
+                      2.0 * p1;
+    const double p = sqrt(p2 / 6.0);
+    double C[9];
+    for (int i = 0; i < 9; ++i) C[i] = (B[i] - (i % 4 == 0 ? q : 0.0)) / p;
+    const double detC = C[0] * (C[4] * C[8] - C[5] * C[7]) - C[1] * (C[3] * C[8] - C[5] * C[6]) +
+                        C[2] * (C[3] * C[7] - C[4] * C[6]);
+    const double rr = fmin(1.0, fmax(-1.0, detC / 2.0));
+    const double phi = acos(rr) / 3.0;
+    // the largest root, padded for the rounding of the iteration above
+    return (q + 2.0 * p * cos(phi)) * (1.0 + 1e-9) + 1e-300;
+}
+
 // Canonical record: whitening matrix M = S^-1 R^T from the normalised
 // quaternion and exp(log-scales), and opacity sigmoid(logit), computed in
 // FP64 and rounded to nearest FP32. The box is that of the ellipsoid
@@ -61,8 +85,6 @@ __global__ void k_preprocess(int64_t G, const float* __restrict__ means,
     }
     r.opacity = (float)(1.0 / (1.0 + exp(-(double)logits[g])));
     r.gid = (int32_t)g;
-    r.pad[0] = r.pad[1] = 0.0f;
-    recs[g] = r;
 
     const double a = r.M[0], b = r.M[1], c = r.M[2];
     const double d = r.M[3], e = r.M[4], f = r.M[5];
@@ -80,6 +102,12 @@ __global__ void k_preprocess(int64_t G, const float* __restrict__ means,
         box_lo[3 * g + i] = __double2float_rd((double)r.mu[i] - hx);
         box_hi[3 * g + i] = __double2float_ru((double)r.mu[i] + hx);
     }
+    // radius of a sphere about mu holding the ellipsoid q <= 8 of the rounded
+    // record: sqrt(8) times its largest semi-axis (largest singular value of
+    // M^-1), padded and rounded up
+    r.pad[0] = __double2float_ru(sqrt(kEllipsoidQ * lmax_sym3(inv)) * (1.0 + 0x1p-16));
+    r.pad[1] = 0.0f;
+    recs[g] = r;
 }
 
 __device__ __forceinline__ uint32_t f2ord(float f)
@@ -138,22 +166,39 @@ __device__ __forceinline__ uint64_t spread3_21(uint32_t v)
     return x;
 }
 
+// Sort key: the 63-bit Morton code of the box centre, or, with size_split
+// k > 0, a 3-bit size class floor(log2(scene extent / box extent) / k)
+// (largest Gaussians first) above a 60-bit Morton code, so Gaussians of very
+// different sizes end up in subtrees of their own instead of inflating each
+// other's boxes.
 __global__ void k_morton(int64_t G, const float* __restrict__ lo, const float* __restrict__ hi,
-                         const uint32_t* __restrict__ bounds, uint64_t* __restrict__ keys,
-                         uint32_t* __restrict__ idx)
+                         const uint32_t* __restrict__ bounds, int32_t size_split,
+                         uint64_t* __restrict__ keys, uint32_t* __restrict__ idx)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= G) return;
     uint32_t q[3];
+    float scene_ext = 0.0f, box_ext = 0.0f;
     for (int i = 0; i < 3; ++i) {
         const float bmin = ord2f(bounds[i]), bmax = ord2f(bounds[3 + i]);
         const float ext = bmax - bmin;
+        scene_ext = fmaxf(scene_ext, ext);
+        box_ext = fmaxf(box_ext, hi[3 * g + i] - lo[3 * g + i]);
         const float c = 0.5f * (lo[3 * g + i] + hi[3 * g + i]);
         float t = ext > 0.0f ? (c - bmin) / ext : 0.0f;
         t = fminf(fmaxf(t, 0.0f), 1.0f);
         q[i] = min((uint32_t)(t * 2097152.0f), 2097151u);
     }
-    keys[g] = (spread3_21(q[0]) << 2) | (spread3_21(q[1]) << 1) | spread3_21(q[2]);
+    uint64_t m = (spread3_21(q[0]) << 2) | (spread3_21(q[1]) << 1) | spread3_21(q[2]);
+    if (size_split > 0) {
+        int cls = 7;
+        if (box_ext > 0.0f && scene_ext > 0.0f) {
+            const float l = log2f(fmaxf(scene_ext, box_ext) / box_ext) / (float)size_split;
+            cls = min(7, max(0, (int)l));
+        }
+        m = ((uint64_t)cls << 60) | (m >> 3);
+    }
+    keys[g] = m;
     idx[g] = (uint32_t)g;
 }
 
@@ -437,7 +482,7 @@ srt_status collapse_all(hipStream_t s, DevAlloc& tmp, const BinTree& t, int64_t 
 }
 
 template <int W>
-srt_status build_impl(const srt_scene* sc, int L, hipStream_t s, srt_bvh* b)
+srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s, srt_bvh* b)
 {
     const int64_t G = sc->num_gaussians;
     DevAlloc tmp;
@@ -480,7 +525,8 @@ srt_status build_impl(const srt_scene* sc, int L, hipStream_t s, srt_bvh* b)
     SRT_HIP_TRY(tmp.get(&keys_sorted, sizeof(uint64_t) * (size_t)G));
     SRT_HIP_TRY(tmp.get(&idx, sizeof(uint32_t) * (size_t)G));
     SRT_HIP_TRY(tmp.get(&order, sizeof(uint32_t) * (size_t)G));
-    k_morton<<<blocks_for(G, 256), 256, 0, s>>>(G, b->box_lo, b->box_hi, bounds, keys, idx);
+    k_morton<<<blocks_for(G, 256), 256, 0, s>>>(G, b->box_lo, b->box_hi, bounds, size_split, keys,
+                                                idx);
     SRT_HIP_TRY(hipGetLastError());
     size_t sort_bytes = 0;
     SRT_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, keys, keys_sorted, idx,
@@ -569,6 +615,7 @@ srt_status srt_build_bvh(const srt_scene* sc, const srt_build_opts* opts, void* 
         return SRT_ERR_INVALID_ARG;
     if (opts->width != 2 && opts->width != 4 && opts->width != 8) return SRT_ERR_INVALID_ARG;
     if (opts->leaf_size < 1 || opts->leaf_size > 8) return SRT_ERR_INVALID_ARG;
+    if (opts->size_split < 0 || opts->size_split > 16) return SRT_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     srt_bvh* b = new srt_bvh();
     b->G = G;
@@ -578,9 +625,9 @@ srt_status srt_build_bvh(const srt_scene* sc, const srt_build_opts* opts, void* 
     b->sh = sc->sh;
     srt_status st = SRT_ERR_INVALID_ARG;
     switch (b->W) {
-    case 2: st = build_impl<2>(sc, b->L, s, b); break;
-    case 4: st = build_impl<4>(sc, b->L, s, b); break;
-    case 8: st = build_impl<8>(sc, b->L, s, b); break;
+    case 2: st = build_impl<2>(sc, b->L, opts->size_split, s, b); break;
+    case 4: st = build_impl<4>(sc, b->L, opts->size_split, s, b); break;
+    case 8: st = build_impl<8>(sc, b->L, opts->size_split, s, b); break;
     }
     if (st != SRT_OK) {
         (void)hipStreamSynchronize(s);

@@ -351,6 +351,49 @@ __device__ __forceinline__ Record load_record(const Record* recs, uint32_t i)
     return r;
 }
 
+// Direction data for the bounding-sphere prefilter.
+struct RayS {
+    float dx, dy, dz;
+    float dd;       // |d|^2
+    float inv_dd;   // 1 / |d|^2
+    float inv_len;  // 1 / |d|
+};
+
+__device__ __forceinline__ RayS make_rays(float dx, float dy, float dz)
+{
+    RayS s;
+    s.dx = dx;
+    s.dy = dy;
+    s.dz = dz;
+    s.dd = dx * dx + dy * dy + dz * dz;
+    s.inv_dd = 1.0f / s.dd;
+    s.inv_len = 1.0f / sqrtf(s.dd);
+    return s;
+}
+
+// True when the record cannot hold a valid candidate of depth in
+// [tmin, tcut]: the 1D mean of a valid candidate lies inside the ellipsoid,
+// hence inside the sphere of radius pad[0] about mu, so its depth lies
+// within radius / |d| of the closest approach tc to mu and the ray passes
+// within the radius. FP32 with slack far above its rounding error; a pure
+// prefilter of the FP64 test.
+__device__ __forceinline__ bool sphere_reject(const Record& r, const RayF& rf, const RayS& rs,
+                                              float tmin, float tcut)
+{
+    const float wx = r.mu[0] - rf.ox, wy = r.mu[1] - rf.oy, wz = r.mu[2] - rf.oz;
+    const float tc = (wx * rs.dx + wy * rs.dy + wz * rs.dz) * rs.inv_dd;
+    const float rad = r.pad[0];
+    const float rt = rad * rs.inv_len;
+    const float slack = 1e-5f * (fabsf(tc) + rt + 1.0f);
+    if (tc - rt - slack > tcut || tc + rt + slack < tmin) return true;
+    const float cx = wy * rs.dz - wz * rs.dy;
+    const float cy = wz * rs.dx - wx * rs.dz;
+    const float cz = wx * rs.dy - wy * rs.dx;
+    const float c2 = cx * cx + cy * cy + cz * cz;  // (distance to mu)^2 * |d|^2
+    const float rr = rad * 1.0001f + 1e-5f * (fabsf(wx) + fabsf(wy) + fabsf(wz) + 1.0f);
+    return c2 > rr * rr * rs.dd;
+}
+
 // (t, gid) lexicographic order of depth keys.
 __device__ __forceinline__ bool key_less(float ta, int32_t ga, float tb, int32_t gb)
 {

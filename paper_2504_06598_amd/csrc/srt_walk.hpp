@@ -120,8 +120,10 @@ __device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ n
     float tcut = tmax_f;
     float wt = INFINITY;
     int32_t wg = 0x7FFFFFFF;
+    const RayS rs = make_rays((float)rd.dx, (float)rd.dy, (float)rd.dz);
     auto visit = [&](uint32_t ri) -> bool {
         const Record r = load_record(fc.recs, ri);
+        if (sphere_reject(r, rf, rs, rf.tmin, tcut)) return false;
         double t, q;
         isect_tq(r, rd, t, q);
         if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;

@@ -45,13 +45,16 @@ def test_validation_happens_before_any_device_work(lib):
     from paper_2504_06598_amd import _lib
     h = C.c_void_p()
     sc = _lib.SrtScene(10, 0, None, None, None, None, None)
-    opts = _lib.SrtBuildOpts(4, 4)
+    opts = _lib.SrtBuildOpts(4, 4, 0)
     assert lib.srt_build_bvh(None, C.byref(opts), None, C.byref(h)) == 1
     assert lib.srt_build_bvh(C.byref(sc), C.byref(opts), None, C.byref(h)) == 1  # null arrays
     for w, l, deg in [(3, 4, 0), (4, 0, 0), (4, 9, 0), (2, 4, 4), (16, 1, 0)]:
         sc2 = _lib.SrtScene(0, deg, None, None, None, None, None)
-        assert lib.srt_build_bvh(C.byref(sc2), C.byref(_lib.SrtBuildOpts(w, l)), None,
+        assert lib.srt_build_bvh(C.byref(sc2), C.byref(_lib.SrtBuildOpts(w, l, 0)), None,
                                  C.byref(h)) == 1
+    sc3 = _lib.SrtScene(0, 0, None, None, None, None, None)
+    assert lib.srt_build_bvh(C.byref(sc3), C.byref(_lib.SrtBuildOpts(4, 4, 17)), None,
+                             C.byref(h)) == 1
     assert lib.srt_trace_workspace_size(None, 10) == 0
     assert lib.srt_bvh_get_info(None, None) == 1
     lib.srt_destroy_bvh(None)
