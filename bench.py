@@ -150,16 +150,24 @@ def main():
         step(k, None, None)
         print(f"# warmup step {k} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    counters.zero_()
-    bw_counters.zero_()
     keep = []
     t0 = time.perf_counter()
+    for k in range(args.steps):
+        keep.append(step(args.warmup + k, None, None))
+        if len(keep) > 1:
+            keep.pop(0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    keep.clear()
+    # the same steps again with the library's counters (deterministic: same
+    # seeds and sample offsets), to count the ray-samples the timed steps did
+    counters.zero_()
+    bw_counters.zero_()
     for k in range(args.steps):
         keep.append(step(args.warmup + k, counters, bw_counters))
         if len(keep) > 1:
             keep.pop(0)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     keep.clear()
     c = srt.counters_dict(counters)
     cb = srt.counters_dict(bw_counters)

@@ -24,11 +24,11 @@
  *    (seed low 32 bits, seed high 32 bits) and counter
  *    (ray id, sample / 4, Gaussian id, purpose); u = (word[sample % 4] >> 8)
  *    * 2^-24. A candidate is accepted iff u < alpha.
- *  - A candidate is valid iff its depth t (the mean of the 1D Gaussian the
- *    ray cuts through it, Sec. 3.1) satisfies tmin < t < tmax and its squared
- *    Mahalanobis distance q at t satisfies q <= s^2 = 8 (eqn "cuboid",
- *    s = 2 sqrt 2); alpha = opacity * exp(-q / 2). The depth key is t rounded
- *    to FP32; keys compare as (t, Gaussian id).
+ *  - A candidate is valid iff its depth t (by default the mean t* of the 1D
+ *    Gaussian the ray cuts through it, Sec. 3.1; see depth_mode) satisfies
+ *    tmin < t < tmax and its squared Mahalanobis distance q at t* satisfies
+ *    q <= s^2 = 8 (eqn "cuboid", s = 2 sqrt 2); alpha = opacity * exp(-q / 2).
+ *    The depth key is t rounded to FP32; keys compare as (t, Gaussian id).
  */
 #ifndef SRT_H
 #define SRT_H
@@ -172,7 +172,14 @@ typedef struct {
  *                 in all three channels and hit_gid is any accepted id.
  *                 Requires n_per_traversal == 1.
  * stack_limit     0 = default; otherwise caps the on-chip traversal stack
- *                 (testing: forces the deep-stack path).                     */
+ *                 (testing: forces the deep-stack path).
+ * depth_mode      0: a candidate's depth is the mean of the 1D Gaussian along
+ *                 the ray (Sec. 3.1). 1: the Gaussian centre projected onto
+ *                 depth_axis, as the ray parameter of the same depth along
+ *                 the axis, t = ((mu - o) . a) / (d . a) (Sec. 4.1; the
+ *                 rasterizer-compatible depth); depth_axis (0,0,0) means each
+ *                 ray's own direction. Opacity stays at the 1D peak; the
+ *                 range test and the depth key use this depth.             */
 typedef struct {
     uint64_t seed;
     int32_t spp;
@@ -181,6 +188,8 @@ typedef struct {
     float bg[3];
     int32_t any_hit;
     int32_t stack_limit;
+    int32_t depth_mode;
+    float depth_axis[3];
 } srt_trace_opts;
 
 /* Counters accumulated (+=) into a device uint64 array of SRT_NUM_COUNTERS

@@ -185,6 +185,26 @@ class Rays:
         return self.o.shape[0]
 
 
+def set_depth_mode(mode=0, axis=(0.0, 0.0, 0.0)):
+    """Depth used for ordering and the range test: 0 = mean of the 1D Gaussian
+    along the ray (Sec. 3.1); 1 = centre projected onto `axis` (Sec. 4.1;
+    zero axis = each ray's direction). Applies to every later call."""
+    _load().srto_set_depth_mode(C.c_int(mode), _p(_f64(axis)))
+
+
+class depth_mode:
+    """Context manager selecting the oracle's depth mode."""
+
+    def __init__(self, mode, axis=(0.0, 0.0, 0.0)):
+        self.mode, self.axis = mode, axis
+
+    def __enter__(self):
+        set_depth_mode(self.mode, self.axis)
+
+    def __exit__(self, *exc):
+        set_depth_mode(0)
+
+
 def trace(rec: Records, rays: Rays, spp=1, seed=0, purpose=0, any_hit=False,
           bg=(0.0, 0.0, 0.0), u_override=None, threads=None):
     """Nearest accepted hit per sample (brute force, FP64)."""

@@ -296,8 +296,40 @@ static int near_rel(double a, double b)
     return fabs(a - b) <= 1e-9 * s;
 }
 
-/* Brute-force candidate collection for one ray: every Gaussian whose 1D mean
- * is valid, plus borderline ones (kept for flagging, never selected). */
+/* Depth of a candidate (Sec. 3.1 and Sec. 4.1). Mode 0 ("mean"): the mean
+ * of the 1D Gaussian along the ray. Mode 1 ("center"): the Gaussian centre
+ * projected onto a viewing axis a, expressed as the ray parameter with the
+ * same depth along a: t = ((mu - o) . a) / (d . a); a = (0,0,0) means the
+ * ray's own direction. Opacity stays at the 1D peak in both modes. */
+static int g_depth_mode = 0;
+static double g_axis[3] = {0.0, 0.0, 0.0};
+
+void srto_set_depth_mode(int mode, const double* axis)
+{
+    g_depth_mode = mode;
+    for (int i = 0; i < 3; ++i) g_axis[i] = axis ? axis[i] : 0.0;
+}
+
+static double depth_key(const isect_t* r, const double* mu, const float* o, const float* d)
+{
+    if (g_depth_mode == 0) return r->t;
+    double a[3] = {g_axis[0], g_axis[1], g_axis[2]};
+    if (a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0) {
+        a[0] = d[0];
+        a[1] = d[1];
+        a[2] = d[2];
+    }
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        num += (mu[i] - (double)o[i]) * a[i];
+        den += (double)d[i] * a[i];
+    }
+    return num / den;
+}
+
+/* Brute-force candidate collection for one ray: every Gaussian whose depth
+ * is in the open ray range and whose 1D mean is inside the ellipsoid, plus
+ * borderline ones (kept for flagging, never selected). */
 static void collect(int64_t G, const double* mu, const double* M, const double* op,
                     const float* o, const float* d, double tmin, double tmax,
                     int32_t ignore_gid, clist_t* out)
@@ -307,16 +339,17 @@ static void collect(int64_t G, const double* mu, const double* M, const double* 
         if ((int32_t)g == ignore_gid) continue;
         isect_t r;
         isect(mu + 3 * g, M + 9 * g, o, d, &r);
-        int valid = (r.t > tmin && r.t < tmax && r.q <= SRTO_S2);
-        int border = near_rel(r.q, SRTO_S2) || near_rel(r.t, tmin) ||
-                     (isfinite(tmax) && near_rel(r.t, tmax));
+        const double t = depth_key(&r, mu + 3 * g, o, d);
+        int valid = (t > tmin && t < tmax && r.q <= SRTO_S2);
+        int border = near_rel(r.q, SRTO_S2) || near_rel(t, tmin) ||
+                     (isfinite(tmax) && near_rel(t, tmax));
         if (!valid && !border) continue;
-        if (!(r.t == r.t)) continue;
+        if (!(t == t)) continue;
         cand_t c;
-        c.t = r.t;
+        c.t = t;
         c.q = r.q;
         c.alpha = op[g] * exp(-0.5 * r.q);
-        c.t32 = (float)r.t;
+        c.t32 = (float)t;
         c.gid = (int32_t)g;
         c.valid = valid;
         c.borderline = border;

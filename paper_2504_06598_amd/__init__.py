@@ -133,8 +133,12 @@ def counters_dict(c):
     return {n: int(x) for n, x in zip(COUNTER_NAMES, v)}
 
 
-def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit):
+def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode=0,
+          depth_axis=(0.0, 0.0, 0.0)):
     o = _lib.SrtTraceOpts()
+    o.depth_mode = int(depth_mode)
+    for i in range(3):
+        o.depth_axis[i] = float(depth_axis[i])
     o.seed = int(seed)
     o.spp = int(spp)
     o.n_per_traversal = int(n_per_traversal)
@@ -149,8 +153,8 @@ def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit):
 def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_gid=None,
                       ray_ids=None, sample_ids=None, purpose=0, seed=0, spp=1,
                       n_per_traversal=1, sample_offset=0, bg=(0.0, 0.0, 0.0), any_hit=False,
-                      stack_limit=0, want_rgb=True, want_hits=True, counters=None,
-                      out=None, workspace=None):
+                      stack_limit=0, depth_mode=0, depth_axis=(0.0, 0.0, 0.0), want_rgb=True,
+                      want_hits=True, counters=None, out=None, workspace=None):
     """Trace rays (device tensors [R,3]); returns dict(rgb [R,3], hit_gid [R,spp],
     hit_t [R,spp])."""
     lib = _lib.load()
@@ -158,7 +162,8 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
     dev = origins.device
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
-    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit)
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode,
+                 depth_axis)
     res = dict(out or {})
     if want_rgb and "rgb" not in res:
         res["rgb"] = torch.empty((R, 3), dtype=torch.float32, device=dev)
@@ -177,7 +182,8 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
 def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t=None,
                        tmin=None, tmax=None, ignore_gid=None, ray_ids=None, sample_ids=None,
                        purpose=0, seed=0, spp=1, n_per_traversal=1, sample_offset=0,
-                       bg=(0.0, 0.0, 0.0), grads=None, counters=None, workspace=None):
+                       bg=(0.0, 0.0, 0.0), depth_mode=0, depth_axis=(0.0, 0.0, 0.0), grads=None,
+                       counters=None, workspace=None):
     """Accumulate gradients of sum(grad_rgb * E[rgb]) into `grads` (a dict of
     tensors shaped like the scene's; zeros are allocated when absent)."""
     lib = _lib.load()
@@ -189,7 +195,7 @@ def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t
                  ("means", "log_scales", "quats", "opacity_logits", "sh")}
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
-    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0)
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0, depth_mode, depth_axis)
     need = lib.srt_backward_workspace_size(bvh.handle, R)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -337,7 +343,8 @@ def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_d
                           extra_tmin=None, extra_tmax=None, extra_ray_ids=None, extra_purpose=4,
                           extra_spp=1, ray_id_base=0, seed=0, n_per_traversal=4,
                           sample_offset=0, bg=(0.0, 0.0, 0.0), stack_limit=0, persistent=True,
-                          refill_threshold=16, waves_per_cu=8) -> BatchPlan:
+                          refill_threshold=16, waves_per_cu=8, depth_mode=0,
+                          depth_axis=(0.0, 0.0, 0.0)) -> BatchPlan:
     lib = _lib.load()
     nv = len(cameras)
     cams = (_lib.SrtCamera * max(nv, 1))(*[_camera(c) for c in cameras])
@@ -347,7 +354,8 @@ def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_d
                          _ptr(extra_tmax), None, _ptr(extra_ray_ids), None, int(extra_purpose))
     batch = _lib.SrtBatch(nv, C.cast(cams, C.c_void_p), C.cast(spp_arr, C.c_void_p), extra,
                           int(extra_spp) if n_extra else 0, int(ray_id_base))
-    opts = _opts(seed, 1, n_per_traversal, sample_offset, bg, False, stack_limit)
+    opts = _opts(seed, 1, n_per_traversal, sample_offset, bg, False, stack_limit, depth_mode,
+                 depth_axis)
     tun = _lib.SrtTuning(1 if persistent else 0, int(refill_threshold), int(waves_per_cu))
     h = C.c_void_p()
     _lib.check("srt_batch_plan_create", lib.srt_batch_plan_create(

@@ -5,7 +5,9 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libsrt.so")
+# SRT_LIB_PATH selects another build of the same library (e.g. a variant
+# compiled with different flags); the default is the in-tree build.
+LIB_PATH = os.environ.get("SRT_LIB_PATH") or os.path.join(_PKG, "libsrt.so")
 
 SRT_NUM_COUNTERS = 8
 COUNTER_NAMES = ["traversals", "nodes", "prims", "candidates", "philox", "deep", "ray_samples",
@@ -37,7 +39,8 @@ class SrtRays(C.Structure):
 class SrtTraceOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("spp", C.c_int32), ("n_per_traversal", C.c_int32),
                 ("sample_offset", C.c_uint32), ("bg", C.c_float * 3), ("any_hit", C.c_int32),
-                ("stack_limit", C.c_int32)]
+                ("stack_limit", C.c_int32), ("depth_mode", C.c_int32),
+                ("depth_axis", C.c_float * 3)]
 
 
 class SrtCamera(C.Structure):

@@ -70,6 +70,9 @@ struct BwdArgs {
     int32_t cap;
     int64_t max_steps;
     unsigned long long* counters;
+    int32_t depth_mode;
+    float depth_axis[3];
+    float r_max;
 };
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v)
@@ -155,9 +158,9 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
             const int32_t ign = a.ign ? a.ign[ray] : -1;
             const uint32_t rid = a.rid ? a.rid[ray] : (uint32_t)ray;
             const uint32_t sbase = (a.sid ? a.sid[ray] : 0u) + a.soff;
-            const RayF rf = make_rayf(ox, oy, oz, dx, dy, dz, tmin_f);
-            const RayD rd{ox, oy, oz, dx, dy, dz};
+            const Ray rr = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
             const double tmin = tmin_f, tmax = tmax_f;
+            const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rr, a.r_max);
             float Y[16];
             {
                 const float n = sqrtf(dx * dx + dy * dy + dz * dz);
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
                     uint32_t dummy_nodes = 0, dummy_prims = 0;
                     const int res = resolve_samples<W, N, false>(
-                        nodes, fc, rf, rd, tmin, tmax, ign, rid, sbase + (uint32_t)(pass * N),
+                        nodes, fc, dc, rr, tmin, tmax, ign, rid, sbase + (uint32_t)(pass * N),
                         n_act, stk, a.max_steps, ta, ga, dummy_nodes, dummy_prims, n_fwd_cands,
                         n_philox);
                     if (res == kWalkOverflow) {
@@ -216,12 +219,14 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                 n_samples += (uint32_t)n_act;
                 ++n_trav;
                 float tcut = fminf(cut_after(wt), tmax_f);
-                const RayS rs = make_rays(dx, dy, dz);
                 auto visit = [&](uint32_t ri) -> bool {
                     const Record r = load_record(a.recs, ri);
-                    if (sphere_reject(r, rf, rs, tmin_f, tcut)) return false;
-                    double t, q, p[3];
-                    isect_tqp(r, rd, t, q, p);
+                    if (dc.mode == 0 ? sphere_reject(r, rr, tmin_f, tcut)
+                                     : sphere_reject(r, rr, -INFINITY, INFINITY))
+                        return false;
+                    double tm, q, p[3];
+                    isect_tqp(r, rr, tm, q, p);
+                    const double t = depth_of(dc, r, rr, tm);
                     if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
                     const float t32 = (float)t;
                     if (!key_less(t32, r.gid, wt, wg)) return false;
@@ -251,7 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     table_add(table, a.acc, r.gid, v);
                     return false;
                 };
-                const int res = walk<W>(nodes, rf, tcut, stk, a.max_steps, n_nodes, n_prims, visit);
+                const int res = walk<W>(nodes, rr, tcut, dc.node_slack, stk, a.max_steps, n_nodes,
+                                        n_prims, visit);
                 if (res == kWalkOverflow) ++n_lost;
                 // colour gradient of each accepted result, samples sharing a Gaussian merged
 #pragma unroll
@@ -429,6 +435,7 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
 {
     if (!b || !rays || !opts || !scene) return SRT_ERR_INVALID_ARG;
     if (opts->spp < 1 || opts->any_hit) return SRT_ERR_INVALID_ARG;
+    if (opts->depth_mode != 0 && opts->depth_mode != 1) return SRT_ERR_INVALID_ARG;
     const int N = opts->n_per_traversal;
     if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
     if (rays->count < 0 || rays->count > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;
@@ -473,6 +480,9 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     a.cap = kLdsEntries + std::max(0, deep_stack_cap(b) - kLdsEntries);
     a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
     a.counters = reinterpret_cast<unsigned long long*>(counters);
+    a.depth_mode = opts->depth_mode;
+    for (int i = 0; i < 3; ++i) a.depth_axis[i] = opts->depth_axis[i];
+    a.r_max = b->r_max;
     BwdFn fn = pick(b->W, N);
     if (!fn) return SRT_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(fn, dim3(ws.threads / kBlock), dim3(kBlock), 0, s, a);

@@ -76,6 +76,9 @@ struct BatchArgs {
     int32_t threshold;
     int64_t max_steps;
     int32_t N;
+    int32_t depth_mode;
+    float depth_axis[3];
+    float r_max;
 };
 
 // Segment of an item (by_item) or plain lane index by binary search.
@@ -184,18 +187,17 @@ __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int 
                                          LaneCounts& cnt, bool atomic, float acc[3])
 {
     const int n_act = min(N, b.spp - pass * N);
-    const RayF rf = make_rayf(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
-    const RayD rd{b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2]};
+    const Ray ray = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
     const ForwardCtx fc{a.recs, b.purpose, a.k0, a.k1};
+    const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, ray, a.r_max);
     float bt[N];
     int32_t bg[N];
     ++cnt.trav;
     const int res = resolve_samples<W, N, false>(
-        static_cast<const WideNode<W>*>(a.nodes), fc, rf, rd, (double)b.tmin, (double)b.tmax, -1,
+        static_cast<const WideNode<W>*>(a.nodes), fc, dc, ray, (double)b.tmin, (double)b.tmax, -1,
         b.rid, a.soff + (uint32_t)(pass * N), n_act, stk, a.max_steps, bt, bg, cnt.nodes, cnt.prims,
         cnt.cands, cnt.philox);
     if (res == kWalkOverflow) return false;
-    cnt.samples += (uint32_t)n_act;
     float Y[16];
     const float n = sqrtf(b.d[0] * b.d[0] + b.d[1] * b.d[1] + b.d[2] * b.d[2]);
     sh_eval(a.deg, b.d[0] / n, b.d[1] / n, b.d[2] / n, Y);
@@ -214,6 +216,8 @@ __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int 
     }
     const float w = 1.0f / (float)b.spp;
     if (atomic) {
+        // an item counts its samples when it completes (items are atomic units)
+        cnt.samples += (uint32_t)n_act;
         atomicAdd(a.rgb + 3 * b.row, c0 * w);
         atomicAdd(a.rgb + 3 * b.row + 1, c1 * w);
         atomicAdd(a.rgb + 3 * b.row + 2, c2 * w);
@@ -256,6 +260,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
             for (int pass = 0; pass * N < b.spp && ok; ++pass)
                 ok = run_pass<W, N>(a, b, pass, stk, cnt, false, acc);
             if (ok) {
+                cnt.samples += (uint32_t)b.spp;
                 const float w = 1.0f / (float)b.spp;
                 a.rgb[3 * b.row] = acc[0] * w;
                 a.rgb[3 * b.row + 1] = acc[1] * w;
@@ -292,6 +297,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_deep(BatchArgs a)
             atomicAdd(&a.ctrl[1], 1u);
             continue;
         }
+        cnt.samples += (uint32_t)b.spp;
         const float w = 1.0f / (float)b.spp;
         a.rgb[3 * b.row] = acc[0] * w;
         a.rgb[3 * b.row + 1] = acc[1] * w;
@@ -337,12 +343,9 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
     b.valid = false;
     int32_t pass = 0, n_act = 0;
     int64_t item_id = 0;
-    RayF rf;
-    RayD rd;
-    float bt[N];
-    int32_t bg[N];
-    float tcut = 0.0f, wt = 0.0f, tmax_f = 0.0f;
-    int32_t wg = 0;
+    Ray lr;
+    DepthCtx dc;
+    FwdSamples<N> st;
     int32_t node = 0;
     int sp = 0;
     int64_t steps = 0;
@@ -371,17 +374,9 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
                     if (b.valid) {
                         item_id = it;
                         n_act = min(N, b.spp - pass * N);
-                        rf = make_rayf(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
-                        rd = RayD{b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2]};
-#pragma unroll
-                        for (int k = 0; k < N; ++k) {
-                            bt[k] = k < n_act ? INFINITY : -INFINITY;
-                            bg[k] = 0x7FFFFFFF;
-                        }
-                        tmax_f = b.tmax;
-                        tcut = tmax_f;
-                        wt = INFINITY;
-                        wg = 0x7FFFFFFF;
+                        lr = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
+                        dc = make_depth(a.depth_mode, a.depth_axis, lr, a.r_max);
+                        st.reset(n_act, b.tmax);
                         node = 0;
                         sp = 0;
                         steps = 0;
@@ -402,7 +397,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
             NodeBuf<W> nb;
             load_node<W>(nodes, node, nb);
             uint32_t key[W];
-            slab_keys<W>(nb, rf, tcut, key);
+            slab_keys<W>(nb, lr, st.tcut + dc.node_slack, key);
             sort_keys<W>(key);
             int nh = 0;
 #pragma unroll
@@ -428,51 +423,16 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
         } else {
             const uint32_t first = leaf_first(node), count = leaf_count(node);
             const double tmin_d = b.tmin, tmax_d = b.tmax;
-            const RayS rs = make_rays(b.d[0], b.d[1], b.d[2]);
+            const ForwardCtx fc{a.recs, b.purpose, a.k0, a.k1};
+            FwdCounts fcnt;
+            const uint32_t s0 = a.soff + (uint32_t)(pass * N);
             for (uint32_t i = 0; i < count; ++i) {
                 ++cnt.prims;
                 const Record r = load_record(a.recs, first + i);
-                if (sphere_reject(r, rf, rs, b.tmin, tcut)) continue;
-                double t, q;
-                isect_tq(r, rd, t, q);
-                if (!(q <= kEllipsoidQ && t > tmin_d && t < tmax_d)) continue;
-                ++cnt.cands;
-                const float t32 = (float)t;
-                if (!key_less(t32, r.gid, wt, wg)) continue;
-                const double alpha = (double)r.opacity * exp(-0.5 * q);
-                uint4 w = make_uint4(0, 0, 0, 0);
-                uint32_t grp = 0xFFFFFFFFu;
-                bool changed = false;
-                const uint32_t s0 = a.soff + (uint32_t)(pass * N);
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    if (k < n_act && key_less(t32, r.gid, bt[k], bg[k])) {
-                        const uint32_t s = s0 + (uint32_t)k;
-                        if ((s >> 2) != grp) {
-                            grp = s >> 2;
-                            w = philox4x32_10(make_uint4(b.rid, grp, (uint32_t)r.gid, b.purpose),
-                                              a.k0, a.k1);
-                            ++cnt.philox;
-                        }
-                        if (u_of_word(word_of(w, s & 3u)) < alpha) {
-                            bt[k] = t32;
-                            bg[k] = r.gid;
-                            changed = true;
-                        }
-                    }
-                }
-                if (changed) {
-                    wt = -INFINITY;
-                    wg = (int32_t)0x80000000;
-#pragma unroll
-                    for (int k = 0; k < N; ++k)
-                        if (k < n_act && key_less(wt, wg, bt[k], bg[k])) {
-                            wt = bt[k];
-                            wg = bg[k];
-                        }
-                    tcut = fminf(cut_after(wt), tmax_f);
-                }
+                fwd_offer<N, false>(st, r, lr, dc, tmin_d, tmax_d, -1, b.rid, s0, fc, fcnt);
             }
+            cnt.cands += fcnt.cands;
+            cnt.philox += fcnt.philox;
             if (sp == 0) {
                 done = true;
             } else {
@@ -494,10 +454,10 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 if (k >= n_act) continue;
-                const bool hit = bg[k] != 0x7FFFFFFF;
-                if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? bg[k] : -1;
+                const bool hit = st.bg[k] != 0x7FFFFFFF;
+                if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? st.bg[k] : -1;
                 if (hit) {
-                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, bg[k], Y));
+                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, st.bg[k], Y));
                     c0 += c.x; c1 += c.y; c2 += c.z;
                 } else {
                     c0 += a.bg[0]; c1 += a.bg[1]; c2 += a.bg[2];
@@ -650,6 +610,9 @@ srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* count
     a.threshold = std::max(1, std::min(64, p->tuning.refill_threshold));
     a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
     a.N = p->opts.n_per_traversal;
+    a.depth_mode = p->opts.depth_mode;
+    for (int i = 0; i < 3; ++i) a.depth_axis[i] = p->opts.depth_axis[i];
+    a.r_max = b->r_max;
     k_reset<<<1, 64, 0, s>>>(p->work, p->ctrl);
     SRT_HIP_TRY(hipGetLastError());
     const bool persistent = p->tuning.persistent != 0;
@@ -688,6 +651,7 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
     const int N = opts->n_per_traversal;
     if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
     if (opts->any_hit || opts->stack_limit < 0) return SRT_ERR_INVALID_ARG;
+    if (opts->depth_mode != 0 && opts->depth_mode != 1) return SRT_ERR_INVALID_ARG;
     if (batch->num_views < 0 || (batch->num_views > 0 && (!batch->cameras || !batch->spp)))
         return SRT_ERR_INVALID_ARG;
     if (batch->extra.count < 0 || batch->extra_spp < 0) return SRT_ERR_INVALID_ARG;

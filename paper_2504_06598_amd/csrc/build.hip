@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "srt_internal.hpp"
@@ -121,12 +122,13 @@ __device__ __forceinline__ float ord2f(uint32_t o)
     return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
 }
 
-// Bounds of box centres: [0..2] min, [3..5] max, as order-preserving uints.
+// Bounds of box centres: [0..2] min, [3..5] max, as order-preserving uints;
+// [6] the largest bounding-sphere radius (positive float bits order as uints).
 __global__ void k_centre_bounds(int64_t G, const float* __restrict__ lo, const float* __restrict__ hi,
-                                uint32_t* out)
+                                const Record* __restrict__ recs, uint32_t* out)
 {
-    __shared__ uint32_t smin[3][256], smax[3][256];
-    uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
+    __shared__ uint32_t smin[3][256], smax[4][256];
+    uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[4] = {0u, 0u, 0u, 0u};
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < G;
          g += (int64_t)gridDim.x * blockDim.x) {
         for (int i = 0; i < 3; ++i) {
@@ -134,25 +136,27 @@ __global__ void k_centre_bounds(int64_t G, const float* __restrict__ lo, const f
             mn[i] = min(mn[i], c);
             mx[i] = max(mx[i], c);
         }
+        mx[3] = max(mx[3], __float_as_uint(recs[g].pad[0]));
     }
-    for (int i = 0; i < 3; ++i) {
-        smin[i][threadIdx.x] = mn[i];
-        smax[i][threadIdx.x] = mx[i];
-    }
+    for (int i = 0; i < 3; ++i) smin[i][threadIdx.x] = mn[i];
+    for (int i = 0; i < 4; ++i) smax[i][threadIdx.x] = mx[i];
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int i = 0; i < 3; ++i) {
+        if ((int)threadIdx.x < s) {
+            for (int i = 0; i < 3; ++i)
                 smin[i][threadIdx.x] = min(smin[i][threadIdx.x], smin[i][threadIdx.x + s]);
+            for (int i = 0; i < 4; ++i)
                 smax[i][threadIdx.x] = max(smax[i][threadIdx.x], smax[i][threadIdx.x + s]);
-            }
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         for (int i = 0; i < 3; ++i) {
             atomicMin(&out[i], smin[i][0]);
             atomicMax(&out[3 + i], smax[i][0]);
         }
+        atomicMax(&out[6], smax[3][0]);
+    }
 }
 
 __device__ __forceinline__ uint64_t spread3_21(uint32_t v)
@@ -515,8 +519,8 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
     SRT_HIP_TRY(tmp.get(&bounds, 8 * sizeof(uint32_t)));
     const uint32_t binit[8] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
     SRT_HIP_TRY(hipMemcpyAsync(bounds, binit, sizeof(binit), hipMemcpyHostToDevice, s));
-    k_centre_bounds<<<std::min<unsigned>(blocks_for(G, 256), 1024u), 256, 0, s>>>(G, b->box_lo,
-                                                                               b->box_hi, bounds);
+    k_centre_bounds<<<std::min<unsigned>(blocks_for(G, 256), 1024u), 256, 0, s>>>(
+        G, b->box_lo, b->box_hi, recs_id, bounds);
     SRT_HIP_TRY(hipGetLastError());
 
     uint64_t *keys = nullptr, *keys_sorted = nullptr;
@@ -569,7 +573,10 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
     b->nodes = nodes;
     SRT_HIP_TRY(hipMemcpyAsync(nodes, nodes_max, sizeof(WideNode<W>) * (size_t)num_nodes,
                                hipMemcpyDeviceToDevice, s));
+    uint32_t rmax_bits = 0;
+    SRT_HIP_TRY(hipMemcpyAsync(&rmax_bits, bounds + 6, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SRT_HIP_TRY(hipStreamSynchronize(s));
+    memcpy(&b->r_max, &rmax_bits, sizeof(float));
     b->num_nodes = num_nodes;
     b->depth = depth;
     b->bytes += (int64_t)sizeof(WideNode<W>) * num_nodes;

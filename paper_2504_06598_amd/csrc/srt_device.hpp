@@ -155,6 +155,15 @@ __device__ __forceinline__ void sh_eval(int deg, float x, float y, float z, floa
     Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
 }
 
+// Makes x opaque to the optimiser so that code using it is not hoisted out
+// of the loop it sits in (keeps e.g. the SH basis from living through a
+// whole traversal and costing registers there).
+__device__ __forceinline__ float opaque(float x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Unclamped SH colour sum of Gaussian gid (0.5 + sum k Y).
 __device__ __forceinline__ float3 sh_colour_pre(const float* sh, int deg, int32_t gid, const float* Y)
 {
@@ -185,10 +194,15 @@ __device__ __forceinline__ float3 clamp0(float3 c)
 constexpr float kIzeFactor = 1.0000003576278687f;  // 1 + 2 gamma_3, gamma_3 = 3u/(1-3u)
 constexpr float kCutSlack = 1.00000095367431641f;  // 1 + 2^-20
 
-struct RayF {
+// One ray, all FP32 (the FP64 candidate test converts on use, so no FP64
+// copy stays live during the traversal).
+struct Ray {
     float ox, oy, oz;
+    float dx, dy, dz;
     float ix, iy, iz;  // 1 / d, with |d_i| clamped away from 0
     float tmin;
+    float inv_dd;      // 1 / |d|^2
+    float inv_len;     // 1 / |d|
 };
 
 __device__ __forceinline__ float safe_inv(float d)
@@ -197,9 +211,29 @@ __device__ __forceinline__ float safe_inv(float d)
     return 1.0f / a;
 }
 
+__device__ __forceinline__ Ray make_ray(float ox, float oy, float oz, float dx, float dy, float dz,
+                                        float tmin)
+{
+    Ray r;
+    r.ox = ox;
+    r.oy = oy;
+    r.oz = oz;
+    r.dx = dx;
+    r.dy = dy;
+    r.dz = dz;
+    r.ix = safe_inv(dx);
+    r.iy = safe_inv(dy);
+    r.iz = safe_inv(dz);
+    r.tmin = tmin;
+    const float dd = dx * dx + dy * dy + dz * dz;
+    r.inv_dd = 1.0f / dd;
+    r.inv_len = 1.0f / sqrtf(dd);
+    return r;
+}
+
 // Hit mask and near-to-far sort keys of the W children of a node.
 template <int W>
-__device__ __forceinline__ void slab_keys(const NodeBuf<W>& b, const RayF& r, float tcut,
+__device__ __forceinline__ void slab_keys(const NodeBuf<W>& b, const Ray& r, float tcut,
                                           uint32_t key[W])
 {
 #pragma unroll
@@ -258,77 +292,25 @@ __device__ __forceinline__ void sort_keys<8>(uint32_t k[8])
 // cuts the Gaussian in a 1D Gaussian with mean t* = -(o'.d')/(d'.d'), where
 // o' = M (o - mu) and d' = M d; q = |o' + t* d'|^2 and alpha = o exp(-q/2).
 // --------------------------------------------------------------------------
-struct RayD {
-    double ox, oy, oz, dx, dy, dz;
-};
-
 struct Isect {
     double t, q;
     double p[3];  // whitened position at t*
-    double w[3];  // world offset x(t*) - mu
 };
 
-__device__ __forceinline__ void isect_record(const Record& r, const RayD& ray, Isect& out)
-{
-    const double wx = ray.ox - (double)r.mu[0];
-    const double wy = ray.oy - (double)r.mu[1];
-    const double wz = ray.oz - (double)r.mu[2];
-    double op[3], dp[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double m0 = r.M[3 * i], m1 = r.M[3 * i + 1], m2 = r.M[3 * i + 2];
-        op[i] = fma(m2, wz, fma(m1, wy, m0 * wx));
-        dp[i] = fma(m2, ray.dz, fma(m1, ray.dy, m0 * ray.dx));
-    }
-    const double dd = fma(dp[2], dp[2], fma(dp[1], dp[1], dp[0] * dp[0]));
-    const double od = fma(op[2], dp[2], fma(op[1], dp[1], op[0] * dp[0]));
-    const double t = -od / dd;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) out.p[i] = fma(t, dp[i], op[i]);
-    out.q = fma(out.p[2], out.p[2], fma(out.p[1], out.p[1], out.p[0] * out.p[0]));
-    out.t = t;
-    out.w[0] = fma(t, ray.dx, wx);
-    out.w[1] = fma(t, ray.dy, wy);
-    out.w[2] = fma(t, ray.dz, wz);
-}
-
-// Only t and q (the forward needs nothing else).
-__device__ __forceinline__ void isect_tq(const Record& r, const RayD& ray, double& t_out,
-                                         double& q_out)
-{
-    const double wx = ray.ox - (double)r.mu[0];
-    const double wy = ray.oy - (double)r.mu[1];
-    const double wz = ray.oz - (double)r.mu[2];
-    double op[3], dp[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double m0 = r.M[3 * i], m1 = r.M[3 * i + 1], m2 = r.M[3 * i + 2];
-        op[i] = fma(m2, wz, fma(m1, wy, m0 * wx));
-        dp[i] = fma(m2, ray.dz, fma(m1, ray.dy, m0 * ray.dx));
-    }
-    const double dd = fma(dp[2], dp[2], fma(dp[1], dp[1], dp[0] * dp[0]));
-    const double od = fma(op[2], dp[2], fma(op[1], dp[1], op[0] * dp[0]));
-    const double t = -od / dd;
-    const double p0 = fma(t, dp[0], op[0]);
-    const double p1 = fma(t, dp[1], op[1]);
-    const double p2 = fma(t, dp[2], op[2]);
-    t_out = t;
-    q_out = fma(p2, p2, fma(p1, p1, p0 * p0));
-}
-
-// t, q and the whitened position p (the backward's needs).
-__device__ __forceinline__ void isect_tqp(const Record& r, const RayD& ray, double& t_out,
+// t*, q and the whitened position p = M (x(t*) - mu).
+__device__ __forceinline__ void isect_tqp(const Record& r, const Ray& ray, double& t_out,
                                           double& q_out, double p[3])
 {
-    const double wx = ray.ox - (double)r.mu[0];
-    const double wy = ray.oy - (double)r.mu[1];
-    const double wz = ray.oz - (double)r.mu[2];
+    const double wx = (double)ray.ox - (double)r.mu[0];
+    const double wy = (double)ray.oy - (double)r.mu[1];
+    const double wz = (double)ray.oz - (double)r.mu[2];
+    const double dx = ray.dx, dy = ray.dy, dz = ray.dz;
     double op[3], dp[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const double m0 = r.M[3 * i], m1 = r.M[3 * i + 1], m2 = r.M[3 * i + 2];
         op[i] = fma(m2, wz, fma(m1, wy, m0 * wx));
-        dp[i] = fma(m2, ray.dz, fma(m1, ray.dy, m0 * ray.dx));
+        dp[i] = fma(m2, dz, fma(m1, dy, m0 * dx));
     }
     const double dd = fma(dp[2], dp[2], fma(dp[1], dp[1], dp[0] * dp[0]));
     const double od = fma(op[2], dp[2], fma(op[1], dp[1], op[0] * dp[0]));
@@ -337,6 +319,14 @@ __device__ __forceinline__ void isect_tqp(const Record& r, const RayD& ray, doub
     for (int i = 0; i < 3; ++i) p[i] = fma(t, dp[i], op[i]);
     t_out = t;
     q_out = fma(p[2], p[2], fma(p[1], p[1], p[0] * p[0]));
+}
+
+// Only t and q (the forward needs nothing else).
+__device__ __forceinline__ void isect_tq(const Record& r, const Ray& ray, double& t_out,
+                                         double& q_out)
+{
+    double p[3];
+    isect_tqp(r, ray, t_out, q_out, p);
 }
 
 __device__ __forceinline__ Record load_record(const Record* recs, uint32_t i)
@@ -351,47 +341,27 @@ __device__ __forceinline__ Record load_record(const Record* recs, uint32_t i)
     return r;
 }
 
-// Direction data for the bounding-sphere prefilter.
-struct RayS {
-    float dx, dy, dz;
-    float dd;       // |d|^2
-    float inv_dd;   // 1 / |d|^2
-    float inv_len;  // 1 / |d|
-};
-
-__device__ __forceinline__ RayS make_rays(float dx, float dy, float dz)
-{
-    RayS s;
-    s.dx = dx;
-    s.dy = dy;
-    s.dz = dz;
-    s.dd = dx * dx + dy * dy + dz * dz;
-    s.inv_dd = 1.0f / s.dd;
-    s.inv_len = 1.0f / sqrtf(s.dd);
-    return s;
-}
-
 // True when the record cannot hold a valid candidate of depth in
 // [tmin, tcut]: the 1D mean of a valid candidate lies inside the ellipsoid,
 // hence inside the sphere of radius pad[0] about mu, so its depth lies
 // within radius / |d| of the closest approach tc to mu and the ray passes
 // within the radius. FP32 with slack far above its rounding error; a pure
 // prefilter of the FP64 test.
-__device__ __forceinline__ bool sphere_reject(const Record& r, const RayF& rf, const RayS& rs,
-                                              float tmin, float tcut)
+__device__ __forceinline__ bool sphere_reject(const Record& r, const Ray& ray, float tmin,
+                                              float tcut)
 {
-    const float wx = r.mu[0] - rf.ox, wy = r.mu[1] - rf.oy, wz = r.mu[2] - rf.oz;
-    const float tc = (wx * rs.dx + wy * rs.dy + wz * rs.dz) * rs.inv_dd;
+    const float wx = r.mu[0] - ray.ox, wy = r.mu[1] - ray.oy, wz = r.mu[2] - ray.oz;
+    const float tc = (wx * ray.dx + wy * ray.dy + wz * ray.dz) * ray.inv_dd;
     const float rad = r.pad[0];
-    const float rt = rad * rs.inv_len;
+    const float rt = rad * ray.inv_len;
     const float slack = 1e-5f * (fabsf(tc) + rt + 1.0f);
     if (tc - rt - slack > tcut || tc + rt + slack < tmin) return true;
-    const float cx = wy * rs.dz - wz * rs.dy;
-    const float cy = wz * rs.dx - wx * rs.dz;
-    const float cz = wx * rs.dy - wy * rs.dx;
-    const float c2 = cx * cx + cy * cy + cz * cz;  // (distance to mu)^2 * |d|^2
+    const float cx = wy * ray.dz - wz * ray.dy;
+    const float cy = wz * ray.dx - wx * ray.dz;
+    const float cz = wx * ray.dy - wy * ray.dx;
+    const float c2 = (cx * cx + cy * cy + cz * cz) * ray.inv_dd;  // (distance to mu)^2
     const float rr = rad * 1.0001f + 1e-5f * (fabsf(wx) + fabsf(wy) + fabsf(wz) + 1.0f);
-    return c2 > rr * rr * rs.dd;
+    return c2 > rr * rr;
 }
 
 // (t, gid) lexicographic order of depth keys.

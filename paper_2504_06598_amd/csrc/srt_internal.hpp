@@ -19,6 +19,7 @@ struct srt_bvh {
     float* box_lo = nullptr;         // [G,3], Gaussian-id order
     float* box_hi = nullptr;
     const float* sh = nullptr;       // borrowed from the scene
+    float r_max = 0.0f;              // largest bounding-sphere radius
     int64_t bytes = 0;
 };
 

@@ -42,10 +42,12 @@ struct TwoTierStack {
 
 enum WalkResult { kWalkDone = 0, kWalkOverflow = 1, kWalkStopped = 2 };
 
-// visit(record_index) -> true stops the walk (any-hit termination).
+// visit(record_index) -> true stops the walk (any-hit termination). Boxes
+// are culled against tcut + slack (slack > 0 when keys are not bounded below
+// by box entry; see DepthCtx).
 template <int W, class Stack, class Visit>
-__device__ __forceinline__ int walk(const WideNode<W>* __restrict__ nodes, const RayF& rf,
-                                    float& tcut, Stack& stk, int64_t max_steps,
+__device__ __forceinline__ int walk(const WideNode<W>* __restrict__ nodes, const Ray& rf,
+                                    float& tcut, float slack, Stack& stk, int64_t max_steps,
                                     uint32_t& n_nodes, uint32_t& n_prims, Visit&& visit)
 {
     int sp = 0;
@@ -57,7 +59,7 @@ __device__ __forceinline__ int walk(const WideNode<W>* __restrict__ nodes, const
             NodeBuf<W> b;
             load_node<W>(nodes, node, b);
             uint32_t key[W];
-            slab_keys<W>(b, rf, tcut, key);
+            slab_keys<W>(b, rf, tcut + slack, key);
             sort_keys<W>(key);
             int nh = 0;
 #pragma unroll
@@ -93,92 +95,177 @@ __device__ __forceinline__ float cut_after(float t)
     return t + fabsf(t) * 0x1p-20f + 1e-30f;
 }
 
-// Forward resolution of N samples in one walk (eqns "rr", "cloest",
-// "multisample"): sample k keeps the smallest (t, gid) key among the valid
-// candidates its Philox number accepts.
+// Depth of a candidate (Sec. 3.1, Sec. 4.1). Mode 0: the mean t* of the 1D
+// Gaussian along the ray. Mode 1: the centre projected onto a viewing axis a,
+// as the ray parameter of the same depth along a, t = ((mu - o) . a) / (d . a)
+// (a = the ray's direction when none is given); the opacity stays at the 1D
+// peak. Because x(t*) lies in the bounding sphere of radius r about mu,
+// |t - t*| <= r / (d . a_hat), so boxes are culled against the cut plus that
+// slack (r = the largest radius in the scene).
+struct DepthCtx {
+    int mode;         // uniform
+    bool own_axis;    // uniform: the axis is each ray's direction
+    float ax, ay, az; // uniform axis (when !own_axis)
+    double inv_den;   // per ray: 1 / (d . a)
+    float node_slack; // per ray
+};
+
+__device__ __forceinline__ DepthCtx make_depth(int mode, const float axis[3], const Ray& ray,
+                                               float r_max)
+{
+    DepthCtx c;
+    c.mode = mode;
+    c.own_axis = axis[0] == 0.0f && axis[1] == 0.0f && axis[2] == 0.0f;
+    c.ax = axis[0];
+    c.ay = axis[1];
+    c.az = axis[2];
+    c.node_slack = 0.0f;
+    c.inv_den = 0.0;
+    if (mode != 0) {
+        double den, alen;
+        if (c.own_axis) {
+            den = (double)ray.dx * ray.dx + (double)ray.dy * ray.dy + (double)ray.dz * ray.dz;
+            alen = sqrt(den);
+        } else {
+            den = (double)ray.dx * c.ax + (double)ray.dy * c.ay + (double)ray.dz * c.az;
+            alen = sqrt((double)c.ax * c.ax + (double)c.ay * c.ay + (double)c.az * c.az);
+        }
+        c.inv_den = 1.0 / den;
+        const double cosd = den / alen;  // d . a_hat
+        c.node_slack = cosd > 0.0 ? (float)((double)r_max * (1.0 + 0x1p-12) / cosd) * 1.0001f
+                                  : INFINITY;
+    }
+    return c;
+}
+
+__device__ __forceinline__ double depth_of(const DepthCtx& c, const Record& r, const Ray& ray,
+                                           double t_mean)
+{
+    if (c.mode == 0) return t_mean;
+    const double wx = (double)r.mu[0] - (double)ray.ox;
+    const double wy = (double)r.mu[1] - (double)ray.oy;
+    const double wz = (double)r.mu[2] - (double)ray.oz;
+    const double num = c.own_axis ? wx * ray.dx + wy * ray.dy + wz * ray.dz
+                                  : wx * c.ax + wy * c.ay + wz * c.az;
+    return num * c.inv_den;
+}
+
+// Forward resolution state of N samples sharing one walk (eqns "rr",
+// "cloest", "multisample"): sample k keeps the smallest (t, gid) key among
+// the valid candidates its Philox number accepts; (wt, wg) is the largest of
+// the N keys and tcut the depth cut it implies.
+template <int N>
+struct FwdSamples {
+    float bt[N];
+    int32_t bg[N];
+    float wt, tcut, tmax_f;
+    int32_t wg;
+    int n_act;
+
+    __device__ __forceinline__ void reset(int n, float tmax)
+    {
+        n_act = n;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            bt[k] = k < n ? INFINITY : -INFINITY;
+            bg[k] = 0x7FFFFFFF;
+        }
+        tmax_f = tmax;
+        tcut = tmax;
+        wt = INFINITY;
+        wg = 0x7FFFFFFF;
+    }
+};
+
 struct ForwardCtx {
     const Record* recs;
     uint32_t purpose, k0, k1;
 };
 
-template <int W, int N, bool ANY, class Stack>
-__device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ nodes,
-                                               const ForwardCtx& fc, const RayF& rf,
-                                               const RayD& rd, double tmin, double tmax,
-                                               int32_t ign, uint32_t rid, uint32_t s0, int n_act,
-                                               Stack& stk, int64_t max_steps, float (&bt)[N],
-                                               int32_t (&bg)[N], uint32_t& n_nodes,
-                                               uint32_t& n_prims, uint32_t& n_cands,
-                                               uint32_t& n_philox)
+struct FwdCounts {
+    uint32_t cands = 0, philox = 0;
+};
+
+// Offer record r to the samples; true when an any-hit walk may stop.
+template <int N, bool ANY>
+__device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, const Ray& ray,
+                                          const DepthCtx& dc, double tmin, double tmax,
+                                          int32_t ign, uint32_t rid, uint32_t s0,
+                                          const ForwardCtx& fc, FwdCounts& cnt)
 {
+    if (dc.mode == 0) {
+        if (sphere_reject(r, ray, ray.tmin, st.tcut)) return false;
+    } else if (sphere_reject(r, ray, -INFINITY, INFINITY)) {
+        return false;
+    }
+    double tm, q;
+    isect_tq(r, ray, tm, q);
+    const double t = depth_of(dc, r, ray, tm);
+    if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
+    ++cnt.cands;
+    const float t32 = (float)t;
+    if (!key_less(t32, r.gid, st.wt, st.wg)) return false;
+    const double alpha = (double)r.opacity * exp(-0.5 * q);
+    uint4 w = make_uint4(0, 0, 0, 0);
+    uint32_t grp = 0xFFFFFFFFu;
+    bool changed = false;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        bt[k] = k < n_act ? INFINITY : -INFINITY;
-        bg[k] = 0x7FFFFFFF;
-    }
-    const float tmax_f = (float)tmax;
-    float tcut = tmax_f;
-    float wt = INFINITY;
-    int32_t wg = 0x7FFFFFFF;
-    const RayS rs = make_rays((float)rd.dx, (float)rd.dy, (float)rd.dz);
-    auto visit = [&](uint32_t ri) -> bool {
-        const Record r = load_record(fc.recs, ri);
-        if (sphere_reject(r, rf, rs, rf.tmin, tcut)) return false;
-        double t, q;
-        isect_tq(r, rd, t, q);
-        if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
-        ++n_cands;
-        const float t32 = (float)t;
-        if (!key_less(t32, r.gid, wt, wg)) return false;
-        const double alpha = (double)r.opacity * exp(-0.5 * q);
-        uint4 w = make_uint4(0, 0, 0, 0);
-        uint32_t grp = 0xFFFFFFFFu;
-        bool changed = false;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            if (k < n_act && key_less(t32, r.gid, bt[k], bg[k])) {
-                const uint32_t s = s0 + (uint32_t)k;
-                if ((s >> 2) != grp) {
-                    grp = s >> 2;
-                    w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, fc.purpose), fc.k0,
-                                      fc.k1);
-                    ++n_philox;
-                }
-                if (u_of_word(word_of(w, s & 3u)) < alpha) {
-                    bt[k] = t32;
-                    bg[k] = r.gid;
-                    changed = true;
-                }
+        if (k < st.n_act && key_less(t32, r.gid, st.bt[k], st.bg[k])) {
+            const uint32_t s = s0 + (uint32_t)k;
+            if ((s >> 2) != grp) {
+                grp = s >> 2;
+                w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, fc.purpose), fc.k0, fc.k1);
+                ++cnt.philox;
+            }
+            if (u_of_word(word_of(w, s & 3u)) < alpha) {
+                st.bt[k] = t32;
+                st.bg[k] = r.gid;
+                changed = true;
             }
         }
-        if (!changed) return false;
-        if (ANY) return true;
-        wt = -INFINITY;
-        wg = (int32_t)0x80000000;
+    }
+    if (!changed) return false;
+    if (ANY) return true;
+    st.wt = -INFINITY;
+    st.wg = (int32_t)0x80000000;
 #pragma unroll
-        for (int k = 0; k < N; ++k)
-            if (k < n_act && key_less(wt, wg, bt[k], bg[k])) {
-                wt = bt[k];
-                wg = bg[k];
-            }
-        tcut = fminf(cut_after(wt), tmax_f);
-        return false;
-    };
-    return walk<W>(nodes, rf, tcut, stk, max_steps, n_nodes, n_prims, visit);
+    for (int k = 0; k < N; ++k)
+        if (k < st.n_act && key_less(st.wt, st.wg, st.bt[k], st.bg[k])) {
+            st.wt = st.bt[k];
+            st.wg = st.bg[k];
+        }
+    st.tcut = fminf(cut_after(st.wt), st.tmax_f);
+    return false;
 }
 
-__device__ __forceinline__ RayF make_rayf(float ox, float oy, float oz, float dx, float dy,
-                                          float dz, float tmin)
+template <int W, int N, bool ANY, class Stack>
+__device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ nodes,
+                                               const ForwardCtx& fc, const DepthCtx& dc,
+                                               const Ray& ray, double tmin,
+                                               double tmax, int32_t ign, uint32_t rid, uint32_t s0,
+                                               int n_act, Stack& stk, int64_t max_steps,
+                                               float (&bt)[N], int32_t (&bg)[N],
+                                               uint32_t& n_nodes, uint32_t& n_prims,
+                                               uint32_t& n_cands, uint32_t& n_philox)
 {
-    RayF rf;
-    rf.ox = ox;
-    rf.oy = oy;
-    rf.oz = oz;
-    rf.ix = safe_inv(dx);
-    rf.iy = safe_inv(dy);
-    rf.iz = safe_inv(dz);
-    rf.tmin = tmin;
-    return rf;
+    FwdSamples<N> st;
+    st.reset(n_act, (float)tmax);
+    FwdCounts fcnt;
+    auto visit = [&](uint32_t ri) -> bool {
+        const Record r = load_record(fc.recs, ri);
+        return fwd_offer<N, ANY>(st, r, ray, dc, tmin, tmax, ign, rid, s0, fc, fcnt);
+    };
+    const int res = walk<W>(nodes, ray, st.tcut, dc.node_slack, stk, max_steps, n_nodes, n_prims,
+                            visit);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        bt[k] = st.bt[k];
+        bg[k] = st.bg[k];
+    }
+    n_cands += fcnt.cands;
+    n_philox += fcnt.philox;
+    return res;
 }
 
 }  // namespace srt

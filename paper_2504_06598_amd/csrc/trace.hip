@@ -57,6 +57,9 @@ struct TraceArgs {
     int32_t deep_cap;
     int64_t max_steps;  // bound on loop iterations of one traversal (a tree visits
                         // each node once); exceeding it marks the ray as lost
+    int32_t depth_mode;
+    float depth_axis[3];
+    float r_max;
 };
 
 struct Counts {
@@ -78,13 +81,14 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
     const uint32_t sbase = (a.sid ? a.sid[ray] : 0u) + a.soff;
     const bool live = tmax_f > tmin_f;
 
-    const RayF rf = make_rayf(ox, oy, oz, dx, dy, dz, tmin_f);
-    const RayD rd{ox, oy, oz, dx, dy, dz};
+    const Ray rd = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
     const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
+    const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rd, a.r_max);
     const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
     FlatStack stack{stk, stride, cap};
 
     const bool shade = a.rgb != nullptr && !ANY;
+    uint32_t samples = 0;  // counted once the whole ray has completed
     float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
     for (int pass = 0; pass * N < a.spp; ++pass) {
         const int n_act = min(N, a.spp - pass * N);
@@ -93,11 +97,11 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
         if (live) {
             ++cnt.trav;
             const int res = resolve_samples<W, N, ANY>(
-                nodes, fc, rf, rd, (double)tmin_f, (double)tmax_f, ign, rid,
+                nodes, fc, dc, rd, (double)tmin_f, (double)tmax_f, ign, rid,
                 sbase + (uint32_t)(pass * N), n_act, stack, a.max_steps, bt, bgid, cnt.nodes,
                 cnt.prims, cnt.cands, cnt.philox);
             if (res == kWalkOverflow) return false;
-            cnt.samples += (uint32_t)n_act;
+            samples += (uint32_t)n_act;
         } else {
 #pragma unroll
             for (int k = 0; k < N; ++k) {
@@ -108,8 +112,9 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
         // the SH basis is formed after the traversal so it is not live during it
         float Y[16];
         if (shade) {
-            const float n = sqrtf(dx * dx + dy * dy + dz * dz);
-            sh_eval(a.deg, dx / n, dy / n, dz / n, Y);
+            const float ex = opaque(dx), ey = opaque(dy), ez = opaque(dz);
+            const float n = sqrtf(ex * ex + ey * ey + ez * ez);
+            sh_eval(a.deg, ex / n, ey / n, ez / n, Y);
         }
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -137,10 +142,13 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
         a.rgb[3 * ray + 1] = acc1 * inv;
         a.rgb[3 * ray + 2] = acc2 * inv;
     }
+    cnt.samples += samples;
     return true;
 }
 
-template <int W, int N, bool ANY, bool DEEP>
+// COUNT: accumulate the statistics counters (a launch without a counters
+// buffer compiles them away, which frees their registers).
+template <int W, int N, bool ANY, bool DEEP, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
 {
     __shared__ int32_t lds[DEEP ? 1 : LdsStack<W>::value * kBlock];
@@ -174,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
             a.ovf_list[slot] = (uint32_t)gt;
         }
     }
-    if (a.counters) {
+    if (COUNT && a.counters) {
         // every lane of the wave reaches this point (no early return above)
         wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, cnt.trav);
         wave_add_u64(a.counters + SRT_CNT_NODES, cnt.nodes);
@@ -190,35 +198,35 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
 using KernelFn = void (*)(TraceArgs);
 
 template <int W, int N, bool ANY>
-void pick(KernelFn* fast, KernelFn* deep)
+void pick(bool count, KernelFn* fast, KernelFn* deep)
 {
-    *fast = k_trace<W, N, ANY, false>;
-    *deep = k_trace<W, N, ANY, true>;
+    *fast = count ? k_trace<W, N, ANY, false, true> : k_trace<W, N, ANY, false, false>;
+    *deep = count ? k_trace<W, N, ANY, true, true> : k_trace<W, N, ANY, true, false>;
 }
 
 template <int W>
-bool pick_w(int N, bool any, KernelFn* f, KernelFn* d)
+bool pick_w(int N, bool any, bool count, KernelFn* f, KernelFn* d)
 {
     if (any) {
         if (N != 1) return false;
-        pick<W, 1, true>(f, d);
+        pick<W, 1, true>(count, f, d);
         return true;
     }
     switch (N) {
-    case 1: pick<W, 1, false>(f, d); return true;
-    case 2: pick<W, 2, false>(f, d); return true;
-    case 4: pick<W, 4, false>(f, d); return true;
-    case 8: pick<W, 8, false>(f, d); return true;
+    case 1: pick<W, 1, false>(count, f, d); return true;
+    case 2: pick<W, 2, false>(count, f, d); return true;
+    case 4: pick<W, 4, false>(count, f, d); return true;
+    case 8: pick<W, 8, false>(count, f, d); return true;
     }
     return false;
 }
 
-bool pick_kernels(int W, int N, bool any, KernelFn* f, KernelFn* d)
+bool pick_kernels(int W, int N, bool any, bool count, KernelFn* f, KernelFn* d)
 {
     switch (W) {
-    case 2: return pick_w<2>(N, any, f, d);
-    case 4: return pick_w<4>(N, any, f, d);
-    case 8: return pick_w<8>(N, any, f, d);
+    case 2: return pick_w<2>(N, any, count, f, d);
+    case 4: return pick_w<4>(N, any, count, f, d);
+    case 8: return pick_w<8>(N, any, count, f, d);
     }
     return false;
 }
@@ -231,6 +239,7 @@ srt_status validate_opts(const srt_trace_opts* o)
     if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
     if (o->any_hit && N != 1) return SRT_ERR_INVALID_ARG;
     if (o->stack_limit < 0) return SRT_ERR_INVALID_ARG;
+    if (o->depth_mode != 0 && o->depth_mode != 1) return SRT_ERR_INVALID_ARG;
     return SRT_OK;
 }
 
@@ -240,7 +249,7 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
                         void* workspace, hipStream_t s)
 {
     KernelFn fast = nullptr, deep = nullptr;
-    if (!pick_kernels(b->W, o->n_per_traversal, o->any_hit != 0, &fast, &deep))
+    if (!pick_kernels(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr, &fast, &deep))
         return SRT_ERR_UNSUPPORTED;
     const TraceWorkspace ws = trace_workspace(b, rays->count, workspace);
     TraceArgs a{};
@@ -272,6 +281,9 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
     a.deep_stack = ws.deep_stack;
     a.deep_cap = deep_stack_cap(b);
     a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
+    a.depth_mode = o->depth_mode;
+    for (int i = 0; i < 3; ++i) a.depth_axis[i] = o->depth_axis[i];
+    a.r_max = b->r_max;
     fill_u32(ws.ctrl, 0u, 2, s);
     if (rays->count > 0) {
         const unsigned grid = (unsigned)((rays->count + kBlock - 1) / kBlock);

@@ -174,3 +174,28 @@ def test_estimator_is_unbiased_for_the_exact_gradient(srt):
             if checked == 3:
                 break
         assert checked >= 1, n
+
+
+def test_backward_center_depth_matches_oracle(srt):
+    say("backward with centre depth vs oracle estimator")
+    sc = tiny_scene(51, 800, (0.03, 0.1), deg=1)
+    cam = si.look_at((0.1, 0.2, 3), (0, 0, 0), 32, 32)
+    o, d = si.camera_rays(cam)
+    ax = tuple(float(x) for x in cam.forward)
+    rec = oracle.Records(sc)
+    with oracle.depth_mode(1, np.asarray(ax, np.float64)):
+        ora_f = oracle.trace(rec, oracle.Rays(o, d), spp=4, seed=5)
+        dL = np.random.default_rng(8).normal(0, 1, (len(o), 3))
+        dL[(ora_f["flags"] != 0).any(1)] = 0.0
+        ora = oracle.estimator_grad(rec, oracle.Rays(o, d), dL.astype(np.float32).astype(np.float64),
+                                    spp=4, seed=5)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
+    oc, dc = _cu(o), _cu(d)
+    fw = srt.srt_trace_forward(bvh, oc, dc, seed=5, spp=4, n_per_traversal=4, depth_mode=1,
+                               depth_axis=ax)
+    g = srt.srt_trace_backward(bvh, oc, dc, _cu(dL.astype(np.float32)), hit_gid=fw["hit_gid"],
+                               hit_t=fw["hit_t"], seed=5, spp=4, n_per_traversal=4,
+                               depth_mode=1, depth_axis=ax)
+    torch.cuda.synchronize()
+    for name in NAMES:
+        _close(to_np(g[name]).reshape(ora[name].shape), ora[name], name)

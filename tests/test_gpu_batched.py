@@ -151,6 +151,7 @@ def test_deep_stack_and_widths(srt, setup):
             _, hits, cnt = _run(plan)
             assert np.array_equal(hits, ref_hits)
             assert cnt[5] > 0 and cnt[7] == 0
+            assert cnt[6] == plan.samples  # rerun rays and items are counted once
     for W, L in [(2, 1), (8, 8), (8, 2)]:
         bvh = srt.srt_build_bvh(s["dsc"], W, L)
         plan = _plan(srt, s, bvh=bvh, persistent=True)

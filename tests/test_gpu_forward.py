@@ -190,7 +190,8 @@ def test_deep_stack_fallback_is_exact(srt, tmp_path):
         g = _trace(srt, bvh, o, d, seed=1, spp=2, n_per_traversal=2, stack_limit=lim,
                    counters=cnt)
         c = srt.counters_dict(cnt)
-        assert c["deep"] > 0
+        assert c["deep"] > 0 and c["lost"] == 0
+        assert c["ray_samples"] == len(o) * 2  # a rerun ray is counted once
         assert np.array_equal(g["hit_gid"], base["hit_gid"])
         np.testing.assert_array_equal(g["rgb"], base["rgb"])
 
@@ -317,3 +318,25 @@ def test_counters(srt):
     assert c["nodes"] >= c["traversals"]
     assert c["prims"] >= c["candidates"] > 0
     assert c["philox"] > 0 and c["deep"] == 0 and c["lost"] == 0
+
+
+@pytest.mark.parametrize("axis", ["camera", "ray"])
+def test_center_depth_matches_oracle(srt, axis):
+    """Centre depth (Sec. 4.1): order and range-test by the centre projected
+    onto the camera axis (or each ray's direction), alpha at the 1D peak."""
+    say(f"centre depth, axis = {axis}")
+    sc = tiny_scene(41, 2500, (0.02, 0.12), deg=1)
+    cam = si.look_at((0.4, 0.3, 2.7), (0, 0, 0), 48, 40)
+    o, d = si.camera_rays(cam)
+    ax = tuple(float(x) for x in cam.forward) if axis == "camera" else (0.0, 0.0, 0.0)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
+    g = _trace(srt, bvh, o, d, seed=8, spp=8, n_per_traversal=4, depth_mode=1, depth_axis=ax)
+    with oracle.depth_mode(1, np.asarray(ax, np.float64)):
+        ora = oracle.trace(oracle.Records(sc), oracle.Rays(o, d), spp=8, seed=8)
+    compare_ids(g["hit_gid"], ora["hit_gid"], ora["flags"])
+    compare_rgb(g["rgb"], ora["rgb"], ora["flags"])
+    same = (g["hit_gid"] == ora["hit_gid"]) & (ora["hit_gid"] >= 0)
+    assert _ulps(g["hit_t"][same], ora["hit_t"][same]).max() <= 1
+    # the centre depth changes results compared with the mean depth
+    g0 = _trace(srt, bvh, o, d, seed=8, spp=8, n_per_traversal=4)
+    assert (g0["hit_gid"] != g["hit_gid"]).mean() > 0.01

@@ -543,3 +543,35 @@ def test_pathmix_shadow_occlusion_probability():
     cand = oracle.candidates(rec, P, (v / ln).astype(F32), tmin=float(F32(1e-4)), tmax=float(ln))
     assert cand["gid"].tolist() == [0]
     assert binomtest(occl, n, float(cand["alpha"][0])).pvalue > 1e-4
+
+
+# --------------------------------------------------------------------------
+# Centre depth (Sec. 4.1)
+# --------------------------------------------------------------------------
+def test_center_depth_orders_by_projected_centre():
+    """Two Gaussians whose 1D means and projected centres order differently:
+    an elongated, tilted front Gaussian whose mean along the ray lies behind a
+    round one, while its centre projects in front of it."""
+    s = math.sqrt(0.5)
+    q_tilt = [math.cos(math.pi / 8), 0.0, math.sin(math.pi / 8), 0.0]  # 45 deg about y
+    sc = _scene([[0.3, 0.0, 1.9], [0.0, 0.0, 2.0]], np.log([[0.6, 0.05, 0.05], [0.1, 0.1, 0.1]]),
+                [q_tilt, [1, 0, 0, 0]], [_logit(0.9), _logit(0.9)])
+    rec = oracle.Records(sc, round_f32=False)
+    o, d = [0, 0, 0], [0, 0, 1]
+    c_mean = oracle.candidates(rec, o, d)
+    assert list(c_mean["gid"]) == [1, 0], c_mean
+    with oracle.depth_mode(1):
+        c_ctr = oracle.candidates(rec, o, d)
+    assert list(c_ctr["gid"]) == [0, 1]
+    np.testing.assert_allclose(c_ctr["t"], [np.float32(1.9), 2.0], rtol=1e-7)
+    # alpha stays at the 1D peak: identical in both modes
+    np.testing.assert_allclose(sorted(c_ctr["alpha"]), sorted(c_mean["alpha"]), rtol=1e-15)
+    # with a viewing axis, the depth is the centre's depth along it converted
+    # to the ray parameter
+    axis = np.array([0.0, 0.6, 0.8])
+    d2 = np.array([0.0, 0.05, 1.0], np.float32)
+    with oracle.depth_mode(1, axis):
+        c_ax = oracle.candidates(rec, o, d2)
+    for g, t in zip(c_ax["gid"], c_ax["t"]):
+        mu = rec.mu[g]
+        assert abs(t - (mu @ axis) / (d2.astype(np.float64) @ axis)) < 1e-12
