@@ -117,7 +117,7 @@ __device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, con
     }
 }
 
-template <int W, int N>
+template <int W, int N, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
 {
     __shared__ int32_t lds[kLdsEntries * kBlock];
@@ -162,10 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
             const double tmin = tmin_f, tmax = tmax_f;
             const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rr, a.r_max);
             float Y[16];
-            {
-                const float n = sqrtf(dx * dx + dy * dy + dz * dz);
-                sh_eval(a.deg, dx / n, dy / n, dz / n, Y);
-            }
+            sh_eval(a.deg, dx * rr.inv_len, dy * rr.inv_len, dz * rr.inv_len, Y);
             for (int pass = 0; pass * N < a.spp; ++pass) {
                 const int n_act = min(N, a.spp - pass * N);
                 float ta[N];
@@ -195,25 +192,26 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                         continue;
                     }
                 }
-                // colour of each sample's result (X) and the farthest result key
-                float X[N][3];
+                // <g, X> of each sample's result colour X (bg on a miss), and the
+                // farthest result key; only these scalars are live during the walk
+                float gx[N];
                 float wt = -INFINITY;
                 int32_t wg = INT_MIN;
+                {
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    if (k >= n_act) {
-                        X[k][0] = X[k][1] = X[k][2] = 0.0f;
-                        continue;
-                    }
-                    if (ga[k] != 0x7FFFFFFF) {
-                        const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, ga[k], Y));
-                        X[k][0] = c.x; X[k][1] = c.y; X[k][2] = c.z;
-                    } else {
-                        X[k][0] = a.bg[0]; X[k][1] = a.bg[1]; X[k][2] = a.bg[2];
-                    }
-                    if (key_less(wt, wg, ta[k], ga[k])) {
-                        wt = ta[k];
-                        wg = ga[k];
+                    for (int k = 0; k < N; ++k) {
+                        gx[k] = 0.0f;
+                        if (k >= n_act) continue;
+                        if (ga[k] != 0x7FFFFFFF) {
+                            const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, ga[k], Y));
+                            gx[k] = g0 * c.x + g1 * c.y + g2 * c.z;
+                        } else {
+                            gx[k] = g0 * a.bg[0] + g1 * a.bg[1] + g2 * a.bg[2];
+                        }
+                        if (key_less(wt, wg, ta[k], ga[k])) {
+                            wt = ta[k];
+                            wg = ga[k];
+                        }
                     }
                 }
                 n_samples += (uint32_t)n_act;
@@ -231,22 +229,19 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     const float t32 = (float)t;
                     if (!key_less(t32, r.gid, wt, wg)) return false;
                     int nf = 0;
-                    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+                    float xs = 0.0f;
 #pragma unroll
                     for (int k = 0; k < N; ++k)
                         if (k < n_act && key_less(t32, r.gid, ta[k], ga[k])) {
                             ++nf;
-                            x0 += X[k][0];
-                            x1 += X[k][1];
-                            x2 += X[k][2];
+                            xs += gx[k];
                         }
                     if (nf == 0) return false;
                     ++n_front;
                     const float alpha = (float)((double)r.opacity * exp(-0.5 * q));
                     const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, r.gid, Y));
-                    const float fn = (float)nf;
-                    const float s_alpha = (g0 * (fn * c.x - x0) + g1 * (fn * c.y - x1) +
-                                           g2 * (fn * c.z - x2)) * inv_spp / (1.0f - alpha);
+                    const float gc = g0 * c.x + g1 * c.y + g2 * c.z;
+                    const float s_alpha = ((float)nf * gc - xs) * inv_spp / (1.0f - alpha);
                     const float sa = s_alpha * alpha;
                     const float p0 = (float)p[0], p1 = (float)p[1], p2 = (float)p[2];
                     const float v[kAccVals] = {sa,           sa * p0,      sa * p1,
@@ -298,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
         }
         __syncthreads();
     }
-    if (a.counters) {
+    if (COUNT && a.counters) {
         wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, n_trav);
         wave_add_u64(a.counters + SRT_CNT_NODES, n_nodes);
         wave_add_u64(a.counters + SRT_CNT_PRIMS, n_prims);
@@ -368,24 +363,24 @@ __global__ void k_chain(int64_t G, const float* __restrict__ acc, const float* _
 
 using BwdFn = void (*)(BwdArgs);
 
-template <int W>
+template <int W, bool C>
 BwdFn pick_n(int N)
 {
     switch (N) {
-    case 1: return k_backward<W, 1>;
-    case 2: return k_backward<W, 2>;
-    case 4: return k_backward<W, 4>;
-    case 8: return k_backward<W, 8>;
+    case 1: return k_backward<W, 1, C>;
+    case 2: return k_backward<W, 2, C>;
+    case 4: return k_backward<W, 4, C>;
+    case 8: return k_backward<W, 8, C>;
     }
     return nullptr;
 }
 
-BwdFn pick(int W, int N)
+BwdFn pick(int W, int N, bool count)
 {
     switch (W) {
-    case 2: return pick_n<2>(N);
-    case 4: return pick_n<4>(N);
-    case 8: return pick_n<8>(N);
+    case 2: return count ? pick_n<2, true>(N) : pick_n<2, false>(N);
+    case 4: return count ? pick_n<4, true>(N) : pick_n<4, false>(N);
+    case 8: return count ? pick_n<8, true>(N) : pick_n<8, false>(N);
     }
     return nullptr;
 }
@@ -483,7 +478,7 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     a.depth_mode = opts->depth_mode;
     for (int i = 0; i < 3; ++i) a.depth_axis[i] = opts->depth_axis[i];
     a.r_max = b->r_max;
-    BwdFn fn = pick(b->W, N);
+    BwdFn fn = pick(b->W, N, counters != nullptr);
     if (!fn) return SRT_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(fn, dim3(ws.threads / kBlock), dim3(kBlock), 0, s, a);
     SRT_HIP_TRY(hipGetLastError());

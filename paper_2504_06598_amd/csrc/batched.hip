@@ -227,10 +227,11 @@ __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int 
     return true;
 }
 
+template <bool COUNT>
 __device__ __forceinline__ void flush_counts(const BatchArgs& a, const LaneCounts& c, uint32_t deep,
                                              uint32_t lost)
 {
-    if (!a.counters) return;
+    if (!COUNT || !a.counters) return;
     wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, c.trav);
     wave_add_u64(a.counters + SRT_CNT_NODES, c.nodes);
     wave_add_u64(a.counters + SRT_CNT_PRIMS, c.prims);
@@ -244,7 +245,7 @@ __device__ __forceinline__ void flush_counts(const BatchArgs& a, const LaneCount
 // ---------------------------------------------------------------------------
 // Plain: one lane per ray.
 // ---------------------------------------------------------------------------
-template <int W, int N>
+template <int W, int N, bool COUNT>
 __global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
 {
     __shared__ int32_t lds[32 * kPlainBlock];
@@ -271,11 +272,11 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
             }
         }
     }
-    flush_counts(a, cnt, 0, 0);
+    flush_counts<COUNT>(a, cnt, 0, 0);
 }
 
 // Plain deep pass: queued rays with the global-memory stack.
-template <int W, int N>
+template <int W, int N, bool COUNT>
 __global__ __launch_bounds__(kPlainBlock) void k_plain_deep(BatchArgs a)
 {
     const int64_t gt = blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_deep(BatchArgs a)
         a.rgb[3 * b.row + 1] = acc[1] * w;
         a.rgb[3 * b.row + 2] = acc[2] * w;
     }
-    flush_counts(a, cnt, deep, lost);
+    flush_counts<COUNT>(a, cnt, deep, lost);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +329,7 @@ __device__ __forceinline__ void decode_item(const BatchArgs& a, int64_t item, in
     }
 }
 
-template <int W, int N>
+template <int W, int N, bool COUNT>
 __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
 {
     __shared__ int32_t lds[32 * kPersistBlock];
@@ -470,11 +471,11 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
             active = false;
         }
     }
-    flush_counts(a, cnt, 0, 0);
+    flush_counts<COUNT>(a, cnt, 0, 0);
 }
 
 // Persistent deep pass: queued items with the global-memory stack.
-template <int W, int N>
+template <int W, int N, bool COUNT>
 __global__ __launch_bounds__(kPlainBlock) void k_persistent_deep(BatchArgs a)
 {
     const int64_t gt = blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
@@ -493,7 +494,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_persistent_deep(BatchArgs a)
             atomicAdd(&a.ctrl[1], 1u);
         }
     }
-    flush_counts(a, cnt, deep, lost);
+    flush_counts<COUNT>(a, cnt, deep, lost);
 }
 
 __global__ void k_zero_f32(float* p, int64_t n)
@@ -514,24 +515,33 @@ __global__ void k_reset(unsigned long long* work, uint32_t* ctrl)
 
 using BatchFn = void (*)(BatchArgs);
 
-template <int W>
+template <int W, int N, bool C>
+void pick4(BatchFn k[4])
+{
+    k[0] = k_plain<W, N, C>;
+    k[1] = k_plain_deep<W, N, C>;
+    k[2] = k_persistent<W, N, C>;
+    k[3] = k_persistent_deep<W, N, C>;
+}
+
+template <int W, bool C>
 bool pick_w(int N, BatchFn k[4])
 {
     switch (N) {
-    case 1: k[0] = k_plain<W, 1>; k[1] = k_plain_deep<W, 1>; k[2] = k_persistent<W, 1>; k[3] = k_persistent_deep<W, 1>; return true;
-    case 2: k[0] = k_plain<W, 2>; k[1] = k_plain_deep<W, 2>; k[2] = k_persistent<W, 2>; k[3] = k_persistent_deep<W, 2>; return true;
-    case 4: k[0] = k_plain<W, 4>; k[1] = k_plain_deep<W, 4>; k[2] = k_persistent<W, 4>; k[3] = k_persistent_deep<W, 4>; return true;
-    case 8: k[0] = k_plain<W, 8>; k[1] = k_plain_deep<W, 8>; k[2] = k_persistent<W, 8>; k[3] = k_persistent_deep<W, 8>; return true;
+    case 1: pick4<W, 1, C>(k); return true;
+    case 2: pick4<W, 2, C>(k); return true;
+    case 4: pick4<W, 4, C>(k); return true;
+    case 8: pick4<W, 8, C>(k); return true;
     }
     return false;
 }
 
-bool pick(int W, int N, BatchFn k[4])
+bool pick(int W, int N, bool count, BatchFn k[4])
 {
     switch (W) {
-    case 2: return pick_w<2>(N, k);
-    case 4: return pick_w<4>(N, k);
-    case 8: return pick_w<8>(N, k);
+    case 2: return count ? pick_w<2, true>(N, k) : pick_w<2, false>(N, k);
+    case 4: return count ? pick_w<4, true>(N, k) : pick_w<4, false>(N, k);
+    case 8: return count ? pick_w<8, true>(N, k) : pick_w<8, false>(N, k);
     }
     return false;
 }
@@ -580,7 +590,7 @@ srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* count
 {
     const srt_bvh* b = p->bvh;
     BatchFn k[4];
-    if (!pick(b->W, p->opts.n_per_traversal, k)) return SRT_ERR_UNSUPPORTED;
+    if (!pick(b->W, p->opts.n_per_traversal, counters != nullptr, k)) return SRT_ERR_UNSUPPORTED;
     BatchArgs a{};
     a.nodes = b->nodes;
     a.recs = b->recs;
