@@ -136,14 +136,16 @@ def main():
             bws = torch.empty(L.srt_backward_workspace_size(bvh.handle, Rb), dtype=torch.uint8,
                               device=dev)
         srt.srt_trace_forward(bvh, vo, vd, seed=si.PHILOX_SEED, spp=bspp, n_per_traversal=bspp,
-                              sample_offset=k * bspp, counters=cnt, out=bout, workspace=fws)
+                              sample_offset=k * bspp, image_width=views[0].width, counters=cnt,
+                              out=bout, workspace=fws)
         grad_rgb = (bout["rgb"] - target) * (2.0 / Rb)
         for g in grads.values():
             g.zero_()
         srt.srt_trace_backward(bvh, vo, vd, grad_rgb, hit_gid=bout["hit_gid"],
                                hit_t=bout["hit_t"], seed=si.PHILOX_SEED, spp=bspp,
-                               n_per_traversal=bspp, sample_offset=k * bspp, grads=grads,
-                               counters=bcnt, workspace=bws)
+                               n_per_traversal=bspp, sample_offset=k * bspp,
+                               image_width=views[0].width, grads=grads, counters=bcnt,
+                               workspace=bws)
         return bvh
 
     for k in range(args.warmup):
@@ -190,7 +192,8 @@ def main():
 
     def cam_trace(cnt):
         srt.srt_trace_forward(bvh, o, d, seed=si.PHILOX_SEED, spp=spp, n_per_traversal=N,
-                              want_hits=False, counters=cnt, out=trace_out, workspace=tws)
+                              image_width=cam.width, want_hits=False, counters=cnt,
+                              out=trace_out, workspace=tws)
 
     cam_trace(rc)
     torch.cuda.synchronize()
@@ -275,7 +278,7 @@ def profile_kernel(args, srt, si, torch, scene, cam, spp, N, dev):
                       dtype=torch.uint8, device=dev)
     for i in range(3):
         srt.srt_trace_forward(bvh, o, d, seed=si.PHILOX_SEED, spp=spp, n_per_traversal=N,
-                              want_hits=False, out=out, workspace=tws)
+                              image_width=cam.width, want_hits=False, out=out, workspace=tws)
         torch.cuda.synchronize()
         print(f"# dominant kernel launch {i} done", file=sys.stderr, flush=True)
     x = torch.ones(64 << 20, device=dev)  # 256 MiB read, 256 MiB written

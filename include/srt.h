@@ -14,8 +14,8 @@
  *    and keeps them alive until the work on `stream` has finished. Nothing in
  *    this library allocates or frees caller memory.
  *  - All calls are asynchronous on `stream` (a hipStream_t; NULL = the null
- *    stream) except srt_build_bvh and srt_batch_plan_create, which
- *    synchronise `stream` before returning.
+ *    stream) except srt_build_bvh, srt_refit_bvh and srt_batch_plan_create,
+ *    which synchronise `stream` before returning.
  *  - Errors are status codes; nothing throws across the ABI. Arguments are
  *    validated on the host before anything is launched; on an error no work
  *    has been enqueued and outputs are untouched.
@@ -119,6 +119,18 @@ typedef struct {
 srt_status srt_build_bvh(const srt_scene* scene, const srt_build_opts* opts, void* stream,
                          srt_bvh** out);
 
+/* Refit a handle to new parameters of the same Gaussians (an optimisation
+ * step, Sec. 7's differentiable-rendering use): the records and Gaussian
+ * boxes are recomputed from `scene` exactly as srt_build_bvh computes them,
+ * and every node box is refilled bottom-up; the topology and leaf order are
+ * kept. Trace results do not depend on the tree, so they equal those of a
+ * fresh build of `scene` bit for bit; only the traversal cost can grow as
+ * Gaussians move away from their build positions. The handle then references
+ * `scene`'s SH buffer. No work on the handle may be pending; synchronises
+ * `stream`. Errors: INVALID_ARG (null pointers, num_gaussians or sh_degree
+ * different from the build's), HIP. */
+srt_status srt_refit_bvh(srt_bvh* bvh, const srt_scene* scene, void* stream);
+
 /* Free a handle (null is ignored). No work on the handle may be pending. */
 void srt_destroy_bvh(srt_bvh* bvh);
 
@@ -179,7 +191,12 @@ typedef struct {
  *                 the axis, t = ((mu - o) . a) / (d . a) (Sec. 4.1; the
  *                 rasterizer-compatible depth); depth_axis (0,0,0) means each
  *                 ray's own direction. Opacity stays at the 1D peak; the
- *                 range test and the depth key use this depth.             */
+ *                 range test and the depth key use this depth.
+ * image_width     0: rays are independent (lane i traces ray i). > 0: the
+ *                 rays are the pixels of a row-major image of this width
+ *                 (count must be a multiple of it, else SRT_ERR_INVALID_ARG)
+ *                 and each wave traces one 8x8 pixel tile, which keeps its
+ *                 lanes on neighbouring rays. Results do not depend on it.  */
 typedef struct {
     uint64_t seed;
     int32_t spp;
@@ -190,6 +207,7 @@ typedef struct {
     int32_t stack_limit;
     int32_t depth_mode;
     float depth_axis[3];
+    int32_t image_width;
 } srt_trace_opts;
 
 /* Counters accumulated (+=) into a device uint64 array of SRT_NUM_COUNTERS

@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import COUNTER_NAMES, SRT_NUM_COUNTERS, SrtError
 
-__all__ = ["DeviceScene", "Bvh", "BatchPlan", "srt_build_bvh", "srt_trace_forward",
+__all__ = ["DeviceScene", "Bvh", "BatchPlan", "srt_build_bvh", "srt_refit_bvh",
+           "srt_trace_forward",
            "srt_trace_backward", "srt_camera_rays", "srt_trace_pathmix", "srt_batch_plan_create",
            "TraceFn", "render", "counters_dict", "new_counters", "COUNTER_NAMES"]
 
@@ -124,6 +125,15 @@ def srt_build_bvh(scene: DeviceScene, width: int = 4, leaf_size: int = 4,
     return Bvh(h.value, scene)
 
 
+def srt_refit_bvh(bvh: Bvh, scene: DeviceScene) -> Bvh:
+    """Refit `bvh` in place to `scene` (the same Gaussians with new parameter
+    values): records and boxes are recomputed, the topology is kept."""
+    sc = scene.c_struct()
+    _lib.check("srt_refit_bvh", _lib.load().srt_refit_bvh(bvh.handle, C.byref(sc), _stream()))
+    bvh.scene = scene
+    return bvh
+
+
 def new_counters(device="cuda"):
     return torch.zeros(SRT_NUM_COUNTERS, dtype=torch.int64, device=device)
 
@@ -134,8 +144,9 @@ def counters_dict(c):
 
 
 def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode=0,
-          depth_axis=(0.0, 0.0, 0.0)):
+          depth_axis=(0.0, 0.0, 0.0), image_width=0):
     o = _lib.SrtTraceOpts()
+    o.image_width = int(image_width)
     o.depth_mode = int(depth_mode)
     for i in range(3):
         o.depth_axis[i] = float(depth_axis[i])
@@ -153,17 +164,18 @@ def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, d
 def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_gid=None,
                       ray_ids=None, sample_ids=None, purpose=0, seed=0, spp=1,
                       n_per_traversal=1, sample_offset=0, bg=(0.0, 0.0, 0.0), any_hit=False,
-                      stack_limit=0, depth_mode=0, depth_axis=(0.0, 0.0, 0.0), want_rgb=True,
-                      want_hits=True, counters=None, out=None, workspace=None):
+                      stack_limit=0, depth_mode=0, depth_axis=(0.0, 0.0, 0.0), image_width=0,
+                      want_rgb=True, want_hits=True, counters=None, out=None, workspace=None):
     """Trace rays (device tensors [R,3]); returns dict(rgb [R,3], hit_gid [R,spp],
-    hit_t [R,spp])."""
+    hit_t [R,spp]). image_width > 0 declares the rays a row-major image of that
+    width (traced in 8x8 tiles; results are unchanged)."""
     lib = _lib.load()
     R = int(origins.shape[0])
     dev = origins.device
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
     opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode,
-                 depth_axis)
+                 depth_axis, image_width)
     res = dict(out or {})
     if want_rgb and "rgb" not in res:
         res["rgb"] = torch.empty((R, 3), dtype=torch.float32, device=dev)
@@ -182,8 +194,8 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
 def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t=None,
                        tmin=None, tmax=None, ignore_gid=None, ray_ids=None, sample_ids=None,
                        purpose=0, seed=0, spp=1, n_per_traversal=1, sample_offset=0,
-                       bg=(0.0, 0.0, 0.0), depth_mode=0, depth_axis=(0.0, 0.0, 0.0), grads=None,
-                       counters=None, workspace=None):
+                       bg=(0.0, 0.0, 0.0), depth_mode=0, depth_axis=(0.0, 0.0, 0.0),
+                       image_width=0, grads=None, counters=None, workspace=None):
     """Accumulate gradients of sum(grad_rgb * E[rgb]) into `grads` (a dict of
     tensors shaped like the scene's; zeros are allocated when absent)."""
     lib = _lib.load()
@@ -195,7 +207,8 @@ def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t
                  ("means", "log_scales", "quats", "opacity_logits", "sh")}
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
-    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0, depth_mode, depth_axis)
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0, depth_mode, depth_axis,
+                 image_width)
     need = lib.srt_backward_workspace_size(bvh.handle, R)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -220,11 +233,16 @@ class TraceFn(torch.autograd.Function):
         scene = DeviceScene(means.detach().contiguous(), log_scales.detach().contiguous(),
                             quats.detach().contiguous(), opacity_logits.detach().contiguous(),
                             sh.detach().contiguous(), cfg["sh_degree"])
-        bvh = srt_build_bvh(scene, cfg.get("width", 4), cfg.get("leaf_size", 4))
+        bvh = cfg.get("bvh")
+        if bvh is not None:  # a handle kept across optimisation steps: refit it
+            srt_refit_bvh(bvh, scene)
+        else:
+            bvh = srt_build_bvh(scene, cfg.get("width", 4), cfg.get("leaf_size", 4))
         res = srt_trace_forward(bvh, origins, dirs, seed=cfg.get("seed", 0), spp=cfg["spp"],
                                 n_per_traversal=cfg.get("n_per_traversal", 1),
                                 sample_offset=cfg.get("sample_offset", 0),
-                                bg=cfg.get("bg", (0.0, 0.0, 0.0)))
+                                bg=cfg.get("bg", (0.0, 0.0, 0.0)),
+                                image_width=cfg.get("image_width", 0))
         ctx.bvh = bvh
         ctx.cfg = cfg
         ctx.save_for_backward(origins, dirs, res["hit_gid"], res["hit_t"])
@@ -238,14 +256,16 @@ class TraceFn(torch.autograd.Function):
                                hit_t=hit_t, seed=cfg.get("seed", 0), spp=cfg["spp"],
                                n_per_traversal=cfg.get("n_per_traversal", 1),
                                sample_offset=cfg.get("sample_offset", 0),
-                               bg=cfg.get("bg", (0.0, 0.0, 0.0)))
+                               bg=cfg.get("bg", (0.0, 0.0, 0.0)),
+                               image_width=cfg.get("image_width", 0))
         return (g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None, None,
                 None)
 
 
 def render(means, log_scales, quats, opacity_logits, sh, origins, dirs, **cfg):
     """Differentiable stochastic render (see TraceFn); cfg keys: sh_degree, spp,
-    n_per_traversal, seed, sample_offset, bg, width, leaf_size."""
+    n_per_traversal, seed, sample_offset, bg, width, leaf_size, image_width, and bvh
+    (a handle of the same Gaussians to refit instead of building a new one)."""
     return TraceFn.apply(means, log_scales, quats, opacity_logits, sh, origins, dirs, cfg)
 
 

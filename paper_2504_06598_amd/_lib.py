@@ -40,7 +40,7 @@ class SrtTraceOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("spp", C.c_int32), ("n_per_traversal", C.c_int32),
                 ("sample_offset", C.c_uint32), ("bg", C.c_float * 3), ("any_hit", C.c_int32),
                 ("stack_limit", C.c_int32), ("depth_mode", C.c_int32),
-                ("depth_axis", C.c_float * 3)]
+                ("depth_axis", C.c_float * 3), ("image_width", C.c_int32)]
 
 
 class SrtCamera(C.Structure):
@@ -70,6 +70,7 @@ PROTOTYPES = {
     "srt_build_bvh": (C.c_int, [C.POINTER(SrtScene), C.POINTER(SrtBuildOpts), C.c_void_p,
                                 C.POINTER(C.c_void_p)]),
     "srt_destroy_bvh": (None, [C.c_void_p]),
+    "srt_refit_bvh": (C.c_int, [C.c_void_p, C.POINTER(SrtScene), C.c_void_p]),
     "srt_bvh_get_info": (C.c_int, [C.c_void_p, C.POINTER(SrtBvhInfo)]),
     "srt_bvh_records": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p]),

@@ -73,6 +73,7 @@ struct BwdArgs {
     int32_t depth_mode;
     float depth_axis[3];
     float r_max;
+    int32_t img_w;  // > 0: rays are a row-major image of this width, walked in 8x8 tiles
 };
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v)
@@ -136,22 +137,25 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
     const float inv_spp = 1.0f / (float)a.spp;
     uint32_t n_trav = 0, n_nodes = 0, n_prims = 0, n_front = 0, n_samples = 0, n_lost = 0,
              n_philox = 0, n_fwd_cands = 0;
-    const int64_t n_tiles = (a.R + kBlock - 1) / kBlock;
+    const int64_t n_threads = a.img_w > 0 ? tile_threads(a.img_w, a.R / a.img_w) : a.R;
+    const int64_t n_tiles = (n_threads + kBlock - 1) / kBlock;
 
     // every thread of the workgroup runs the same tiles (the loop bound is
     // per workgroup), so the barriers below are reached by all of them
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t ray = tile * kBlock + threadIdx.x;
+    for (int64_t tile = xcd_block(blockIdx.x, gridDim.x); tile < n_tiles; tile += gridDim.x) {
+        const int64_t t = tile * kBlock + threadIdx.x;
+        const int64_t ray = a.img_w > 0 ? tile_pixel(t, a.img_w, a.R / a.img_w) : t;
+        const bool valid = ray >= 0 && ray < a.R;
         float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
         float tmin_f = 0.0f, tmax_f = 0.0f;
-        if (ray < a.R) {
+        if (valid) {
             g0 = a.grad_rgb[3 * ray];
             g1 = a.grad_rgb[3 * ray + 1];
             g2 = a.grad_rgb[3 * ray + 2];
             tmin_f = a.tmin ? a.tmin[ray] : 0.0f;
             tmax_f = a.tmax ? a.tmax[ray] : INFINITY;
         }
-        const bool work = ray < a.R && (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f) && tmax_f > tmin_f;
+        const bool work = valid && (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f) && tmax_f > tmin_f;
         if (work) {
             const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
             const float dx = a.d[3 * ray], dy = a.d[3 * ray + 1], dz = a.d[3 * ray + 2];
@@ -431,6 +435,8 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     if (!b || !rays || !opts || !scene) return SRT_ERR_INVALID_ARG;
     if (opts->spp < 1 || opts->any_hit) return SRT_ERR_INVALID_ARG;
     if (opts->depth_mode != 0 && opts->depth_mode != 1) return SRT_ERR_INVALID_ARG;
+    if (opts->image_width < 0) return SRT_ERR_INVALID_ARG;
+    if (opts->image_width > 0 && rays->count % opts->image_width != 0) return SRT_ERR_INVALID_ARG;
     const int N = opts->n_per_traversal;
     if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
     if (rays->count < 0 || rays->count > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;
@@ -478,6 +484,7 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     a.depth_mode = opts->depth_mode;
     for (int i = 0; i < 3; ++i) a.depth_axis[i] = opts->depth_axis[i];
     a.r_max = b->r_max;
+    a.img_w = opts->image_width;
     BwdFn fn = pick(b->W, N, counters != nullptr);
     if (!fn) return SRT_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(fn, dim3(ws.threads / kBlock), dim3(kBlock), 0, s, a);

@@ -58,13 +58,11 @@ __device__ inline double lmax_sym3(const double A[9])
 // FP64 and rounded to nearest FP32. The box is that of the ellipsoid
 // q <= 8 of the ROUNDED record: Sigma' = (M^T M)^-1 = M^-1 M^-T, half extent
 // sqrt(8 Sigma'_ii), padded by 2^-20 relative and rounded outward to FP32.
-__global__ void k_preprocess(int64_t G, const float* __restrict__ means,
-                             const float* __restrict__ log_scales, const float* __restrict__ quats,
-                             const float* __restrict__ logits, Record* __restrict__ recs,
-                             float* __restrict__ box_lo, float* __restrict__ box_hi)
+__device__ void make_record(int64_t g, const float* __restrict__ means,
+                            const float* __restrict__ log_scales, const float* __restrict__ quats,
+                            const float* __restrict__ logits, Record& r, float* __restrict__ box_lo,
+                            float* __restrict__ box_hi)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= G) return;
     double qw = quats[4 * g], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
     const double nrm = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
     if (nrm > 0.0) {
@@ -78,7 +76,6 @@ __global__ void k_preprocess(int64_t G, const float* __restrict__ means,
                          1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
                          2.0 * (qx * qz - qw * qy),       2.0 * (qy * qz + qw * qx),
                          1.0 - 2.0 * (qx * qx + qy * qy)};
-    Record r;
     for (int i = 0; i < 3; ++i) {
         const double inv_s = exp(-(double)log_scales[3 * g + i]);
         for (int j = 0; j < 3; ++j) r.M[3 * i + j] = (float)(R[3 * j + i] * inv_s);
@@ -108,7 +105,34 @@ __global__ void k_preprocess(int64_t G, const float* __restrict__ means,
     // M^-1), padded and rounded up
     r.pad[0] = __double2float_ru(sqrt(kEllipsoidQ * lmax_sym3(inv)) * (1.0 + 0x1p-16));
     r.pad[1] = 0.0f;
+}
+
+__global__ void k_preprocess(int64_t G, const float* __restrict__ means,
+                             const float* __restrict__ log_scales, const float* __restrict__ quats,
+                             const float* __restrict__ logits, Record* __restrict__ recs,
+                             float* __restrict__ box_lo, float* __restrict__ box_hi)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    Record r;
+    make_record(g, means, log_scales, quats, logits, r, box_lo, box_hi);
     recs[g] = r;
+}
+
+// Refit: the record of the Gaussian at leaf position k, written in place
+// (the tree keeps its leaf order; the boxes are refilled afterwards).
+__global__ void k_refit_records(int64_t G, const int32_t* __restrict__ leaf_order,
+                                const float* __restrict__ means,
+                                const float* __restrict__ log_scales,
+                                const float* __restrict__ quats, const float* __restrict__ logits,
+                                Record* __restrict__ recs, float* __restrict__ box_lo,
+                                float* __restrict__ box_hi)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= G) return;
+    Record r;
+    make_record(leaf_order[k], means, log_scales, quats, logits, r, box_lo, box_hi);
+    recs[k] = r;
 }
 
 __device__ __forceinline__ uint32_t f2ord(float f)
@@ -444,7 +468,9 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)std::max<int64_
 template <int W>
 srt_status collapse_all(hipStream_t s, DevAlloc& tmp, const BinTree& t, int64_t n, int L,
                         const uint32_t* order, const float* lo, const float* hi,
-                        WideNode<W>* nodes, int64_t* num_nodes, int32_t* depth)
+                        WideNode<W>* nodes, int64_t* num_nodes, int32_t* depth,
+                        int32_t** level_nodes_out, std::vector<uint32_t>& level_off,
+                        std::vector<uint32_t>& level_cnt)
 {
     Task *qa = nullptr, *qb = nullptr;
     uint32_t* ctr = nullptr;  // [0] n_in, [1] n_out, [2] node counter
@@ -457,7 +483,8 @@ srt_status collapse_all(hipStream_t s, DevAlloc& tmp, const BinTree& t, int64_t 
     const uint32_t init[4] = {1u, 0u, 1u, 0u};
     SRT_HIP_TRY(hipMemcpyAsync(qa, &root, sizeof(Task), hipMemcpyHostToDevice, s));
     SRT_HIP_TRY(hipMemcpyAsync(ctr, init, sizeof(init), hipMemcpyHostToDevice, s));
-    std::vector<uint32_t> level_off, level_cnt;
+    level_off.clear();
+    level_cnt.clear();
     uint32_t n_level = 1, off = 0;
     while (n_level > 0) {
         if (level_off.size() > 4096) return SRT_ERR_HIP;  // cannot happen for a valid tree
@@ -482,7 +509,62 @@ srt_status collapse_all(hipStream_t s, DevAlloc& tmp, const BinTree& t, int64_t 
         SRT_HIP_TRY(hipGetLastError());
     }
     *depth = (int32_t)level_off.size();
+    *level_nodes_out = level_nodes;
     return SRT_OK;
+}
+
+// Fill every wide node's boxes from the Gaussian boxes, deepest level first.
+template <int W>
+srt_status fill_boxes(const srt_bvh* b, hipStream_t s)
+{
+    WideNode<W>* nodes = static_cast<WideNode<W>*>(b->nodes);
+    if (b->level_cnt.empty()) {
+        k_single_leaf<W><<<1, 1, 0, s>>>(b->G, b->box_lo, b->box_hi, nodes);
+        SRT_HIP_TRY(hipGetLastError());
+        return SRT_OK;
+    }
+    const uint32_t* order = reinterpret_cast<const uint32_t*>(b->leaf_order);
+    for (size_t lv = b->level_off.size(); lv-- > 0;) {
+        k_wide_boxes<W><<<blocks_for(b->level_cnt[lv], 128), 128, 0, s>>>(
+            b->level_nodes + b->level_off[lv], b->level_cnt[lv], order, b->box_lo, b->box_hi,
+            nodes);
+        SRT_HIP_TRY(hipGetLastError());
+    }
+    return SRT_OK;
+}
+
+// Largest bounding-sphere radius of the records (synchronises the stream).
+srt_status read_r_max(srt_bvh* b, hipStream_t s)
+{
+    const uint32_t binit[8] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
+    SRT_HIP_TRY(hipMemcpyAsync(b->bounds, binit, sizeof(binit), hipMemcpyHostToDevice, s));
+    k_centre_bounds<<<std::min<unsigned>(blocks_for(b->G, 256), 1024u), 256, 0, s>>>(
+        b->G, b->box_lo, b->box_hi, b->recs, b->bounds);
+    SRT_HIP_TRY(hipGetLastError());
+    uint32_t rmax_bits = 0;
+    SRT_HIP_TRY(hipMemcpyAsync(&rmax_bits, b->bounds + 6, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               s));
+    SRT_HIP_TRY(hipStreamSynchronize(s));
+    memcpy(&b->r_max, &rmax_bits, sizeof(float));
+    return SRT_OK;
+}
+
+// Refit (same topology and leaf order): new records and Gaussian boxes from
+// the scene's current parameters, then every node box bottom-up.
+template <int W>
+srt_status refit_impl(srt_bvh* b, const srt_scene* sc, hipStream_t s)
+{
+    const int64_t G = b->G;
+    b->sh = sc->sh;
+    if (G == 0) return SRT_OK;
+    k_refit_records<<<blocks_for(G, 256), 256, 0, s>>>(G, b->leaf_order, sc->means,
+                                                       sc->log_scales, sc->quats,
+                                                       sc->opacity_logits, b->recs, b->box_lo,
+                                                       b->box_hi);
+    SRT_HIP_TRY(hipGetLastError());
+    const srt_status st = fill_boxes<W>(b, s);
+    if (st != SRT_OK) return st;
+    return read_r_max(b, s);
 }
 
 template <int W>
@@ -515,8 +597,8 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
                                                     b->box_hi);
     SRT_HIP_TRY(hipGetLastError());
 
-    uint32_t* bounds = nullptr;
-    SRT_HIP_TRY(tmp.get(&bounds, 8 * sizeof(uint32_t)));
+    SRT_HIP_TRY(hipMalloc(&b->bounds, 8 * sizeof(uint32_t)));
+    uint32_t* bounds = b->bounds;
     const uint32_t binit[8] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
     SRT_HIP_TRY(hipMemcpyAsync(bounds, binit, sizeof(binit), hipMemcpyHostToDevice, s));
     k_centre_bounds<<<std::min<unsigned>(blocks_for(G, 256), 1024u), 256, 0, s>>>(
@@ -564,9 +646,16 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
         SRT_HIP_TRY(hipGetLastError());
         SRT_HIP_TRY(tmp.get(&nodes_max, sizeof(WideNode<W>) * (size_t)(n - 1)));
         const BinTree t{left, right, first, last};
+        int32_t* lvl = nullptr;
         const srt_status st = collapse_all<W>(s, tmp, t, n, L, order, b->box_lo, b->box_hi,
-                                              nodes_max, &num_nodes, &depth);
+                                              nodes_max, &num_nodes, &depth, &lvl, b->level_off,
+                                              b->level_cnt);
         if (st != SRT_OK) return st;
+        const size_t listed = (size_t)b->level_off.back() + b->level_cnt.back();
+        SRT_HIP_TRY(hipMalloc(&b->level_nodes, sizeof(int32_t) * listed));
+        SRT_HIP_TRY(hipMemcpyAsync(b->level_nodes, lvl, sizeof(int32_t) * listed,
+                                   hipMemcpyDeviceToDevice, s));
+        b->bytes += (int64_t)(sizeof(int32_t) * listed);
     }
     WideNode<W>* nodes = nullptr;
     SRT_HIP_TRY(hipMalloc(&nodes, sizeof(WideNode<W>) * (size_t)num_nodes));
@@ -653,7 +742,24 @@ void srt_destroy_bvh(srt_bvh* b)
     (void)hipFree(b->leaf_order);
     (void)hipFree(b->box_lo);
     (void)hipFree(b->box_hi);
+    (void)hipFree(b->level_nodes);
+    (void)hipFree(b->bounds);
     delete b;
+}
+
+srt_status srt_refit_bvh(srt_bvh* b, const srt_scene* sc, void* stream)
+{
+    if (!b || !sc) return SRT_ERR_INVALID_ARG;
+    if (sc->num_gaussians != b->G || sc->sh_degree != b->deg) return SRT_ERR_INVALID_ARG;
+    if (b->G > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
+        return SRT_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (b->W) {
+    case 2: return refit_impl<2>(b, sc, s);
+    case 4: return refit_impl<4>(b, sc, s);
+    case 8: return refit_impl<8>(b, sc, s);
+    }
+    return SRT_ERR_INVALID_ARG;
 }
 
 srt_status srt_bvh_get_info(const srt_bvh* b, srt_bvh_info* info)

@@ -377,4 +377,32 @@ __device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned l
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
 }
 
+// Workgroups of a launch are dispatched to the 8 XCDs in turn (b -> XCD b % 8).
+// Renumber them so that each XCD runs one contiguous range of logical
+// workgroups: neighbouring rays then share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+    const uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Thread t of an image launch -> pixel index in a row-major w x h image, with
+// each group of 64 threads on one 8x8 tile (tiles in row-major order); -1 for
+// the threads of a partial tile that fall outside the image.
+__device__ __forceinline__ int64_t tile_pixel(int64_t t, int32_t w, int64_t h)
+{
+    const int64_t tiles_x = (w + 7) / 8;
+    const int64_t tile = t >> 6;
+    const int32_t lane = (int32_t)(t & 63);
+    const int64_t x = (tile % tiles_x) * 8 + (lane & 7);
+    const int64_t y = (tile / tiles_x) * 8 + (lane >> 3);
+    return (x < w && y < h) ? y * w + x : -1;
+}
+
+// Threads an image launch needs for w x h pixels.
+__host__ __device__ __forceinline__ int64_t tile_threads(int32_t w, int64_t h)
+{
+    return (int64_t)((w + 7) / 8) * ((h + 7) / 8) * 64;
+}
+
 }  // namespace srt

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "srt.h"
 #include "srt_device.hpp"
@@ -21,6 +22,12 @@ struct srt_bvh {
     const float* sh = nullptr;       // borrowed from the scene
     float r_max = 0.0f;              // largest bounding-sphere radius
     int64_t bytes = 0;
+    // topology kept for refits: node indices grouped by level (root level
+    // first; empty when the tree is a single leaf), and a small device
+    // buffer for the scene bounds
+    int32_t* level_nodes = nullptr;
+    std::vector<uint32_t> level_off, level_cnt;
+    uint32_t* bounds = nullptr;      // [8]
 };
 
 namespace srt {

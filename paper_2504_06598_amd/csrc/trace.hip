@@ -60,6 +60,7 @@ struct TraceArgs {
     int32_t depth_mode;
     float depth_axis[3];
     float r_max;
+    int32_t img_w;  // > 0: rays are a row-major image of this width, traced in tiles
 };
 
 struct Counts {
@@ -176,10 +177,12 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
                 ++lost;
             }
         }
-    } else if (gt < a.R) {
-        if (!trace_ray<W, N, ANY>(a, gt, stk, stride, cap, cnt)) {
+    } else {
+        const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+        const int64_t ray = a.img_w > 0 ? tile_pixel(t, a.img_w, a.R / a.img_w) : t;
+        if (ray >= 0 && ray < a.R && !trace_ray<W, N, ANY>(a, ray, stk, stride, cap, cnt)) {
             const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
-            a.ovf_list[slot] = (uint32_t)gt;
+            a.ovf_list[slot] = (uint32_t)ray;
         }
     }
     if (COUNT && a.counters) {
@@ -240,6 +243,7 @@ srt_status validate_opts(const srt_trace_opts* o)
     if (o->any_hit && N != 1) return SRT_ERR_INVALID_ARG;
     if (o->stack_limit < 0) return SRT_ERR_INVALID_ARG;
     if (o->depth_mode != 0 && o->depth_mode != 1) return SRT_ERR_INVALID_ARG;
+    if (o->image_width < 0) return SRT_ERR_INVALID_ARG;
     return SRT_OK;
 }
 
@@ -284,9 +288,13 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
     a.depth_mode = o->depth_mode;
     for (int i = 0; i < 3; ++i) a.depth_axis[i] = o->depth_axis[i];
     a.r_max = b->r_max;
+    a.img_w = o->image_width;
+    if (a.img_w > 0 && rays->count % a.img_w != 0) return SRT_ERR_INVALID_ARG;
     fill_u32(ws.ctrl, 0u, 2, s);
     if (rays->count > 0) {
-        const unsigned grid = (unsigned)((rays->count + kBlock - 1) / kBlock);
+        const int64_t threads =
+            a.img_w > 0 ? tile_threads(a.img_w, rays->count / a.img_w) : rays->count;
+        const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(fast, dim3(grid), dim3(kBlock), 0, s, a);
         SRT_HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL(deep, dim3(kDeepThreads / kBlock), dim3(kBlock), 0, s, a);
@@ -589,7 +597,9 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
         cr.ray_ids = rid_tab;
     }
     cr.purpose = 0;
-    srt_status st = launch_trace(b, &cr, opts, nullptr, cg, ct, counters, w.trace_ws, s);
+    srt_trace_opts co = *opts;
+    co.image_width = cam->width;
+    srt_status st = launch_trace(b, &cr, &co, nullptr, cg, ct, counters, w.trace_ws, s);
     if (st != SRT_OK) return st;
 
     k_spawn<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(R, opts->spp, ray_id_base, w.co, w.cd, cg,
@@ -600,6 +610,7 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
     so.spp = 1;
     so.n_per_traversal = 1;
     so.sample_offset = opts->sample_offset;
+    so.image_width = 0;
     for (int pass = 0; pass < 2; ++pass) {
         const SecRays& sr = pass == 0 ? w.sh : w.mr;
         srt_rays rr{};

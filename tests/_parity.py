@@ -55,3 +55,55 @@ def tiny_scene(seed, n, scale=(0.01, 0.05), deg=0):
     rng = np.random.default_rng(seed + 77)
     sc.log_scales = rng.uniform(lo, hi, sc.log_scales.shape).astype(np.float32)
     return sc
+
+
+def _parse_nodes(raw, W):
+    f = raw.view(np.float32)
+    lo = f[:, 0:3 * W].reshape(-1, 3, W)
+    hi = f[:, 3 * W:6 * W].reshape(-1, 3, W)
+    child = raw[:, 6 * W:7 * W]
+    return lo, hi, child
+
+
+def check_bvh_structure(bvh, W, L, G):
+    """Every Gaussian in exactly one leaf of at most L, every slot box holds
+    its child's boxes (or its Gaussians' boxes), no node reached twice."""
+    info = bvh.info()
+    raw, order = bvh.nodes()
+    raw, order = to_np(raw), to_np(order)
+    recs = {k: to_np(v) for k, v in bvh.records().items()}
+    lo, hi, child = _parse_nodes(raw, W)
+    assert sorted(order.tolist()) == list(range(G))
+    seen = np.zeros(G, np.int32)
+    stack = [(0, 1)]
+    max_depth = 0
+    visited = 0
+    while stack:
+        n, depth = stack.pop()
+        visited += 1
+        assert visited <= info["num_nodes"], "node reached twice"
+        assert 0 <= n < info["num_nodes"]
+        max_depth = max(max_depth, depth)
+        for c in range(W):
+            ref = int(child[n, c])
+            if ref == 0x7FFFFFFF:
+                assert lo[n, 0, c] > hi[n, 0, c]
+                continue
+            if ref >= 0:
+                # the slot box contains every box of the child node
+                sub = child[ref] != 0x7FFFFFFF
+                assert np.all(lo[n, :, c][:, None] <= lo[ref][:, sub])
+                assert np.all(hi[n, :, c][:, None] >= hi[ref][:, sub])
+                stack.append((ref, depth + 1))
+            else:
+                v = ~ref & 0xFFFFFFFF
+                first, count = v >> 3, (v & 7) + 1
+                assert count <= L
+                for p in range(first, first + count):
+                    seen[p] += 1
+                    g = order[p]
+                    assert np.all(lo[n, :, c] <= recs["box_lo"][g])
+                    assert np.all(hi[n, :, c] >= recs["box_hi"][g])
+    assert np.all(seen == 1), "every Gaussian in exactly one leaf"
+    assert visited == info["num_nodes"]
+    assert max_depth <= info["depth"]

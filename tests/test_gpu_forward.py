@@ -8,7 +8,8 @@ import torch
 
 import oracle
 import srt_inputs as si
-from _parity import (compare_ids, compare_rgb, device_scene, say, tiny_scene, to_np)
+from _parity import (check_bvh_structure, compare_ids, compare_rgb, device_scene, say,
+                     tiny_scene, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -58,58 +59,12 @@ def test_records_match_oracle(srt):
     assert np.all(r["box_hi"] - r["box_lo"] <= 2 * h * (1 + 1e-5) + 1e-6)
 
 
-def _parse_nodes(raw, W):
-    f = raw.view(np.float32)
-    lo = f[:, 0:3 * W].reshape(-1, 3, W)
-    hi = f[:, 3 * W:6 * W].reshape(-1, 3, W)
-    child = raw[:, 6 * W:7 * W]
-    return lo, hi, child
-
-
 @pytest.mark.parametrize("W,L", [(2, 1), (4, 4), (8, 8), (4, 1), (8, 3)])
 def test_bvh_structure(srt, W, L):
     say(f"bvh structure W={W} L={L}")
     sc = si.scene_shell(9, 5000, 0)
     bvh = srt.srt_build_bvh(device_scene(sc), W, L)
-    info = bvh.info()
-    raw, order = bvh.nodes()
-    raw, order = to_np(raw), to_np(order)
-    recs = {k: to_np(v) for k, v in bvh.records().items()}
-    lo, hi, child = _parse_nodes(raw, W)
-    assert sorted(order.tolist()) == list(range(5000))
-    seen = np.zeros(5000, np.int32)
-    stack = [(0, 1)]
-    max_depth = 0
-    visited = 0
-    while stack:
-        n, depth = stack.pop()
-        visited += 1
-        assert visited <= info["num_nodes"], "node reached twice"
-        assert 0 <= n < info["num_nodes"]
-        max_depth = max(max_depth, depth)
-        for c in range(W):
-            ref = int(child[n, c])
-            if ref == 0x7FFFFFFF:
-                assert lo[n, 0, c] > hi[n, 0, c]
-                continue
-            if ref >= 0:
-                # the slot box contains every box of the child node
-                sub = child[ref] != 0x7FFFFFFF
-                assert np.all(lo[n, :, c][:, None] <= lo[ref][:, sub])
-                assert np.all(hi[n, :, c][:, None] >= hi[ref][:, sub])
-                stack.append((ref, depth + 1))
-            else:
-                v = ~ref & 0xFFFFFFFF
-                first, count = v >> 3, (v & 7) + 1
-                assert count <= L
-                for p in range(first, first + count):
-                    seen[p] += 1
-                    g = order[p]
-                    assert np.all(lo[n, :, c] <= recs["box_lo"][g])
-                    assert np.all(hi[n, :, c] >= recs["box_hi"][g])
-    assert np.all(seen == 1), "every Gaussian in exactly one leaf"
-    assert visited == info["num_nodes"]
-    assert max_depth <= info["depth"]
+    check_bvh_structure(bvh, W, L, 5000)
 
 
 def test_camera_rays_bit_exact(srt):
@@ -340,3 +295,38 @@ def test_center_depth_matches_oracle(srt, axis):
     # the centre depth changes results compared with the mean depth
     g0 = _trace(srt, bvh, o, d, seed=8, spp=8, n_per_traversal=4)
     assert (g0["hit_gid"] != g["hit_gid"]).mean() > 0.01
+
+
+@pytest.mark.parametrize("w,h", [(13, 9), (40, 24), (1, 5), (8, 8)])
+def test_image_tiles_change_nothing(srt, w, h):
+    say(f"tiled image launch {w}x{h}")
+    sc = tiny_scene(19, 2500, (0.02, 0.08))
+    cam = si.look_at((0.2, 0.1, 2.9), (0, 0, 0), w, h)
+    o, d = si.camera_rays(cam)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    for lim in (0, 1):  # the on-chip stack, and the deep-stack rerun of every ray
+        base = _trace(srt, bvh, o, d, seed=5, spp=4, n_per_traversal=4, stack_limit=lim)
+        cnt = srt.new_counters()
+        tiled = _trace(srt, bvh, o, d, seed=5, spp=4, n_per_traversal=4, stack_limit=lim,
+                       image_width=w, counters=cnt)
+        for k in ("hit_gid", "hit_t", "rgb"):
+            np.testing.assert_array_equal(tiled[k], base[k])
+        c = srt.counters_dict(cnt)
+        assert c["ray_samples"] == w * h * 4 and c["lost"] == 0
+    if (w, h) == (13, 9):
+        ora = oracle.trace(oracle.Records(sc), oracle.Rays(o, d), spp=4, seed=5)
+        compare_ids(tiled["hit_gid"], ora["hit_gid"], ora["flags"])
+
+
+def test_image_width_errors(srt):
+    sc = tiny_scene(20, 100)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    o = torch.zeros((10, 3), device="cuda")
+    for bad in (3, -1):
+        with pytest.raises(srt.SrtError) as e:
+            srt.srt_trace_forward(bvh, o, o, image_width=bad)
+        assert e.value.code == 1
+        with pytest.raises(srt.SrtError) as e:
+            srt.srt_trace_backward(bvh, o, o, torch.ones((10, 3), device="cuda"),
+                                   image_width=bad)
+        assert e.value.code == 1

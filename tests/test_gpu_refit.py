@@ -1,0 +1,147 @@
+"""BVH refit and the optimisation loop built on it.
+
+A refit keeps the topology and recomputes records and boxes, so traces
+through it must equal traces through a fresh build of the same parameters
+bit for bit (the accepted set does not depend on the tree), and the fresh
+build is itself checked against the oracle. The loop must lower the exact
+(oracle) L2 loss of the differentiation recipe."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import srt_inputs as si
+from _parity import check_bvh_structure, compare_ids, device_scene, say, tiny_scene, to_np
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@pytest.fixture(scope="module")
+def srt():
+    import paper_2504_06598_amd as srt
+    assert torch.cuda.is_available()
+    srt._lib.load()
+    return srt
+
+
+def _moved(sc, seed, step=0.05):
+    """The same Gaussians with every parameter changed."""
+    rng = np.random.default_rng(seed)
+    m = sc.copy()
+    m.means = (sc.means + rng.normal(0, step, sc.means.shape)).astype(np.float32)
+    m.log_scales = (sc.log_scales + rng.normal(0, 0.2, sc.log_scales.shape)).astype(np.float32)
+    m.quats = (sc.quats + rng.normal(0, 0.2, sc.quats.shape)).astype(np.float32)
+    m.opacity_logits = (sc.opacity_logits
+                        + rng.normal(0, 0.5, sc.opacity_logits.shape)).astype(np.float32)
+    m.sh = (sc.sh + rng.normal(0, 0.1, sc.sh.shape)).astype(np.float32)
+    return m
+
+
+def _copy_into(dsc, host):
+    for n in NAMES:
+        getattr(dsc, n).copy_(torch.from_numpy(np.ascontiguousarray(getattr(host, n))).cuda())
+
+
+def _trace(srt, bvh, o, d, **kw):
+    res = srt.srt_trace_forward(bvh, o, d, **kw)
+    torch.cuda.synchronize()
+    return {k: to_np(v) for k, v in res.items()}
+
+
+@pytest.mark.parametrize("W,L,G", [(2, 1, 3000), (4, 4, 3000), (8, 2, 3000), (4, 4, 3)])
+def test_refit_equals_fresh_build(srt, W, L, G):
+    say(f"refit W={W} L={L} G={G}")
+    sc = tiny_scene(41, G, (0.02, 0.08))
+    moved = _moved(sc, 42)
+    cam = si.look_at((0.3, 0.2, 2.9), (0, 0, 0), 40, 40)
+    o, d = si.camera_rays(cam)
+    oc, dc = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    dsc = device_scene(sc)
+    bvh = srt.srt_build_bvh(dsc, W, L)
+    nodes_before = bvh.info()["num_nodes"]
+    _copy_into(dsc, moved)  # update the parameters in place, as an optimiser does
+    srt.srt_refit_bvh(bvh, dsc)
+    torch.cuda.synchronize()
+    assert bvh.info()["num_nodes"] == nodes_before
+    check_bvh_structure(bvh, W, L, G)
+    fresh = srt.srt_build_bvh(device_scene(moved), W, L)
+    ra = {k: to_np(v) for k, v in bvh.records().items()}
+    rb = {k: to_np(v) for k, v in fresh.records().items()}
+    for k in ra:
+        np.testing.assert_array_equal(ra[k], rb[k])
+    refit_ids = {}
+    for mode in (0, 1):  # the centre depth mode also reads the refit sphere radii
+        kw = dict(seed=8, spp=4, n_per_traversal=4, depth_mode=mode)
+        a = _trace(srt, bvh, oc, dc, **kw)
+        b = _trace(srt, fresh, oc, dc, **kw)
+        for k in ("hit_gid", "hit_t", "rgb"):
+            np.testing.assert_array_equal(a[k], b[k])
+        refit_ids[mode] = a["hit_gid"]
+    ora = oracle.trace(oracle.Records(moved), oracle.Rays(o, d), spp=4, seed=8)
+    compare_ids(refit_ids[0], ora["hit_gid"], ora["flags"])
+
+
+def test_refit_errors(srt):
+    sc = tiny_scene(43, 200)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_refit_bvh(bvh, device_scene(tiny_scene(44, 199)))
+    assert e.value.code == 1
+    other = tiny_scene(45, 200, deg=1)
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_refit_bvh(bvh, device_scene(other))
+    assert e.value.code == 1
+
+
+def test_refit_empty_scene(srt):
+    sc = tiny_scene(46, 0)
+    dsc = device_scene(sc)
+    bvh = srt.srt_build_bvh(dsc, 4, 4)
+    srt.srt_refit_bvh(bvh, dsc)
+    o = torch.zeros((5, 3), device="cuda")
+    d = torch.tensor([[0.0, 0.0, 1.0]] * 5, device="cuda")
+    res = _trace(srt, bvh, o, d, spp=2, bg=(0.25, 0.5, 0.75))
+    assert np.all(res["hit_gid"] == -1)
+    np.testing.assert_array_equal(res["rgb"], np.tile([0.25, 0.5, 0.75], (5, 1)).astype(np.float32))
+
+
+def test_fit_recovers_perturbed_scene(srt):
+    """The differentiation recipe in miniature: the tiny cube scene starts
+    where it was generated; the target images are the exact composites of the
+    perturbed scene on 8 ring views of 64x64; Adam on means and opacity
+    logits through the refit BVH. The exact loss (oracle composite of the
+    fitted parameters) must fall well below its starting value and the means
+    must move toward the target's."""
+    from paper_2504_06598_amd.fit import fit
+    say("optimisation loop: 8 ring views 64x64, 4 spp, 40 Adam steps")
+    sc0 = si.workload(1)["scene"]
+    tgt = si.perturbed(sc0, 104)
+    cams = si.ring_cameras(8, 3.0, 64, 64)
+    o, d = zip(*[si.camera_rays(c) for c in cams])
+    o, d = np.concatenate(o), np.concatenate(d)
+    rays = oracle.Rays(o, d)
+    target = oracle.composite(oracle.Records(tgt), rays)["L"]
+
+    def exact_loss(host):
+        L = oracle.composite(oracle.Records(host), rays)["L"]
+        return float(((L - target) ** 2).mean())
+
+    params = {n: torch.from_numpy(np.ascontiguousarray(getattr(sc0, n))).cuda() for n in NAMES}
+    losses = fit(params, sc0.sh_degree, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(),
+                 torch.from_numpy(target.astype(np.float32)).cuda(), steps=40,
+                 lr={"means": 5e-4, "opacity_logits": 5e-3}, spp=4, n_per_traversal=4,
+                 image_width=64)
+    torch.cuda.synchronize()
+    fitted = sc0.copy()
+    fitted.means = to_np(params["means"])
+    fitted.opacity_logits = to_np(params["opacity_logits"])
+    before, after = exact_loss(sc0), exact_loss(fitted)
+    err0 = float(np.abs(sc0.means - tgt.means).mean())
+    err1 = float(np.abs(fitted.means - tgt.means).mean())
+    say(f"exact loss {before:.3e} -> {after:.3e}; mean error {err0:.4f} -> {err1:.4f}; "
+        f"stochastic loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert np.all(np.isfinite(losses))
+    assert after < 0.35 * before
+    assert err1 < 0.8 * err0
