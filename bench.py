@@ -45,7 +45,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--width", type=int, default=4)
-    p.add_argument("--leaf", type=int, default=4)
+    p.add_argument("--leaf", type=int, default=2)
     p.add_argument("--n-per-traversal", type=int, default=4)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-pixels", type=int, default=192)
@@ -222,6 +222,24 @@ def main():
     print(f"# dominant kernel {avg_ms:.3f} ms/launch, {bytes_per_launch / 1e9:.3f} GB "
           f"algorithmic -> {achieved:.0f} GB/s", file=sys.stderr, flush=True)
 
+    # ---- BVH build vs refit at 1M (a refit replaces the build inside an
+    # optimisation loop; both synchronise) ----
+    def timed(fn, reps=3):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return min(ts)
+
+    bvh_times = {"build_ms": round(timed(lambda: srt.srt_build_bvh(scene, args.width,
+                                                                   args.leaf)), 3),
+                 "refit_ms": round(timed(lambda: srt.srt_refit_bvh(bvh, scene)), 3)}
+    print(f"# BVH at 1M: build {bvh_times['build_ms']} ms, refit {bvh_times['refit_ms']} ms",
+          file=sys.stderr, flush=True)
+
     # ---- CPU baseline: the oracle on a bounded pixel sample ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -265,7 +283,8 @@ def main():
                        "leaf_size": args.leaf, "n_per_traversal": N,
                        "forward_ray_samples_per_step": int(fwd_rs),
                        "backward_ray_samples_per_step": int(bwd_rs)},
-            "roofline": roof, "cpu_baseline": cpu, "persistent_vs_plain": batched}
+            "roofline": roof, "cpu_baseline": cpu, "persistent_vs_plain": batched,
+            "bvh": bvh_times}
     print(json.dumps(line), flush=True)
 
 
