@@ -295,15 +295,15 @@ def srt_camera_rays(cam, device="cuda"):
 
 def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_traversal=1,
                       sample_offset=0, bg=(0.0, 0.0, 0.0), light=(5.0, 5.0, 5.0), plane_y=-2.5,
-                      tmin_secondary=1e-4, want_hits=True, counters=None, workspace=None,
-                      out=None):
+                      tmin_secondary=1e-4, stack_limit=0, want_hits=True, counters=None,
+                      workspace=None, out=None):
     """Path-tracer mix of one camera; returns dict(rgb [, cam_gid, cam_t,
     shadow_vis, mirror_gid])."""
     lib = _lib.load()
     dev = bvh.scene.means.device
     R = int(cam.width) * int(cam.height)
     c = _camera(cam)
-    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0)
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, stack_limit)
     pm = _lib.SrtPathmixOpts()
     for i in range(3):
         pm.light[i] = float(light[i])
