@@ -212,7 +212,8 @@ def main():
                         kc["ray_samples"] * sh_bytes + R * (24 + 12))
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(args.width, args.leaf),
             "kernel": f"k_trace<W={args.width},N={N}> camera rays",
             "kernel_ms": round(avg_ms, 3),
             "bytes_per_launch": int(bytes_per_launch),
@@ -286,6 +287,25 @@ def main():
             "roofline": roof, "cpu_baseline": cpu, "persistent_vs_plain": batched,
             "bvh": bvh_times}
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic(width, leaf, root=ROOT):
+    """HBM bytes per launch of the camera-ray kernel, from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs recorded under profiles/ (scaled by the same
+    counters read on a copy of known size); None when the kernel's sources or
+    the tree shape differ from those that were measured."""
+    import hashlib
+    path = os.path.join(root, "profiles", "k_trace_camera_1M_pmc.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha1()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(root, f), "rb").read())
+    except (OSError, ValueError, KeyError):
+        return None
+    if h.hexdigest() != rec["sources_sha1"] or (width, leaf) != (rec["width"], rec["leaf_size"]):
+        return None
+    return int(rec["hbm_bytes_per_launch"])
 
 
 def profile_kernel(args, srt, si, torch, scene, cam, spp, N, dev):
