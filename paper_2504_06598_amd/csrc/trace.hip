@@ -11,8 +11,6 @@
 // paper's ReportIntersection). A lane whose stack overflows abandons the ray
 // and queues it; a second launch reruns queued rays with a stack in global
 // memory sized by the tree depth.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <climits>
 
@@ -473,218 +471,6 @@ __global__ void k_compose(int64_t R, int32_t spp, int32_t deg, const float* __re
     rgb[3 * p + 2] = a2 * inv;
 }
 
-
-// --------------------------------------------------------------------------
-// Shadow rays in groups. The shadow rays of a pixel's samples that start on
-// the same accepted Gaussian (or all on the plane) are one and the same ray,
-// so one traversal resolves all of them. Every sample keeps its own
-// acceptance numbers (the Philox counter carries its own sample index), and
-// the walk visits the same nodes in the same order as that sample's own
-// any-hit walk (any-hit walks cull nothing by depth), so each sample's
-// visibility and reported id equal those of its own walk.
-// --------------------------------------------------------------------------
-constexpr int kGroupBits = 64;  // samples of one pixel per group block
-
-__device__ __forceinline__ bool has_ray(const SecRays& r, int64_t i)
-{
-    return r.tmax[i] > r.tmin[i];
-}
-
-// A slot leads a group when no earlier sample of its pixel, in the same block
-// of 64 samples, has a shadow ray from the same start; the leader's mask
-// holds every sample of the block sharing that ray.
-__global__ void k_group_mark(int64_t n, int32_t spp, SecRays sh, uint32_t* __restrict__ flag,
-                             uint64_t* __restrict__ mask)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t p = i / spp;
-    const int32_t s = (int32_t)(i - p * spp);
-    const int32_t c0 = (s / kGroupBits) * kGroupBits;
-    const int32_t c1 = min(spp, c0 + kGroupBits);
-    uint32_t lead = 0;
-    if (has_ray(sh, i)) {
-        const int32_t key = sh.ign[i];
-        lead = 1;
-        for (int32_t t = c0; t < s; ++t) {
-            const int64_t j = p * spp + t;
-            if (has_ray(sh, j) && sh.ign[j] == key) {
-                lead = 0;
-                break;
-            }
-        }
-        if (lead) {
-            uint64_t m = 0;
-            for (int32_t t = s; t < c1; ++t) {
-                const int64_t j = p * spp + t;
-                if (has_ray(sh, j) && sh.ign[j] == key) m |= 1ull << (t - c0);
-            }
-            mask[i] = m;
-        }
-    }
-    flag[i] = lead;
-}
-
-__global__ void k_group_emit(int64_t n, const uint32_t* __restrict__ flag,
-                             const uint32_t* __restrict__ pos, uint32_t* __restrict__ lead,
-                             uint32_t* __restrict__ count)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (flag[i]) lead[pos[i]] = (uint32_t)i;
-    if (i == n - 1) *count = pos[i] + flag[i];
-}
-
-struct GroupArgs {
-    const void* nodes;
-    const Record* recs;
-    SecRays sh;
-    const uint32_t* lead;   // [count] leader slots
-    const uint64_t* mask;   // [n] by slot (leaders only)
-    const uint32_t* count;  // device: number of groups
-    int32_t spp;
-    uint32_t soff, purpose, k0, k1;
-    int32_t* out;           // [n] accepted id per slot, -1 unoccluded
-    unsigned long long* counters;
-    uint32_t* ctrl;
-    uint32_t* ovf_list;
-    int32_t* deep_stack;
-    int32_t deep_cap;
-    int32_t stack_cap;
-    int64_t max_steps;
-    int32_t depth_mode;
-    float depth_axis[3];
-    float r_max;
-};
-
-template <int W>
-__device__ __forceinline__ bool shadow_group(const GroupArgs& a, uint32_t gi, int32_t* stk,
-                                             int stride, int cap, Counts& cnt)
-{
-    const uint32_t li = a.lead[gi];
-    const uint64_t m0 = a.mask[li];
-    const int64_t p = li / a.spp;
-    const int32_t c0 = ((int32_t)(li - p * a.spp) / kGroupBits) * kGroupBits;
-    const int64_t slot0 = p * a.spp + c0;
-    const float tmin_f = a.sh.tmin[li], tmax_f = a.sh.tmax[li];
-    const int32_t ign = a.sh.ign[li];
-    const uint32_t rid = a.sh.rid[li];
-    const uint32_t sbase = a.soff + (uint32_t)c0;  // sample index of mask bit 0
-    const Ray rd = make_ray(a.sh.o[3 * li], a.sh.o[3 * li + 1], a.sh.o[3 * li + 2],
-                            a.sh.d[3 * li], a.sh.d[3 * li + 1], a.sh.d[3 * li + 2], tmin_f);
-    const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rd, a.r_max);
-    const double tmin = tmin_f, tmax = tmax_f;
-    FlatStack stack{stk, stride, cap};
-    uint64_t pending = m0;
-    float tcut = tmax_f;
-    auto visit = [&](uint32_t ri) -> bool {
-        const Record r = load_record(a.recs, ri);
-        if (dc.mode == 0 ? sphere_reject(r, rd, rd.tmin, tcut)
-                         : sphere_reject(r, rd, -INFINITY, INFINITY))
-            return false;
-        double tm, q;
-        isect_tq(r, rd, tm, q);
-        const double t = depth_of(dc, r, rd, tm);
-        if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
-        ++cnt.cands;
-        const double alpha = (double)r.opacity * exp(-0.5 * q);
-        uint64_t m = pending;
-        uint32_t grp = 0xFFFFFFFFu;
-        uint4 w = make_uint4(0, 0, 0, 0);
-        while (m != 0) {
-            const int bit = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const uint32_t smp = sbase + (uint32_t)bit;
-            if ((smp >> 2) != grp) {
-                grp = smp >> 2;
-                w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, a.purpose), a.k0, a.k1);
-                ++cnt.philox;
-            }
-            if (u_of_word(word_of(w, smp & 3u)) < alpha) {
-                pending &= ~(1ull << bit);
-                a.out[slot0 + bit] = r.gid;
-            }
-        }
-        return pending == 0;
-    };
-    const int res = walk<W>(static_cast<const WideNode<W>*>(a.nodes), rd, tcut, dc.node_slack,
-                            stack, a.max_steps, cnt.nodes, cnt.prims, visit);
-    if (res == kWalkOverflow) return false;
-    while (pending != 0) {
-        const int bit = __ffsll((unsigned long long)pending) - 1;
-        pending &= pending - 1;
-        a.out[slot0 + bit] = -1;
-    }
-    ++cnt.trav;
-    cnt.samples += (uint32_t)__popcll((unsigned long long)m0);
-    return true;
-}
-
-template <int W, bool DEEP, bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_shadow_groups(GroupArgs a)
-{
-    __shared__ int32_t lds[DEEP ? 1 : LdsStack<W>::value * kBlock];
-    int32_t* stk;
-    int stride, cap;
-    const int64_t gt = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (DEEP) {
-        stk = a.deep_stack + gt;
-        stride = kDeepThreads;
-        cap = a.deep_cap;
-    } else {
-        stk = lds + threadIdx.x;
-        stride = kBlock;
-        cap = min(LdsStack<W>::value, a.stack_cap);
-    }
-    Counts cnt;
-    uint32_t deep_runs = 0, lost = 0;
-    if (DEEP) {
-        const int64_t n = (int64_t)a.ctrl[0];
-        for (int64_t it = gt; it < n; it += (int64_t)gridDim.x * kBlock) {
-            ++deep_runs;
-            if (!shadow_group<W>(a, a.ovf_list[it], stk, stride, cap, cnt)) {
-                atomicAdd(&a.ctrl[1], 1u);
-                ++lost;
-            }
-        }
-    } else {
-        const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-        if (gi < (int64_t)*a.count && !shadow_group<W>(a, (uint32_t)gi, stk, stride, cap, cnt)) {
-            const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
-            a.ovf_list[slot] = (uint32_t)gi;
-        }
-    }
-    if (COUNT && a.counters) {
-        wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, cnt.trav);
-        wave_add_u64(a.counters + SRT_CNT_NODES, cnt.nodes);
-        wave_add_u64(a.counters + SRT_CNT_PRIMS, cnt.prims);
-        wave_add_u64(a.counters + SRT_CNT_CANDIDATES, cnt.cands);
-        wave_add_u64(a.counters + SRT_CNT_PHILOX, cnt.philox);
-        wave_add_u64(a.counters + SRT_CNT_DEEP, deep_runs);
-        wave_add_u64(a.counters + SRT_CNT_RAY_SAMPLES, cnt.samples);
-        wave_add_u64(a.counters + SRT_CNT_LOST, lost);
-    }
-}
-
-using GroupFn = void (*)(GroupArgs);
-
-template <int W>
-void pick_groups_w(bool count, GroupFn* f, GroupFn* d)
-{
-    *f = count ? k_shadow_groups<W, false, true> : k_shadow_groups<W, false, false>;
-    *d = count ? k_shadow_groups<W, true, true> : k_shadow_groups<W, true, false>;
-}
-
-bool pick_groups(int W, bool count, GroupFn* f, GroupFn* d)
-{
-    switch (W) {
-    case 2: pick_groups_w<2>(count, f, d); return true;
-    case 4: pick_groups_w<4>(count, f, d); return true;
-    case 8: pick_groups_w<8>(count, f, d); return true;
-    }
-    return false;
-}
-
 __global__ void k_iota(uint32_t* p, uint32_t base, int64_t n)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -697,10 +483,6 @@ struct PathmixWs {
     float* cam_t;
     SecRays sh, mr;
     int32_t *sh_hit, *mr_hit;
-    uint32_t *gflag, *gpos, *glead, *gcount;  // shadow-ray groups
-    uint64_t* gmask;
-    void* scan_tmp;
-    size_t scan_bytes;
     void* trace_ws;
     size_t bytes;
 };
@@ -731,67 +513,10 @@ PathmixWs pathmix_ws(const srt_bvh* b, int64_t R, int32_t spp, void* base)
     }
     w.sh_hit = static_cast<int32_t*>(take(4 * (size_t)n));
     w.mr_hit = static_cast<int32_t*>(take(4 * (size_t)n));
-    w.gflag = static_cast<uint32_t*>(take(4 * (size_t)n));
-    w.gpos = static_cast<uint32_t*>(take(4 * (size_t)n));
-    w.glead = static_cast<uint32_t*>(take(4 * (size_t)n));
-    w.gmask = static_cast<uint64_t*>(take(8 * (size_t)n));
-    w.gcount = static_cast<uint32_t*>(take(4));
-    w.scan_bytes = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, w.scan_bytes, (const uint32_t*)nullptr,
-                                           (uint32_t*)nullptr, (int)std::max<int64_t>(n, 1));
-    w.scan_tmp = take(w.scan_bytes);
     TraceWorkspace tw = trace_workspace(b, n, nullptr);
     w.trace_ws = take(tw.bytes);
     w.bytes = off;
     return w;
-}
-
-// Group the shadow rays of each pixel, compact the groups, and trace each
-// group once (fast pass with the LDS stack, then the deep-stack pass).
-srt_status launch_shadow_groups(const srt_bvh* b, const PathmixWs& w, int64_t n,
-                                const srt_trace_opts* o, uint64_t* counters, hipStream_t s)
-{
-    GroupFn fast = nullptr, deep = nullptr;
-    if (!pick_groups(b->W, counters != nullptr, &fast, &deep)) return SRT_ERR_UNSUPPORTED;
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    k_group_mark<<<blocks, 256, 0, s>>>(n, o->spp, w.sh, w.gflag, w.gmask);
-    SRT_HIP_TRY(hipGetLastError());
-    size_t scan_bytes = w.scan_bytes;
-    SRT_HIP_TRY(hipcub::DeviceScan::ExclusiveSum(w.scan_tmp, scan_bytes, w.gflag, w.gpos, (int)n,
-                                                 s));
-    k_group_emit<<<blocks, 256, 0, s>>>(n, w.gflag, w.gpos, w.glead, w.gcount);
-    SRT_HIP_TRY(hipGetLastError());
-    const TraceWorkspace ws = trace_workspace(b, n, w.trace_ws);
-    GroupArgs a{};
-    a.nodes = b->nodes;
-    a.recs = b->recs;
-    a.sh = w.sh;
-    a.lead = w.glead;
-    a.mask = w.gmask;
-    a.count = w.gcount;
-    a.spp = o->spp;
-    a.soff = o->sample_offset;
-    a.purpose = 2u;
-    a.k0 = (uint32_t)o->seed;
-    a.k1 = (uint32_t)(o->seed >> 32);
-    a.out = w.sh_hit;
-    a.counters = reinterpret_cast<unsigned long long*>(counters);
-    a.ctrl = ws.ctrl;
-    a.ovf_list = ws.ovf_list;
-    a.deep_stack = ws.deep_stack;
-    a.deep_cap = deep_stack_cap(b);
-    a.stack_cap = o->stack_limit > 0 ? o->stack_limit : INT_MAX;
-    a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
-    a.depth_mode = o->depth_mode;
-    for (int i = 0; i < 3; ++i) a.depth_axis[i] = o->depth_axis[i];
-    a.r_max = b->r_max;
-    fill_u32(ws.ctrl, 0u, 2, s);
-    // at most one group per slot; blocks past the group count exit at once
-    hipLaunchKernelGGL(fast, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
-    SRT_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(deep, dim3(kDeepThreads / kBlock), dim3(kBlock), 0, s, a);
-    SRT_HIP_TRY(hipGetLastError());
-    return SRT_OK;
 }
 
 }  // namespace
@@ -847,7 +572,7 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
     if (opts->any_hit) return SRT_ERR_INVALID_ARG;
     if (cam->width < 1 || cam->height < 1) return SRT_ERR_INVALID_ARG;
     const int64_t R = (int64_t)cam->width * cam->height;
-    if (R * opts->spp > (int64_t)INT32_MAX) return SRT_ERR_INVALID_ARG;
+    if (R * opts->spp > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;
     if (!workspace || workspace_bytes < srt_pathmix_workspace_size(b, cam, opts->spp))
         return SRT_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -886,23 +611,23 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
     so.n_per_traversal = 1;
     so.sample_offset = opts->sample_offset;
     so.image_width = 0;
-    // shadow rays: one any-hit walk per group of identical rays
-    st = launch_shadow_groups(b, w, n, opts, counters, s);
-    if (st != SRT_OK) return st;
-    // mirror rays
-    srt_rays rr{};
-    rr.count = n;
-    rr.origins = w.mr.o;
-    rr.dirs = w.mr.d;
-    rr.tmin = w.mr.tmin;
-    rr.tmax = w.mr.tmax;
-    rr.ignore_gid = w.mr.ign;
-    rr.ray_ids = w.mr.rid;
-    rr.sample_ids = w.mr.sid;
-    rr.purpose = 3u;
-    so.any_hit = 0;
-    st = launch_trace(b, &rr, &so, nullptr, w.mr_hit, nullptr, counters, w.trace_ws, s);
-    if (st != SRT_OK) return st;
+    for (int pass = 0; pass < 2; ++pass) {
+        const SecRays& sr = pass == 0 ? w.sh : w.mr;
+        srt_rays rr{};
+        rr.count = n;
+        rr.origins = sr.o;
+        rr.dirs = sr.d;
+        rr.tmin = sr.tmin;
+        rr.tmax = sr.tmax;
+        rr.ignore_gid = sr.ign;
+        rr.ray_ids = sr.rid;
+        rr.sample_ids = sr.sid;
+        rr.purpose = pass == 0 ? 2u : 3u;
+        so.any_hit = pass == 0 ? 1 : 0;
+        st = launch_trace(b, &rr, &so, nullptr, pass == 0 ? w.sh_hit : w.mr_hit, nullptr, counters,
+                          w.trace_ws, s);
+        if (st != SRT_OK) return st;
+    }
     k_compose<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(
         R, opts->spp, b->deg, b->sh, w.cd, cg, w.sh, w.mr, w.sh_hit, w.mr_hit, opts->bg[0],
         opts->bg[1], opts->bg[2], rgb, shadow_vis, mirror_gid);

@@ -93,68 +93,27 @@ def test_path_tracer_full_size_sampled(srt):
 
 
 def test_pathmix_many_samples_per_pixel(srt):
-    say("path-tracer mix: 80 spp (two 64-sample groups blocks per pixel), N=8, 24x14")
+    say("path-tracer mix: 80 spp, N=8, 24x14")
     w = si.workload(3, small=True)
     cam = si.look_at((0, 0, 4), (0, 0, 0), 24, 14)
     _pathmix_check(srt, w["scene"], cam, 80, 8, np.arange(24 * 14))
 
 
-def _shadow_rays_host(o, d, cam_gid, cam_t, spp):
-    """The shadow ray of every (pixel, sample), built with the same FP32
-    operations, in the same order, as the spawn step of the path-tracer mix."""
-    f = np.float32
-    P = len(o)
-    g = cam_gid.reshape(P, spp)
-    tg = np.where(g >= 0, cam_t.reshape(P, spp), np.inf).astype(f)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        tt = (f(si.PLANE_Y) - o[:, 1]) / d[:, 1]
-    tp = np.where((d[:, 1] < 0) & (tt > 0), tt, np.inf).astype(f)[:, None]
-    on_g = (g >= 0) & (tg <= tp)
-    on_p = ~on_g & np.isfinite(tp)
-    t = np.where(on_g, tg, tp).astype(f)
-    Pt = (o[:, None, :] + (t[..., None] * d[:, None, :]).astype(f)).astype(f)
-    Pt[..., 1] = np.where(on_p, f(si.PLANE_Y), Pt[..., 1])
-    v = (np.asarray(si.LIGHT_POS, f)[None, None, :] - Pt).astype(f)
-    ln = np.sqrt(((v[..., 0] * v[..., 0] + v[..., 1] * v[..., 1]).astype(f)
-                  + v[..., 2] * v[..., 2]).astype(f)).astype(f)
-    dirs = (v / ln[..., None]).astype(f)
-    live = on_g | on_p
-    ign = np.where(on_g, g, -1).astype(np.int32)
-    return Pt, dirs, ln, ign, live
-
-
-@pytest.mark.parametrize("stack_limit", [0, 1])
-def test_grouped_shadow_rays_equal_single_walks(srt, stack_limit):
-    say(f"grouped shadow rays vs one any-hit walk per sample, stack limit {stack_limit}")
+def test_pathmix_deep_stack_is_exact(srt):
+    say("path-tracer mix through the deep-stack pass (stack limit 1)")
     w = si.workload(3, small=True)
     cam = si.look_at((0.3, -0.2, 4), (0, 0, 0), 48, 27)
-    spp = 8
     bvh = srt.srt_build_bvh(device_scene(w["scene"]), 4, 2)
-    cnt = srt.new_counters()
-    res = srt.srt_trace_pathmix(bvh, cam, seed=3, spp=spp, n_per_traversal=4, sample_offset=5,
-                                light=si.LIGHT_POS, plane_y=si.PLANE_Y,
-                                tmin_secondary=si.SECONDARY_TMIN, stack_limit=stack_limit,
-                                counters=cnt)
-    torch.cuda.synchronize()
-    g = {k: to_np(v) for k, v in res.items()}
-    o, d = si.camera_rays(cam)
-    Pt, dirs, ln, ign, live = _shadow_rays_host(o, d, g["cam_gid"], g["cam_t"], spp)
-    np.testing.assert_array_equal(live, g["shadow_vis"] != 255)
-    P = len(o)
-    sel = live.reshape(-1)
-    pix = np.repeat(np.arange(P, dtype=np.uint32), spp)[sel]
-    smp = np.tile(np.arange(spp, dtype=np.uint32), P)[sel]
-    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    single = srt.srt_trace_forward(
-        bvh, cu(Pt.reshape(-1, 3)[sel]), cu(dirs.reshape(-1, 3)[sel]),
-        tmin=cu(np.full(sel.sum(), si.SECONDARY_TMIN, np.float32)), tmax=cu(ln.reshape(-1)[sel]),
-        ignore_gid=cu(ign.reshape(-1)[sel]), ray_ids=cu(pix), sample_ids=cu(smp), purpose=2,
-        seed=3, spp=1, n_per_traversal=1, sample_offset=5, any_hit=True, want_rgb=False)
-    torch.cuda.synchronize()
-    vis_single = (to_np(single["hit_gid"])[:, 0] < 0).astype(np.uint8)
-    np.testing.assert_array_equal(g["shadow_vis"].reshape(-1)[sel], vis_single)
-    assert (vis_single == 0).any() and (vis_single == 1).any()
-    c = srt.counters_dict(cnt)
-    assert c["lost"] == 0
-    if stack_limit:
-        assert c["deep"] > 0
+    out = []
+    for lim in (0, 1):
+        cnt = srt.new_counters()
+        res = srt.srt_trace_pathmix(bvh, cam, seed=3, spp=8, n_per_traversal=4, sample_offset=5,
+                                    light=si.LIGHT_POS, plane_y=si.PLANE_Y,
+                                    tmin_secondary=si.SECONDARY_TMIN, stack_limit=lim,
+                                    counters=cnt)
+        torch.cuda.synchronize()
+        out.append(({k: to_np(v) for k, v in res.items()}, srt.counters_dict(cnt)))
+    (a, ca), (b, cb) = out
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+    assert cb["deep"] > 0 and cb["lost"] == 0 and ca["deep"] == 0
