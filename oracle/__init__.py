@@ -265,11 +265,16 @@ def composite_grad(rec: Records, rays: Rays, dL, bg=(0.0, 0.0, 0.0), threads=Non
 
 
 def estimator_grad(rec: Records, rays: Rays, dL, spp=1, seed=0, purpose=0,
-                   bg=(0.0, 0.0, 0.0), threads=None):
-    """The stochastic gradient estimator on the realisation ``trace`` draws."""
+                   bg=(0.0, 0.0, 0.0), threads=None, estimator="plain"):
+    """The stochastic gradient estimator on the realisation ``trace`` draws;
+    estimator="rb" averages each candidate's term over its own acceptance
+    number (see srto_estimator_grad_rb)."""
     lib = _load()
     g = _grad_bufs(rec)
-    lib.srto_estimator_grad(C.c_int64(rec.G), _p(rec.mu), _p(rec.M), _p(rec.op),
+    if estimator not in ("plain", "rb"):
+        raise ValueError(estimator)
+    fn = lib.srto_estimator_grad if estimator == "plain" else lib.srto_estimator_grad_rb
+    fn(C.c_int64(rec.G), _p(rec.mu), _p(rec.M), _p(rec.op),
                             C.c_int(rec.deg), _p(rec._sh), _p(rec._ls), _p(rec._q),
                             _p(rec._lg), C.c_int64(rays.count), _p(rays.o), _p(rays.d),
                             _p(rays.tmin), _p(rays.tmax), _p(rays.ignore_gid),

@@ -826,6 +826,104 @@ void srto_estimator_grad(int64_t G, const double* mu, const double* M, const dou
     }
 }
 
+/* A lower-variance form of the same estimator (the paper leaves lower-
+ * variance gradient estimators open, Sec. 7): each candidate's term is
+ * averaged over its own acceptance number. With the candidates in depth
+ * order, candidate k's term in the estimator above is
+ *   [all j < k rejected] [u_k >= alpha_k] <dL, c_k - X_k> / (1 - alpha_k),
+ * X_k the colour of the first accepted candidate behind k (bg if none),
+ * which does not depend on u_k. Its mean over u_k is
+ *   [all j < k rejected] <dL, c_k - X_k>,
+ * still with expectation T_k (c_k - B_k) = dL/dalpha_k and, by the
+ * Rao-Blackwell theorem, no larger variance. On a sample whose first and
+ * second accepted candidates are a and a2: every k in front of a gets
+ * <dL, c_k - c_a>, a gets <dL, c_a - c_a2> (c_a2 = bg if a has no accepted
+ * candidate behind it), and the colour gradient still goes to a. */
+void srto_estimator_grad_rb(int64_t G, const double* mu, const double* M, const double* op,
+                            int deg, const float* sh, const float* log_scales,
+                            const float* quats, const float* logits, int64_t R,
+                            const float* o, const float* d, const float* tmin,
+                            const float* tmax, const int32_t* ignore_gid,
+                            const uint32_t* ray_id, const uint32_t* sample_base, int32_t spp,
+                            uint64_t seed, uint32_t purpose, const double* bg,
+                            const double* dL, double* g_means, double* g_ls, double* g_quats,
+                            double* g_logits, double* g_sh, int threads)
+{
+    rays_t RR = {R, o, d, tmin, tmax, ignore_gid, ray_id, sample_base};
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#endif
+#pragma omp parallel
+    {
+        sorted_t S = {{0, 0, 0}, 0, 0};
+        double* sa = 0;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < R; ++i) {
+            double t0, t1;
+            int32_t ign;
+            uint32_t rid, sb;
+            ray_get(&RR, i, &t0, &t1, &ign, &rid, &sb);
+            double Y[16], dir[3] = {d[3 * i], d[3 * i + 1], d[3 * i + 2]};
+            srto_sh_basis(deg, dir, Y);
+            sorted_build(&S, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
+            int64_t n = S.cl.n;
+            if (n == 0) continue;
+            if (cap < n) {
+                cap = n;
+                sa = (double*)realloc(sa, (size_t)cap * sizeof(double));
+            }
+            memset(sa, 0, (size_t)n * sizeof(double));
+            const double* g = dL + 3 * i;
+            for (int32_t s = 0; s < spp; ++s) {
+                uint32_t sample = sb + (uint32_t)s;
+                /* first and second accepted candidates in depth order */
+                int64_t a = -1, a2 = -1;
+                for (int64_t k = 0; k < n; ++k) {
+                    double u = accept_u(seed, rid, sample, (uint32_t)S.cl.v[k].gid, purpose);
+                    if (u < S.cl.v[k].alpha) {
+                        if (a < 0) {
+                            a = k;
+                        } else {
+                            a2 = k;
+                            break;
+                        }
+                    }
+                }
+                double X[3], X2[3];
+                for (int ch = 0; ch < 3; ++ch) {
+                    X[ch] = a >= 0 ? S.c[3 * a + ch] : bg[ch];
+                    X2[ch] = a2 >= 0 ? S.c[3 * a2 + ch] : bg[ch];
+                }
+                int64_t front = a >= 0 ? a : n;
+                for (int64_t k = 0; k < front; ++k) {
+                    double v = 0.0;
+                    for (int ch = 0; ch < 3; ++ch) v += g[ch] * (S.c[3 * k + ch] - X[ch]);
+                    sa[k] += v / (double)spp;
+                }
+                if (a >= 0) {
+                    double v = 0.0;
+                    for (int ch = 0; ch < 3; ++ch) v += g[ch] * (X[ch] - X2[ch]);
+                    sa[a] += v / (double)spp;
+                    double gc[3] = {g[0] / spp, g[1] / spp, g[2] / spp};
+                    chain_colour(deg, S.cl.v[a].gid, Y, S.pre + 3 * a, gc, g_sh);
+                }
+            }
+            for (int64_t k = 0; k < n; ++k) {
+                if (sa[k] == 0.0) continue;
+                isect_t r;
+                regeo(mu, M, S.cl.v[k].gid, o + 3 * i, d + 3 * i, &r);
+                chain_alpha(S.cl.v[k].gid, sa[k], S.cl.v[k].alpha, &r, log_scales, quats,
+                            logits, g_means, g_ls, g_quats, g_logits);
+            }
+        }
+        free(S.cl.v);
+        free(S.c);
+        free(S.pre);
+        free(sa);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Path-tracer mix: Gaussians inside a renderer with shadows and mirror      */
 /* reflections (Sec. 1 and Sec. 5: secondary rays go through the same       */

@@ -496,6 +496,91 @@ def test_estimator_gradient_single_sample_by_hand():
                 assert g["opacity_logits"][k] == 0.0
 
 
+def test_rb_estimator_single_sample_by_hand():
+    """The Rao-Blackwellised estimator on one ray and one sample: front
+    candidates get <dL, c_k - c_a> (no 1 / (1 - alpha_k)), the first accepted
+    a gets <dL, c_a - c_a2> with a2 the next accepted behind it (bg if none),
+    the colour gradient stays on a."""
+    sc = _line_scene([1.0, 1.5, 2.0, 2.5], [0.4, 0.5, 0.6, 0.7])
+    sc.sh = np.zeros((4, 1, 3), F32)
+    sc.sh[:, 0, :] = ((np.array([0.1, 0.3, 0.5, 0.9]) - 0.5) / si.SH_C0)[:, None]
+    rec = oracle.Records(sc, round_f32=False)
+    rays = oracle.Rays([[0, 0, 0]], [[0, 0, 1]], ray_id=[3])
+    dL = np.array([[1.0, -0.5, 0.25]])
+    bg = np.array([0.05, 0.1, 0.2])
+    c = 0.5 + sc.sh[:, 0, :].astype(np.float64) * oracle.sh_basis(0, [[0, 0, 1]])[0, 0]
+    seen = set()
+    for seed in range(16):
+        g = oracle.estimator_grad(rec, rays, dL, spp=1, seed=seed, bg=bg, estimator="rb")
+        us = [oracle.accept_u(seed, 3, 0, k, 0) for k in range(4)]
+        acc = [k for k in range(4) if us[k] < rec.op[k]]
+        a = acc[0] if acc else None
+        a2 = acc[1] if len(acc) > 1 else None
+        seen.add((a, a2))
+        X = c[a] if a is not None else bg
+        X2 = c[a2] if a2 is not None else bg
+        for k in range(4):
+            if a is None or k < a:
+                s_alpha = dL[0] @ (c[k] - X)
+            elif k == a:
+                s_alpha = dL[0] @ (X - X2)
+            else:
+                s_alpha = 0.0
+            expect = s_alpha * rec.op[k] * (1 - rec.op[k])  # d alpha / d logit on the axis
+            assert abs(g["opacity_logits"][k] - expect) < 1e-12, (seed, k)
+        if a is not None:
+            np.testing.assert_allclose(g["sh"][a, 0], dL[0] * si.SH_C0, atol=1e-12)
+    assert len(seen) >= 4  # several different (a, a2) realisations were covered
+
+
+def test_rb_estimator_is_exact_on_single_candidate_rays():
+    """With one candidate per ray the averaged term is <dL, c - bg> whatever
+    the sample draws, i.e. the exact gradient of the composite for every
+    parameter that reaches alpha."""
+    means = [[x, y, 0.0] for x in (-0.6, 0.0, 0.6) for y in (-0.6, 0.0, 0.6)]
+    n = len(means)
+    rng = np.random.default_rng(8)
+    sc = _scene(means, np.log(rng.uniform(0.03, 0.08, (n, 3))), rng.standard_normal((n, 4)),
+                rng.uniform(-1.5, 1.5, n), rng.normal(0, 0.3, (n, 4, 3)), 1)
+    rec = oracle.Records(sc)
+    cam = si.look_at((0.05, 0.02, 3), (0, 0, 0), 24, 24, vfov_deg=35)
+    o, d = si.camera_rays(cam)
+    rays = oracle.Rays(o, d)
+    assert oracle.composite(rec, rays)["n_cand"].max() == 1
+    assert (oracle.composite(rec, rays)["n_cand"] == 1).sum() > 20
+    bg = np.array([0.3, 0.2, 0.1])
+    dL = rng.normal(0, 1, (len(o), 3))
+    exact = oracle.composite_grad(rec, rays, dL, bg)
+    for seed in (0, 1):
+        g = oracle.estimator_grad(rec, rays, dL, spp=3, seed=seed, bg=bg, estimator="rb")
+        for name in ("means", "log_scales", "quats", "opacity_logits"):
+            np.testing.assert_allclose(g[name], exact[name], rtol=1e-9,
+                                       atol=1e-12 * max(1.0, np.abs(exact[name]).max()))
+
+
+def test_rb_estimator_unbiased_with_lower_variance():
+    sc = _grad_scene()
+    o, d = _grad_rays()
+    bg = np.array([0.1, 0.2, 0.3])
+    rng = np.random.default_rng(6)
+    dL = rng.normal(0, 1, (o.shape[0], 3))
+    rec = oracle.Records(sc)
+    rays = oracle.Rays(o, d)
+    exact = oracle.composite_grad(rec, rays, dL, bg)
+    runs = {e: [oracle.estimator_grad(rec, rays, dL, spp=8, seed=s, bg=bg, estimator=e)
+                for s in range(60)] for e in ("plain", "rb")}
+    var = {}
+    for e, rs in runs.items():
+        var[e] = 0.0
+        for name in ("means", "log_scales", "quats", "opacity_logits"):
+            est = np.stack([r[name] for r in rs])
+            m, se = est.mean(0), est.std(0, ddof=1) / math.sqrt(len(rs))
+            tol = 5 * se + 1e-3 * np.abs(exact[name]) + 1e-9
+            assert np.all(np.abs(m - exact[name]) <= tol), (e, name)
+            var[e] += float(est.var(0, ddof=1).sum())
+    assert var["rb"] < 0.7 * var["plain"], var
+
+
 # --------------------------------------------------------------------------
 # Path-tracer mix
 # --------------------------------------------------------------------------
