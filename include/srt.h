@@ -196,7 +196,23 @@ typedef struct {
  *                 rays are the pixels of a row-major image of this width
  *                 (count must be a multiple of it, else SRT_ERR_INVALID_ARG)
  *                 and each wave traces one 8x8 pixel tile, which keeps its
- *                 lanes on neighbouring rays. Results do not depend on it.  */
+ *                 lanes on neighbouring rays. Results do not depend on it.
+ * persistent      0: one lane per ray. 1: work-stealing waves (one wave per
+ *                 workgroup, as many as fit on the GPU) loop over the rays; a
+ *                 lane runs all passes of its ray, and once refill_threshold
+ *                 lanes of a wave are idle the wave takes that many new rays
+ *                 with one atomic, so short walks do not wait for the
+ *                 longest walk of their wave. Results do not depend on it.
+ * refill_threshold idle lanes (1..64) that trigger a refill; 0 = 16.
+ * estimator       backward only. 0: per sample, every valid candidate k in
+ *                 front of the result a gets <g, c_k - X> / (1 - alpha_k) on
+ *                 its alpha (X = c_a, bg on a miss). 1: the same terms
+ *                 averaged over each candidate's own acceptance number:
+ *                 k in front of a gets <g, c_k - c_a>, and a gets
+ *                 <g, c_a - c_a2>, a2 the sample's next accepted candidate
+ *                 behind a (bg if none; the walk goes on to find it). Both are
+ *                 unbiased for the exact composite's gradient; 1 has no larger
+ *                 variance (Rao-Blackwell). Colour gradients are the same.   */
 typedef struct {
     uint64_t seed;
     int32_t spp;
@@ -208,6 +224,9 @@ typedef struct {
     int32_t depth_mode;
     float depth_axis[3];
     int32_t image_width;
+    int32_t persistent;
+    int32_t refill_threshold;
+    int32_t estimator;
 } srt_trace_opts;
 
 /* Counters accumulated (+=) into a device uint64 array of SRT_NUM_COUNTERS
@@ -326,7 +345,10 @@ size_t srt_pathmix_workspace_size(const srt_bvh* bvh, const srt_camera* cam, int
  * 0 occluded, 255 no shadow ray) [H*W,spp], mirror_gid (-2 no mirror ray,
  * -1 miss) [H*W,spp]: device or null. counters as srt_trace_forward; its
  * SRT_CNT_RAY_SAMPLES entry counts camera samples plus secondary rays.
- * opts->any_hit must be 0. Errors: INVALID_ARG, WORKSPACE, HIP. */
+ * opts->any_hit must be 0. Camera rays are traced as an image (8x8 tiles);
+ * the any-hit shadow rays always run on work-stealing waves (see
+ * srt_trace_opts.persistent); camera and mirror rays follow opts->persistent.
+ * Errors: INVALID_ARG, WORKSPACE, HIP. */
 srt_status srt_trace_pathmix(const srt_bvh* bvh, const srt_camera* cam, uint32_t ray_id_base,
                              const srt_trace_opts* opts, const srt_pathmix_opts* pm,
                              float* rgb, int32_t* cam_gid, float* cam_t, uint8_t* shadow_vis,

@@ -143,10 +143,19 @@ def counters_dict(c):
     return {n: int(x) for n, x in zip(COUNTER_NAMES, v)}
 
 
+ESTIMATORS = {"plain": 0, "rb": 1}
+
+
 def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode=0,
-          depth_axis=(0.0, 0.0, 0.0), image_width=0):
+          depth_axis=(0.0, 0.0, 0.0), image_width=0, persistent=False, refill_threshold=0,
+          estimator="plain"):
     o = _lib.SrtTraceOpts()
+    if estimator not in ESTIMATORS:
+        raise ValueError(f"estimator must be one of {sorted(ESTIMATORS)}")
+    o.estimator = ESTIMATORS[estimator]
     o.image_width = int(image_width)
+    o.persistent = 1 if persistent else 0
+    o.refill_threshold = int(refill_threshold)
     o.depth_mode = int(depth_mode)
     for i in range(3):
         o.depth_axis[i] = float(depth_axis[i])
@@ -165,17 +174,19 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
                       ray_ids=None, sample_ids=None, purpose=0, seed=0, spp=1,
                       n_per_traversal=1, sample_offset=0, bg=(0.0, 0.0, 0.0), any_hit=False,
                       stack_limit=0, depth_mode=0, depth_axis=(0.0, 0.0, 0.0), image_width=0,
-                      want_rgb=True, want_hits=True, counters=None, out=None, workspace=None):
+                      persistent=False, refill_threshold=0, want_rgb=True, want_hits=True,
+                      counters=None, out=None, workspace=None):
     """Trace rays (device tensors [R,3]); returns dict(rgb [R,3], hit_gid [R,spp],
     hit_t [R,spp]). image_width > 0 declares the rays a row-major image of that
-    width (traced in 8x8 tiles; results are unchanged)."""
+    width (traced in 8x8 tiles); persistent=True runs work-stealing waves
+    (refilled once refill_threshold lanes are idle). Neither changes results."""
     lib = _lib.load()
     R = int(origins.shape[0])
     dev = origins.device
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
     opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode,
-                 depth_axis, image_width)
+                 depth_axis, image_width, persistent, refill_threshold)
     res = dict(out or {})
     if want_rgb and "rgb" not in res:
         res["rgb"] = torch.empty((R, 3), dtype=torch.float32, device=dev)
@@ -195,9 +206,12 @@ def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t
                        tmin=None, tmax=None, ignore_gid=None, ray_ids=None, sample_ids=None,
                        purpose=0, seed=0, spp=1, n_per_traversal=1, sample_offset=0,
                        bg=(0.0, 0.0, 0.0), depth_mode=0, depth_axis=(0.0, 0.0, 0.0),
-                       image_width=0, grads=None, counters=None, workspace=None):
+                       image_width=0, estimator="plain", grads=None, counters=None,
+                       workspace=None):
     """Accumulate gradients of sum(grad_rgb * E[rgb]) into `grads` (a dict of
-    tensors shaped like the scene's; zeros are allocated when absent)."""
+    tensors shaped like the scene's; zeros are allocated when absent).
+    estimator: "plain" (per-sample score terms) or "rb" (each term averaged
+    over its own acceptance number; no larger variance)."""
     lib = _lib.load()
     sc = bvh.scene
     R = int(origins.shape[0])
@@ -208,7 +222,7 @@ def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
     opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0, depth_mode, depth_axis,
-                 image_width)
+                 image_width, estimator=estimator)
     need = lib.srt_backward_workspace_size(bvh.handle, R)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -257,15 +271,17 @@ class TraceFn(torch.autograd.Function):
                                n_per_traversal=cfg.get("n_per_traversal", 1),
                                sample_offset=cfg.get("sample_offset", 0),
                                bg=cfg.get("bg", (0.0, 0.0, 0.0)),
-                               image_width=cfg.get("image_width", 0))
+                               image_width=cfg.get("image_width", 0),
+                               estimator=cfg.get("estimator", "plain"))
         return (g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None, None,
                 None)
 
 
 def render(means, log_scales, quats, opacity_logits, sh, origins, dirs, **cfg):
     """Differentiable stochastic render (see TraceFn); cfg keys: sh_degree, spp,
-    n_per_traversal, seed, sample_offset, bg, width, leaf_size, image_width, and bvh
-    (a handle of the same Gaussians to refit instead of building a new one)."""
+    n_per_traversal, seed, sample_offset, bg, width, leaf_size, image_width,
+    estimator ("plain" or "rb", see srt_trace_backward), and bvh (a handle of
+    the same Gaussians to refit instead of building a new one)."""
     return TraceFn.apply(means, log_scales, quats, opacity_logits, sh, origins, dirs, cfg)
 
 
@@ -295,15 +311,16 @@ def srt_camera_rays(cam, device="cuda"):
 
 def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_traversal=1,
                       sample_offset=0, bg=(0.0, 0.0, 0.0), light=(5.0, 5.0, 5.0), plane_y=-2.5,
-                      tmin_secondary=1e-4, stack_limit=0, want_hits=True, counters=None,
-                      workspace=None, out=None):
+                      tmin_secondary=1e-4, stack_limit=0, persistent=False, refill_threshold=0,
+                      want_hits=True, counters=None, workspace=None, out=None):
     """Path-tracer mix of one camera; returns dict(rgb [, cam_gid, cam_t,
     shadow_vis, mirror_gid])."""
     lib = _lib.load()
     dev = bvh.scene.means.device
     R = int(cam.width) * int(cam.height)
     c = _camera(cam)
-    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, stack_limit)
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, stack_limit,
+                 persistent=persistent, refill_threshold=refill_threshold)
     pm = _lib.SrtPathmixOpts()
     for i in range(3):
         pm.light[i] = float(light[i])

@@ -40,7 +40,9 @@ class SrtTraceOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("spp", C.c_int32), ("n_per_traversal", C.c_int32),
                 ("sample_offset", C.c_uint32), ("bg", C.c_float * 3), ("any_hit", C.c_int32),
                 ("stack_limit", C.c_int32), ("depth_mode", C.c_int32),
-                ("depth_axis", C.c_float * 3), ("image_width", C.c_int32)]
+                ("depth_axis", C.c_float * 3), ("image_width", C.c_int32),
+                ("persistent", C.c_int32), ("refill_threshold", C.c_int32),
+                ("estimator", C.c_int32)]
 
 
 class SrtCamera(C.Structure):

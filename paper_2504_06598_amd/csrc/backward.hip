@@ -74,6 +74,7 @@ struct BwdArgs {
     float depth_axis[3];
     float r_max;
     int32_t img_w;  // > 0: rays are a row-major image of this width, walked in 8x8 tiles
+    const int32_t* leaf_pos;  // leaf position of each Gaussian id
 };
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v)
@@ -118,7 +119,7 @@ __device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, con
     }
 }
 
-template <int W, int N, bool COUNT>
+template <int W, int N, bool COUNT, bool RB>
 __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
 {
     __shared__ int32_t lds[kLdsEntries * kBlock];
@@ -197,30 +198,44 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     }
                 }
                 // <g, X> of each sample's result colour X (bg on a miss), and the
-                // farthest result key; only these scalars are live during the walk
+                // farthest key the walk has to reach; only scalars are live during it.
+                // RB: a hit sample also searches its second accepted candidate
+                // (tb, gb) behind its first, so its far key is that one; a miss
+                // sample's front is every candidate.
                 float gx[N];
+                float tb[RB ? N : 1];
+                int32_t gb[RB ? N : 1];
                 float wt = -INFINITY;
                 int32_t wg = INT_MIN;
-                {
 #pragma unroll
-                    for (int k = 0; k < N; ++k) {
-                        gx[k] = 0.0f;
-                        if (k >= n_act) continue;
-                        if (ga[k] != 0x7FFFFFFF) {
-                            const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, ga[k], Y));
-                            gx[k] = g0 * c.x + g1 * c.y + g2 * c.z;
-                        } else {
-                            gx[k] = g0 * a.bg[0] + g1 * a.bg[1] + g2 * a.bg[2];
+                for (int k = 0; k < N; ++k) {
+                    gx[k] = 0.0f;
+                    if constexpr (RB) {
+                        tb[k] = -INFINITY;
+                        gb[k] = INT_MIN;
+                    }
+                    if (k >= n_act) continue;
+                    if (ga[k] != 0x7FFFFFFF) {
+                        const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, ga[k], Y));
+                        gx[k] = g0 * c.x + g1 * c.y + g2 * c.z;
+                        if constexpr (RB) {
+                            tb[k] = INFINITY;
+                            gb[k] = 0x7FFFFFFF;
                         }
-                        if (key_less(wt, wg, ta[k], ga[k])) {
-                            wt = ta[k];
-                            wg = ga[k];
-                        }
+                    } else {
+                        gx[k] = g0 * a.bg[0] + g1 * a.bg[1] + g2 * a.bg[2];
+                    }
+                    const float fk = RB && ga[k] != 0x7FFFFFFF ? tb[k] : ta[k];
+                    const int32_t fg = RB && ga[k] != 0x7FFFFFFF ? gb[k] : ga[k];
+                    if (key_less(wt, wg, fk, fg)) {
+                        wt = fk;
+                        wg = fg;
                     }
                 }
                 n_samples += (uint32_t)n_act;
                 ++n_trav;
                 float tcut = fminf(cut_after(wt), tmax_f);
+                const uint32_t s0 = sbase + (uint32_t)(pass * N);
                 auto visit = [&](uint32_t ri) -> bool {
                     const Record r = load_record(a.recs, ri);
                     if (dc.mode == 0 ? sphere_reject(r, rr, tmin_f, tcut)
@@ -232,20 +247,68 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
                     const float t32 = (float)t;
                     if (!key_less(t32, r.gid, wt, wg)) return false;
-                    int nf = 0;
+                    double alpha_d = 0.0;
+                    if constexpr (RB) alpha_d = (double)r.opacity * exp(-0.5 * q);
+                    int nf = 0, na = 0;
                     float xs = 0.0f;
+                    bool found = false;
+                    uint4 w = make_uint4(0, 0, 0, 0);
+                    uint32_t grp = 0xFFFFFFFFu;
 #pragma unroll
-                    for (int k = 0; k < N; ++k)
-                        if (k < n_act && key_less(t32, r.gid, ta[k], ga[k])) {
+                    for (int k = 0; k < N; ++k) {
+                        if (k >= n_act) continue;
+                        if (key_less(t32, r.gid, ta[k], ga[k])) {
                             ++nf;
                             xs += gx[k];
+                        } else if constexpr (RB) {
+                            if (r.gid == ga[k] && t32 == ta[k]) {
+                                ++na;  // the sample's first accepted candidate
+                            } else if (key_less(t32, r.gid, tb[k], gb[k])) {
+                                // behind the first accepted: is it a nearer second one?
+                                const uint32_t smp = s0 + (uint32_t)k;
+                                if ((smp >> 2) != grp) {
+                                    grp = smp >> 2;
+                                    w = philox4x32_10(
+                                        make_uint4(rid, grp, (uint32_t)r.gid, a.purpose), a.k0,
+                                        a.k1);
+                                    ++n_philox;
+                                }
+                                if (u_of_word(word_of(w, smp & 3u)) < alpha_d) {
+                                    tb[k] = t32;
+                                    gb[k] = r.gid;
+                                    found = true;
+                                }
+                            }
                         }
-                    if (nf == 0) return false;
+                    }
+                    if constexpr (RB) {
+                        if (found) {
+                            wt = -INFINITY;
+                            wg = INT_MIN;
+#pragma unroll
+                            for (int k = 0; k < N; ++k) {
+                                if (k >= n_act) continue;
+                                const float fk = ga[k] != 0x7FFFFFFF ? tb[k] : ta[k];
+                                const int32_t fg = ga[k] != 0x7FFFFFFF ? gb[k] : ga[k];
+                                if (key_less(wt, wg, fk, fg)) {
+                                    wt = fk;
+                                    wg = fg;
+                                }
+                            }
+                            tcut = fminf(cut_after(wt), tmax_f);
+                        }
+                    }
+                    if (nf == 0 && na == 0) return false;
                     ++n_front;
-                    const float alpha = (float)((double)r.opacity * exp(-0.5 * q));
+                    if constexpr (!RB) alpha_d = (double)r.opacity * exp(-0.5 * q);
+                    const float alpha = (float)alpha_d;
                     const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, r.gid, Y));
                     const float gc = g0 * c.x + g1 * c.y + g2 * c.z;
-                    const float s_alpha = ((float)nf * gc - xs) * inv_spp / (1.0f - alpha);
+                    // plain: <g, c_k - X> / (1 - alpha_k) per front sample; RB: the
+                    // same without the division, and <g, c_a> for a sample's first
+                    // accepted a (its -<g, X2> part is added after the walk)
+                    const float s_alpha = RB ? ((float)(nf + na) * gc - xs) * inv_spp
+                                             : ((float)nf * gc - xs) * inv_spp / (1.0f - alpha);
                     const float sa = s_alpha * alpha;
                     const float p0 = (float)p[0], p1 = (float)p[1], p2 = (float)p[2];
                     const float v[kAccVals] = {sa,           sa * p0,      sa * p1,
@@ -258,6 +321,43 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                 const int res = walk<W>(nodes, rr, tcut, dc.node_slack, stk, a.max_steps, n_nodes,
                                         n_prims, visit);
                 if (res == kWalkOverflow) ++n_lost;
+                if constexpr (RB) {
+                    // -<g, X2> on the alpha of each sample's first accepted a (X2 the
+                    // colour of its second accepted, bg if none), samples sharing a merged
+                    if (res != kWalkOverflow) {
+#pragma unroll
+                        for (int k = 0; k < N; ++k) {
+                            if (k >= n_act || ga[k] == 0x7FFFFFFF) continue;
+                            bool first = true;
+                            float s2 = 0.0f;
+#pragma unroll
+                            for (int j = 0; j < N; ++j) {
+                                if (j >= n_act || ga[j] != ga[k]) continue;
+                                if (j < k) first = false;
+                                float x2;
+                                if (gb[j] != 0x7FFFFFFF) {
+                                    const float3 c2 = clamp0(sh_colour_pre(a.sh, a.deg, gb[j], Y));
+                                    x2 = g0 * c2.x + g1 * c2.y + g2 * c2.z;
+                                } else {
+                                    x2 = g0 * a.bg[0] + g1 * a.bg[1] + g2 * a.bg[2];
+                                }
+                                s2 -= x2;
+                            }
+                            if (!first) continue;
+                            const Record r = load_record(a.recs, (uint32_t)a.leaf_pos[ga[k]]);
+                            double tm, q, p[3];
+                            isect_tqp(r, rr, tm, q, p);
+                            const float alpha = (float)((double)r.opacity * exp(-0.5 * q));
+                            const float sa = s2 * inv_spp * alpha;
+                            const float p0 = (float)p[0], p1 = (float)p[1], p2 = (float)p[2];
+                            const float v[kAccVals] = {sa,           sa * p0,      sa * p1,
+                                                       sa * p2,      sa * p0 * p0, sa * p1 * p1,
+                                                       sa * p2 * p2, sa * p0 * p1, sa * p0 * p2,
+                                                       sa * p1 * p2};
+                            table_add(table, a.acc, r.gid, v);
+                        }
+                    }
+                }
                 // colour gradient of each accepted result, samples sharing a Gaussian merged
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
@@ -367,24 +467,31 @@ __global__ void k_chain(int64_t G, const float* __restrict__ acc, const float* _
 
 using BwdFn = void (*)(BwdArgs);
 
-template <int W, bool C>
+template <int W, bool C, bool RB>
 BwdFn pick_n(int N)
 {
     switch (N) {
-    case 1: return k_backward<W, 1, C>;
-    case 2: return k_backward<W, 2, C>;
-    case 4: return k_backward<W, 4, C>;
-    case 8: return k_backward<W, 8, C>;
+    case 1: return k_backward<W, 1, C, RB>;
+    case 2: return k_backward<W, 2, C, RB>;
+    case 4: return k_backward<W, 4, C, RB>;
+    case 8: return k_backward<W, 8, C, RB>;
     }
     return nullptr;
 }
 
-BwdFn pick(int W, int N, bool count)
+template <int W>
+BwdFn pick_w(int N, bool count, bool rb)
+{
+    if (rb) return count ? pick_n<W, true, true>(N) : pick_n<W, false, true>(N);
+    return count ? pick_n<W, true, false>(N) : pick_n<W, false, false>(N);
+}
+
+BwdFn pick(int W, int N, bool count, bool rb)
 {
     switch (W) {
-    case 2: return count ? pick_n<2, true>(N) : pick_n<2, false>(N);
-    case 4: return count ? pick_n<4, true>(N) : pick_n<4, false>(N);
-    case 8: return count ? pick_n<8, true>(N) : pick_n<8, false>(N);
+    case 2: return pick_w<2>(N, count, rb);
+    case 4: return pick_w<4>(N, count, rb);
+    case 8: return pick_w<8>(N, count, rb);
     }
     return nullptr;
 }
@@ -437,6 +544,7 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     if (opts->depth_mode != 0 && opts->depth_mode != 1) return SRT_ERR_INVALID_ARG;
     if (opts->image_width < 0) return SRT_ERR_INVALID_ARG;
     if (opts->image_width > 0 && rays->count % opts->image_width != 0) return SRT_ERR_INVALID_ARG;
+    if (opts->estimator != 0 && opts->estimator != 1) return SRT_ERR_INVALID_ARG;
     const int N = opts->n_per_traversal;
     if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
     if (rays->count < 0 || rays->count > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;
@@ -485,7 +593,8 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     for (int i = 0; i < 3; ++i) a.depth_axis[i] = opts->depth_axis[i];
     a.r_max = b->r_max;
     a.img_w = opts->image_width;
-    BwdFn fn = pick(b->W, N, counters != nullptr);
+    a.leaf_pos = b->leaf_pos;
+    BwdFn fn = pick(b->W, N, counters != nullptr, opts->estimator == 1);
     if (!fn) return SRT_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(fn, dim3(ws.threads / kBlock), dim3(kBlock), 0, s, a);
     SRT_HIP_TRY(hipGetLastError());

@@ -418,13 +418,15 @@ __global__ void k_single_leaf(int64_t G, const float* __restrict__ lo, const flo
 }
 
 __global__ void k_permute(int64_t G, const uint32_t* __restrict__ order, const Record* __restrict__ in,
-                          Record* __restrict__ out, int32_t* __restrict__ leaf_order)
+                          Record* __restrict__ out, int32_t* __restrict__ leaf_order,
+                          int32_t* __restrict__ leaf_pos)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= G) return;
     const uint32_t g = order[k];
     out[k] = in[g];
     leaf_order[k] = (int32_t)g;
+    leaf_pos[g] = (int32_t)k;
 }
 
 __global__ void k_unpermute_records(int64_t G, const Record* __restrict__ recs, float* mu, float* M,
@@ -590,7 +592,8 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
     SRT_HIP_TRY(hipMalloc(&b->box_hi, sizeof(float) * 3 * (size_t)G));
     SRT_HIP_TRY(hipMalloc(&b->recs, sizeof(Record) * (size_t)G));
     SRT_HIP_TRY(hipMalloc(&b->leaf_order, sizeof(int32_t) * (size_t)G));
-    b->bytes = (int64_t)(sizeof(float) * 6 + sizeof(Record) + sizeof(int32_t)) * G;
+    SRT_HIP_TRY(hipMalloc(&b->leaf_pos, sizeof(int32_t) * (size_t)G));
+    b->bytes = (int64_t)(sizeof(float) * 6 + sizeof(Record) + 2 * sizeof(int32_t)) * G;
 
     k_preprocess<<<blocks_for(G, 256), 256, 0, s>>>(G, sc->means, sc->log_scales, sc->quats,
                                                     sc->opacity_logits, recs_id, b->box_lo,
@@ -622,7 +625,8 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
     SRT_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, keys, keys_sorted, idx,
                                                    order, (int)G, 0, 63, s));
 
-    k_permute<<<blocks_for(G, 256), 256, 0, s>>>(G, order, recs_id, b->recs, b->leaf_order);
+    k_permute<<<blocks_for(G, 256), 256, 0, s>>>(G, order, recs_id, b->recs, b->leaf_order,
+                                                 b->leaf_pos);
     SRT_HIP_TRY(hipGetLastError());
 
     WideNode<W>* nodes_max = nullptr;
@@ -740,6 +744,7 @@ void srt_destroy_bvh(srt_bvh* b)
     (void)hipFree(b->nodes);
     (void)hipFree(b->recs);
     (void)hipFree(b->leaf_order);
+    (void)hipFree(b->leaf_pos);
     (void)hipFree(b->box_lo);
     (void)hipFree(b->box_hi);
     (void)hipFree(b->level_nodes);

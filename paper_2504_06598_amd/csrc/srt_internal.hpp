@@ -17,6 +17,7 @@ struct srt_bvh {
     void* nodes = nullptr;           // WideNode<W>[num_nodes]
     srt::Record* recs = nullptr;     // leaf order
     int32_t* leaf_order = nullptr;   // Gaussian id at each leaf position
+    int32_t* leaf_pos = nullptr;     // leaf position of each Gaussian id
     float* box_lo = nullptr;         // [G,3], Gaussian-id order
     float* box_hi = nullptr;
     const float* sh = nullptr;       // borrowed from the scene

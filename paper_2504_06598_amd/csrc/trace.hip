@@ -61,6 +61,8 @@ struct TraceArgs {
     float depth_axis[3];
     float r_max;
     int32_t img_w;  // > 0: rays are a row-major image of this width, traced in tiles
+    unsigned long long* work;  // persistent launch: next ray (item) to hand out
+    int32_t threshold;         // persistent launch: idle lanes that trigger a refill
 };
 
 struct Counts {
@@ -198,6 +200,220 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
     }
 }
 
+// Persistent work-stealing variant (same outputs as k_trace, bit for bit):
+// each workgroup is one wave that loops until the rays run out. A lane walks
+// its ray one node or one leaf per iteration and runs all passes of the ray
+// before it goes idle; when at least `threshold` lanes are idle, the wave
+// takes that many rays with one atomic on the work counter. Lanes that
+// finish early no longer wait for the longest walk of their wave. A ray
+// whose stack overflows is queued for the deep pass (k_trace with DEEP),
+// which reruns all its passes.
+constexpr int kPersistBlock = 64;
+constexpr int kDefaultRefill = 16;
+
+template <int W, int N, bool ANY, bool COUNT>
+__global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
+{
+    __shared__ int32_t lds[LdsStack<W>::value * kPersistBlock];
+    const int lane = threadIdx.x;
+    const int cap = min(LdsStack<W>::value, a.stack_cap);
+    const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
+    const int64_t n_items = a.img_w > 0 ? tile_threads(a.img_w, a.R / a.img_w) : a.R;
+    const bool shade = a.rgb != nullptr && !ANY;
+    Counts cnt;
+
+    bool active = false, exhausted = false;
+    int64_t ray = 0;
+    int32_t pass = 0, n_act = 0;
+    float tmin_f = 0.0f, tmax_f = 0.0f;
+    int32_t ign = -1;
+    uint32_t rid = 0, sbase = 0, samples = 0;
+    Ray lr;
+    DepthCtx dc;
+    FwdSamples<N> st;
+    int32_t node = 0;
+    int sp = 0;
+    int64_t steps = 0;
+    float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+    const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
+
+    for (;;) {
+        // ---- refill idle lanes (wave-uniform decision) ----
+        const unsigned long long idle = __ballot(!active);
+        const int n_idle = __popcll(idle);
+        if (n_idle == 64 && exhausted) break;
+        if (!exhausted && (n_idle >= a.threshold || n_idle == 64)) {
+            const int leader = __ffsll((long long)idle) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(a.work, (unsigned long long)n_idle);
+            base = __shfl(base, leader, 64);
+            if (base + (unsigned long long)n_idle >= (unsigned long long)n_items) exhausted = true;
+            if (!active) {
+                const unsigned long long below = idle & ((1ull << lane) - 1ull);
+                const int64_t it = (int64_t)(base + (unsigned long long)__popcll(below));
+                const int64_t r = it >= n_items ? -1
+                                  : a.img_w > 0 ? tile_pixel(it, a.img_w, a.R / a.img_w)
+                                                : it;
+                if (r >= 0 && r < a.R) {
+                    ray = r;
+                    tmin_f = a.tmin ? a.tmin[ray] : 0.0f;
+                    tmax_f = a.tmax ? a.tmax[ray] : INFINITY;
+                    if (tmax_f > tmin_f) {
+                        ign = a.ign ? a.ign[ray] : -1;
+                        rid = a.rid ? a.rid[ray] : (uint32_t)ray;
+                        sbase = (a.sid ? a.sid[ray] : 0u) + a.soff;
+                        lr = make_ray(a.o[3 * ray], a.o[3 * ray + 1], a.o[3 * ray + 2],
+                                      a.d[3 * ray], a.d[3 * ray + 1], a.d[3 * ray + 2], tmin_f);
+                        dc = make_depth(a.depth_mode, a.depth_axis, lr, a.r_max);
+                        pass = 0;
+                        n_act = min(N, a.spp);
+                        st.reset(n_act, tmax_f);
+                        node = 0;
+                        sp = 0;
+                        steps = 0;
+                        samples = 0;
+                        acc0 = acc1 = acc2 = 0.0f;
+                        active = true;
+                        ++cnt.trav;
+                    } else {
+                        // an empty ray: every sample misses, nothing to walk
+                        for (int32_t k = 0; k < a.spp; ++k) {
+                            const int64_t o = ray * a.spp + k;
+                            if (a.hit_gid) a.hit_gid[o] = -1;
+                            if (a.hit_t) a.hit_t[o] = INFINITY;
+                        }
+                        if (a.rgb) {  // the same sum as a walked ray's, term by term
+                            float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+                            for (int32_t k = 0; k < a.spp; ++k) {
+                                e0 += ANY ? 1.0f : a.bg[0];
+                                e1 += ANY ? 1.0f : a.bg[1];
+                                e2 += ANY ? 1.0f : a.bg[2];
+                            }
+                            const float inv = 1.0f / (float)a.spp;
+                            a.rgb[3 * ray] = e0 * inv;
+                            a.rgb[3 * ray + 1] = e1 * inv;
+                            a.rgb[3 * ray + 2] = e2 * inv;
+                        }
+                    }
+                }
+            }
+        }
+        if (!active) continue;
+
+        // ---- one traversal step: one node or one leaf ----
+        bool done = false, overflow = false;
+        if (++steps > a.max_steps) {
+            overflow = true;
+        } else if (node >= 0) {
+            ++cnt.nodes;
+            NodeBuf<W> nb;
+            load_node<W>(nodes, node, nb);
+            uint32_t key[W];
+            slab_keys<W>(nb, lr, st.tcut + dc.node_slack, key);
+            sort_keys<W>(key);
+            int nh = 0;
+#pragma unroll
+            for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
+            if (nh > 0) {
+                if (sp + nh - 1 > cap) {
+                    overflow = true;
+                } else {
+#pragma unroll
+                    for (int c = W - 1; c >= 1; --c)
+                        if (key[c] != 0xFFFFFFFFu) {
+                            lds[sp * kPersistBlock + lane] = child_at<W>(nb, key[c] & 7u);
+                            ++sp;
+                        }
+                    node = child_at<W>(nb, key[0] & 7u);
+                }
+            } else if (sp == 0) {
+                done = true;
+            } else {
+                --sp;
+                node = lds[sp * kPersistBlock + lane];
+            }
+        } else {
+            const uint32_t first = leaf_first(node), count = leaf_count(node);
+            FwdCounts fcnt;
+            const uint32_t s0 = sbase + (uint32_t)(pass * N);
+            bool stop = false;
+            for (uint32_t i = 0; i < count && !stop; ++i) {
+                ++cnt.prims;
+                const Record r = load_record(a.recs, first + i);
+                stop = fwd_offer<N, ANY>(st, r, lr, dc, (double)tmin_f, (double)tmax_f, ign, rid,
+                                         s0, fc, fcnt);
+            }
+            cnt.cands += fcnt.cands;
+            cnt.philox += fcnt.philox;
+            if (stop || sp == 0) {
+                done = true;
+            } else {
+                --sp;
+                node = lds[sp * kPersistBlock + lane];
+            }
+        }
+        if (overflow) {
+            const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+            a.ovf_list[slot] = (uint32_t)ray;
+            active = false;
+        } else if (done) {
+            // the pass is resolved: write its samples, shade, then the next pass
+            float Y[16];
+            if (shade) {
+                const float ex = opaque(lr.dx), ey = opaque(lr.dy), ez = opaque(lr.dz);
+                const float n = sqrtf(ex * ex + ey * ey + ez * ez);
+                sh_eval(a.deg, ex / n, ey / n, ez / n, Y);
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                if (k >= n_act) continue;
+                const bool hit = st.bg[k] != INT_MAX;
+                const int64_t o = ray * a.spp + pass * N + k;
+                if (a.hit_gid) a.hit_gid[o] = hit ? st.bg[k] : -1;
+                if (a.hit_t) a.hit_t[o] = hit ? st.bt[k] : INFINITY;
+                if (ANY) {
+                    const float v = hit ? 0.0f : 1.0f;
+                    acc0 += v; acc1 += v; acc2 += v;
+                } else if (shade) {
+                    if (hit) {
+                        const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, st.bg[k], Y));
+                        acc0 += c.x; acc1 += c.y; acc2 += c.z;
+                    } else {
+                        acc0 += a.bg[0]; acc1 += a.bg[1]; acc2 += a.bg[2];
+                    }
+                }
+            }
+            samples += (uint32_t)n_act;
+            if ((pass + 1) * N < a.spp) {
+                ++pass;
+                n_act = min(N, a.spp - pass * N);
+                st.reset(n_act, tmax_f);
+                node = 0;
+                sp = 0;
+                steps = 0;
+                ++cnt.trav;
+            } else {
+                if (a.rgb) {
+                    const float inv = 1.0f / (float)a.spp;
+                    a.rgb[3 * ray] = acc0 * inv;
+                    a.rgb[3 * ray + 1] = acc1 * inv;
+                    a.rgb[3 * ray + 2] = acc2 * inv;
+                }
+                cnt.samples += samples;
+                active = false;
+            }
+        }
+    }
+    if (COUNT && a.counters) {
+        wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, cnt.trav);
+        wave_add_u64(a.counters + SRT_CNT_NODES, cnt.nodes);
+        wave_add_u64(a.counters + SRT_CNT_PRIMS, cnt.prims);
+        wave_add_u64(a.counters + SRT_CNT_CANDIDATES, cnt.cands);
+        wave_add_u64(a.counters + SRT_CNT_PHILOX, cnt.philox);
+        wave_add_u64(a.counters + SRT_CNT_RAY_SAMPLES, cnt.samples);
+    }
+}
+
 using KernelFn = void (*)(TraceArgs);
 
 template <int W, int N, bool ANY>
@@ -234,6 +450,47 @@ bool pick_kernels(int W, int N, bool any, bool count, KernelFn* f, KernelFn* d)
     return false;
 }
 
+template <int W, int N, bool ANY>
+KernelFn persist_fn(bool count)
+{
+    return count ? k_trace_persist<W, N, ANY, true> : k_trace_persist<W, N, ANY, false>;
+}
+
+template <int W>
+KernelFn persist_w(int N, bool any, bool count)
+{
+    if (any) return N == 1 ? persist_fn<W, 1, true>(count) : nullptr;
+    switch (N) {
+    case 1: return persist_fn<W, 1, false>(count);
+    case 2: return persist_fn<W, 2, false>(count);
+    case 4: return persist_fn<W, 4, false>(count);
+    case 8: return persist_fn<W, 8, false>(count);
+    }
+    return nullptr;
+}
+
+KernelFn pick_persistent(int W, int N, bool any, bool count)
+{
+    switch (W) {
+    case 2: return persist_w<2>(N, any, count);
+    case 4: return persist_w<4>(N, any, count);
+    case 8: return persist_w<8>(N, any, count);
+    }
+    return nullptr;
+}
+
+// Waves a persistent launch keeps resident: its occupancy on every CU.
+srt_status persistent_grid(KernelFn fn, unsigned* blocks)
+{
+    int dev = 0, n_cu = 0, per_cu = 0;
+    SRT_HIP_TRY(hipGetDevice(&dev));
+    SRT_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    SRT_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(fn), kPersistBlock, 0));
+    *blocks = (unsigned)std::max(1, n_cu * std::max(1, per_cu));
+    return SRT_OK;
+}
+
 srt_status validate_opts(const srt_trace_opts* o)
 {
     if (!o) return SRT_ERR_INVALID_ARG;
@@ -244,6 +501,8 @@ srt_status validate_opts(const srt_trace_opts* o)
     if (o->stack_limit < 0) return SRT_ERR_INVALID_ARG;
     if (o->depth_mode != 0 && o->depth_mode != 1) return SRT_ERR_INVALID_ARG;
     if (o->image_width < 0) return SRT_ERR_INVALID_ARG;
+    if (o->persistent != 0 && o->persistent != 1) return SRT_ERR_INVALID_ARG;
+    if (o->refill_threshold < 0 || o->refill_threshold > 64) return SRT_ERR_INVALID_ARG;
     return SRT_OK;
 }
 
@@ -290,12 +549,27 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
     a.r_max = b->r_max;
     a.img_w = o->image_width;
     if (a.img_w > 0 && rays->count % a.img_w != 0) return SRT_ERR_INVALID_ARG;
-    fill_u32(ws.ctrl, 0u, 2, s);
+    // ctrl[0] overflow count, ctrl[1] rays lost, ctrl[2..3] the persistent work counter
+    a.work = reinterpret_cast<unsigned long long*>(ws.ctrl + 2);
+    a.threshold = o->refill_threshold > 0 ? o->refill_threshold : kDefaultRefill;
+    KernelFn pf = nullptr;
+    unsigned blocks = 0;
+    if (o->persistent && rays->count > 0) {
+        pf = pick_persistent(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr);
+        if (!pf) return SRT_ERR_UNSUPPORTED;
+        const srt_status gs = persistent_grid(pf, &blocks);
+        if (gs != SRT_OK) return gs;
+    }
+    fill_u32(ws.ctrl, 0u, 4, s);
     if (rays->count > 0) {
-        const int64_t threads =
-            a.img_w > 0 ? tile_threads(a.img_w, rays->count / a.img_w) : rays->count;
-        const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(fast, dim3(grid), dim3(kBlock), 0, s, a);
+        if (pf) {
+            hipLaunchKernelGGL(pf, dim3(blocks), dim3(kPersistBlock), 0, s, a);
+        } else {
+            const int64_t threads =
+                a.img_w > 0 ? tile_threads(a.img_w, rays->count / a.img_w) : rays->count;
+            const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
+            hipLaunchKernelGGL(fast, dim3(grid), dim3(kBlock), 0, s, a);
+        }
         SRT_HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL(deep, dim3(kDeepThreads / kBlock), dim3(kBlock), 0, s, a);
         SRT_HIP_TRY(hipGetLastError());
@@ -624,6 +898,11 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
         rr.sample_ids = sr.sid;
         rr.purpose = pass == 0 ? 2u : 3u;
         so.any_hit = pass == 0 ? 1 : 0;
+        // shadow rays (walks of very uneven length: many end at a neighbour of
+        // their start, the unoccluded ones cross the whole scene) always run on
+        // work-stealing waves, which measured faster for them; camera and
+        // mirror rays follow the caller's choice
+        so.persistent = pass == 0 ? 1 : opts->persistent;
         st = launch_trace(b, &rr, &so, nullptr, pass == 0 ? w.sh_hit : w.mr_hit, nullptr, counters,
                           w.trace_ws, s);
         if (st != SRT_OK) return st;

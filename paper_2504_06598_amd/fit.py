@@ -18,7 +18,7 @@ PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
 def fit(params, sh_degree, origins, dirs, target, *, steps, lr, spp=4, n_per_traversal=4,
-        seed=0, image_width=0, width=4, leaf_size=4, log=None):
+        seed=0, image_width=0, width=4, leaf_size=4, estimator="plain", log=None):
     """Adam on mean((render - target)^2) over the parameters named in `lr`.
 
     params: dict of the five device tensors (FP32, contiguous) of a scene;
@@ -43,7 +43,8 @@ def fit(params, sh_degree, origins, dirs, target, *, steps, lr, spp=4, n_per_tra
         opt.zero_grad(set_to_none=True)
         rgb = render(*(leaves[n] for n in PARAM_NAMES), origins, dirs, sh_degree=sh_degree,
                      spp=spp, n_per_traversal=n_per_traversal, seed=seed,
-                     sample_offset=k * spp, image_width=image_width, bvh=bvh)
+                     sample_offset=k * spp, image_width=image_width, estimator=estimator,
+                     bvh=bvh)
         loss = ((rgb - target) ** 2).sum() / (3 * R)
         loss.backward()
         opt.step()

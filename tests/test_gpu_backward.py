@@ -41,9 +41,11 @@ def _close(g, o, name, rel=2e-4):
     assert np.all(err <= tol), (name, float((err / scale).max()), float(scale))
 
 
-@pytest.mark.parametrize("N,deg", [(1, 1), (4, 1), (4, 3), (2, 0)])
-def test_backward_matches_oracle_same_realisation(srt, N, deg):
-    say(f"backward vs oracle estimator, N={N}, SH degree {deg}")
+@pytest.mark.parametrize("N,deg,est", [(1, 1, "plain"), (4, 1, "plain"), (4, 3, "plain"),
+                                       (2, 0, "plain"), (1, 1, "rb"), (4, 3, "rb"),
+                                       (8, 0, "rb")])
+def test_backward_matches_oracle_same_realisation(srt, N, deg, est):
+    say(f"backward vs oracle estimator, N={N}, SH degree {deg}, estimator {est}")
     sc = tiny_scene(31 + deg, 800, (0.03, 0.1), deg=deg)
     cam = si.look_at((0.1, 0.2, 3), (0, 0, 0), 40, 40)
     o, d = si.camera_rays(cam)
@@ -61,16 +63,18 @@ def test_backward_matches_oracle_same_realisation(srt, N, deg):
     dLc = _cu(dL.astype(np.float32))
     cnt = srt.new_counters()
     g = srt.srt_trace_backward(bvh, oc, dc, dLc, hit_gid=fw["hit_gid"], hit_t=fw["hit_t"],
-                               seed=seed, spp=spp, n_per_traversal=N, bg=bg, counters=cnt)
+                               seed=seed, spp=spp, n_per_traversal=N, bg=bg, counters=cnt,
+                               estimator=est)
     torch.cuda.synchronize()
     ora = oracle.estimator_grad(rec, oracle.Rays(o, d), dL.astype(np.float32).astype(np.float64),
-                                spp=spp, seed=seed, bg=bg)
+                                spp=spp, seed=seed, bg=bg, estimator=est)
     for name in NAMES:
         _close(to_np(g[name]).reshape(ora[name].shape), ora[name], name)
     c = srt.counters_dict(cnt)
     assert c["lost"] == 0 and c["candidates"] > 0
     # recomputing the forward inside the backward gives the same gradients
-    g2 = srt.srt_trace_backward(bvh, oc, dc, dLc, seed=seed, spp=spp, n_per_traversal=N, bg=bg)
+    g2 = srt.srt_trace_backward(bvh, oc, dc, dLc, seed=seed, spp=spp, n_per_traversal=N, bg=bg,
+                                estimator=est)
     torch.cuda.synchronize()
     for name in NAMES:
         a, b = to_np(g[name]), to_np(g2[name])
@@ -78,7 +82,8 @@ def test_backward_matches_oracle_same_realisation(srt, N, deg):
     # walking the rays as 8x8 tiles of the 40x40 image changes only the order
     # of the FP32 sums
     g3 = srt.srt_trace_backward(bvh, oc, dc, dLc, hit_gid=fw["hit_gid"], hit_t=fw["hit_t"],
-                                seed=seed, spp=spp, n_per_traversal=N, bg=bg, image_width=40)
+                                seed=seed, spp=spp, n_per_traversal=N, bg=bg, image_width=40,
+                                estimator=est)
     torch.cuda.synchronize()
     for name in NAMES:
         a, b = to_np(g[name]), to_np(g3[name])
@@ -207,3 +212,41 @@ def test_backward_center_depth_matches_oracle(srt):
     torch.cuda.synchronize()
     for name in NAMES:
         _close(to_np(g[name]).reshape(ora[name].shape), ora[name], name)
+
+
+def test_rb_estimator_has_lower_variance_on_gpu(srt):
+    """Both estimators on the same 24 seeds of the tiny cube scene (GPU):
+    their means agree within the noise and the Rao-Blackwellised one has the
+    smaller spread for the parameters that reach alpha."""
+    say("RB vs plain estimator variance over 24 seeds")
+    sc = _scene()
+    cam = si.look_at((0, 0.2, 3), (0, 0, 0), 48, 48)
+    o, d = si.camera_rays(cam)
+    oc, dc = _cu(o), _cu(d)
+    dsc = device_scene(sc)
+    bvh = srt.srt_build_bvh(dsc, 4, 2)
+    rng = np.random.default_rng(4)
+    dLc = _cu(rng.normal(0, 1, (len(o), 3)).astype(np.float32))
+    runs = {}
+    for est in ("plain", "rb"):
+        rs = []
+        for seed in range(24):
+            fw = srt.srt_trace_forward(bvh, oc, dc, seed=seed, spp=4, n_per_traversal=4)
+            g = srt.srt_trace_backward(bvh, oc, dc, dLc, hit_gid=fw["hit_gid"],
+                                       hit_t=fw["hit_t"], seed=seed, spp=4, n_per_traversal=4,
+                                       estimator=est)
+            rs.append({k: to_np(v).astype(np.float64) for k, v in g.items()})
+        torch.cuda.synchronize()
+        runs[est] = rs
+    var = {}
+    for est, rs in runs.items():
+        var[est] = 0.0
+        for name in ("means", "log_scales", "quats", "opacity_logits"):
+            var[est] += float(np.stack([r[name] for r in rs]).var(0, ddof=1).sum())
+    for name in ("means", "opacity_logits"):
+        a = np.stack([r[name] for r in runs["plain"]])
+        b = np.stack([r[name] for r in runs["rb"]])
+        se = np.sqrt(a.var(0, ddof=1) / len(a) + b.var(0, ddof=1) / len(b))
+        assert np.mean(np.abs(a.mean(0) - b.mean(0)) <= 4 * se + 1e-9) > 0.97, name
+    say(f"variance sum: plain {var['plain']:.4e}, rb {var['rb']:.4e}")
+    assert var["rb"] < 0.8 * var["plain"], var

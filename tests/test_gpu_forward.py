@@ -330,3 +330,69 @@ def test_image_width_errors(srt):
             srt.srt_trace_backward(bvh, o, o, torch.ones((10, 3), device="cuda"),
                                    image_width=bad)
         assert e.value.code == 1
+
+
+@pytest.mark.parametrize("N,spp,any_hit,thr", [(4, 8, False, 16), (1, 3, False, 1),
+                                               (8, 8, False, 64), (2, 6, False, 0),
+                                               (1, 1, True, 16)])
+def test_persistent_equals_plain(srt, N, spp, any_hit, thr):
+    say(f"persistent waves vs one lane per ray: N={N} spp={spp} any_hit={any_hit} thr={thr}")
+    sc = tiny_scene(21, 3000, (0.02, 0.08))
+    cam = si.look_at((0.1, 0.3, 2.8), (0, 0, 0), 37, 29)
+    o, d = si.camera_rays(cam)
+    R = len(o)
+    rng = np.random.default_rng(5)
+    tmin = rng.uniform(0.0, 1.5, R).astype(np.float32)
+    tmax = (tmin + rng.uniform(-0.2, 4.0, R)).astype(np.float32)  # some rays empty
+    ign = rng.integers(-1, 3000, R).astype(np.int32)
+    kw = dict(seed=11, spp=spp, n_per_traversal=N, any_hit=any_hit, bg=(0.2, 0.1, 0.7),
+              tmin=_cuda(tmin), tmax=_cuda(tmax), ignore_gid=_cuda(ign), sample_offset=7)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
+    for lim, iw in ((0, 0), (1, 0), (0, cam.width)):
+        base = _trace(srt, bvh, o, d, stack_limit=lim, image_width=iw, **kw)
+        cnt = srt.new_counters()
+        pers = _trace(srt, bvh, o, d, stack_limit=lim, image_width=iw, persistent=True,
+                      refill_threshold=thr, counters=cnt, **kw)
+        for k in ("hit_gid", "hit_t", "rgb"):
+            np.testing.assert_array_equal(pers[k], base[k], err_msg=f"{k} lim={lim} iw={iw}")
+        c = srt.counters_dict(cnt)
+        assert c["lost"] == 0
+        assert c["ray_samples"] == int((tmax > tmin).sum()) * spp
+        if lim:
+            assert c["deep"] > 0
+
+
+def test_persistent_pathmix_equals_plain(srt):
+    say("path-tracer mix with persistent waves")
+    w = si.workload(3, small=True)
+    cam = w["cameras"][0]
+    bvh = srt.srt_build_bvh(device_scene(w["scene"]), 4, 2)
+    outs = []
+    for pers in (False, True):
+        res = srt.srt_trace_pathmix(bvh, cam, seed=2, spp=8, n_per_traversal=4,
+                                    light=si.LIGHT_POS, plane_y=si.PLANE_Y,
+                                    tmin_secondary=si.SECONDARY_TMIN, persistent=pers)
+        torch.cuda.synchronize()
+        outs.append({k: to_np(v) for k, v in res.items()})
+    for k in outs[0]:
+        np.testing.assert_array_equal(outs[0][k], outs[1][k], err_msg=k)
+
+
+def test_persistent_option_errors(srt):
+    sc = tiny_scene(22, 100)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    o = torch.zeros((10, 3), device="cuda")
+    for kw in (dict(persistent=True, refill_threshold=65),
+               dict(persistent=True, refill_threshold=-1)):
+        with pytest.raises(srt.SrtError) as e:
+            srt.srt_trace_forward(bvh, o, o, **kw)
+        assert e.value.code == 1
+    opts = srt._opts(0, 1, 1, 0, (0, 0, 0), False, 0)
+    opts.persistent = 2
+    import ctypes as C
+    lib = srt._lib.load()
+    rays = srt._lib.SrtRays(10, o.data_ptr(), o.data_ptr(), None, None, None, None, None, 0)
+    ws = torch.empty(lib.srt_trace_workspace_size(bvh.handle, 10), dtype=torch.uint8,
+                     device="cuda")
+    assert lib.srt_trace_forward(bvh.handle, C.byref(rays), C.byref(opts), None, None, None,
+                                 None, ws.data_ptr(), ws.numel(), None) == 1
