@@ -223,6 +223,12 @@ def main():
     print(f"# dominant kernel {avg_ms:.3f} ms/launch, {bytes_per_launch / 1e9:.3f} GB "
           f"algorithmic -> {achieved:.0f} GB/s", file=sys.stderr, flush=True)
 
+    # ---- the two backward estimators on the ring views: time per launch and
+    # the variance of the alpha-side gradients over fresh samples ----
+    est_cmp = compare_estimators(args, srt, si, torch, bvh, vo, vd, target, bout, grads, fws,
+                                 bws, bspp, stream)
+    print(f"# backward estimators: {est_cmp}", file=sys.stderr, flush=True)
+
     # ---- BVH build vs refit at 1M (a refit replaces the build inside an
     # optimisation loop; both synchronise) ----
     def timed(fn, reps=3):
@@ -285,8 +291,48 @@ def main():
                        "forward_ray_samples_per_step": int(fwd_rs),
                        "backward_ray_samples_per_step": int(bwd_rs)},
             "roofline": roof, "cpu_baseline": cpu, "persistent_vs_plain": batched,
-            "bvh": bvh_times}
+            "bvh": bvh_times, "backward_estimators": est_cmp}
     print(json.dumps(line), flush=True)
+
+
+def compare_estimators(args, srt, si, torch, bvh, vo, vd, target, bout, grads, fws, bws, bspp,
+                       stream, seeds=6):
+    """Plain and Rao-Blackwellised backward on the same forward realisations
+    (sample offsets 1000 + k*spp): best launch time of each and the summed
+    variance, over the realisations, of the gradients of means, log-scales,
+    quaternions and opacity logits."""
+    names = ("means", "log_scales", "quats", "opacity_logits")
+    Rb = vo.shape[0]
+    width = int(round((Rb // 8) ** 0.5))
+    res = {}
+    for est in ("plain", "rb"):
+        per, ms = [], []
+        for k in range(seeds):
+            srt.srt_trace_forward(bvh, vo, vd, seed=si.PHILOX_SEED, spp=bspp,
+                                  n_per_traversal=bspp, sample_offset=1000 + k * bspp,
+                                  image_width=width, out=bout, workspace=fws)
+            grad_rgb = (bout["rgb"] - target) * (2.0 / Rb)
+            for g in grads.values():
+                g.zero_()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            srt.srt_trace_backward(bvh, vo, vd, grad_rgb, hit_gid=bout["hit_gid"],
+                                   hit_t=bout["hit_t"], seed=si.PHILOX_SEED, spp=bspp,
+                                   n_per_traversal=bspp, sample_offset=1000 + k * bspp,
+                                   image_width=width, estimator=est, grads=grads, workspace=bws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            per.append(torch.cat([grads[n].flatten() for n in names]).double())
+        var = float(torch.stack(per).var(0).sum())
+        res[est] = (min(ms), var)
+        del per
+    (pm, pv), (rm, rv) = res["plain"], res["rb"]
+    return {"plain_ms": round(pm, 3), "rb_ms": round(rm, 3),
+            "variance_ratio": round(rv / pv, 4) if pv > 0 else None,
+            "variance_time_ratio": round(rv * rm / (pv * pm), 4) if pv > 0 else None,
+            "realisations": seeds}
 
 
 def measured_traffic(width, leaf, root=ROOT):

@@ -40,7 +40,11 @@ constexpr int kBlock = 128;
 constexpr int kLdsEntries = 32;
 constexpr int kAccStride = 16;  // floats per Gaussian: sa, sa p (3), sa p p^T (6), pad (6)
 constexpr int kAccVals = 10;
-constexpr int kTableSlots = 512;  // LDS hash table entries per workgroup
+constexpr int kTableSlots = 128;  // LDS table of the alpha sums (a 128-ray tile of the
+                                  // 1M scene's views holds 40-70 distinct front Gaussians)
+constexpr int kShSlots = 64;      // LDS table of SH colour gradients (28-44 distinct
+                                  // accepted Gaussians per such tile, of 512 samples)
+constexpr int kShVals = 48;       // (deg + 1)^2 * 3 at degree 3
 constexpr int kProbes = 8;
 
 struct BwdArgs {
@@ -87,28 +91,32 @@ struct Table {
     float* vals;    // [kAccVals][kTableSlots]
 };
 
-// Add one candidate's ten sums to the workgroup table (global atomics when
-// the table has no room within kProbes probes).
-__device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, const float v[kAccVals])
+// Slot of `gid` in an open-addressing LDS table of `slots` keys (a power of
+// two; -1 = empty), claimed with a compare-and-swap; -1 when no slot within
+// kProbes probes holds or takes it.
+template <int SLOTS>
+__device__ __forceinline__ int lds_slot(int32_t* keys, int32_t gid)
 {
-    uint32_t h = ((uint32_t)gid * 2654435761u) >> (32 - 9);
-    int slot = -1;
+    constexpr int bits = __builtin_ctz(SLOTS);
+    uint32_t h = ((uint32_t)gid * 2654435761u) >> (32 - bits);
 #pragma unroll 1
     for (int p = 0; p < kProbes; ++p) {
-        const int32_t k = t.keys[h];
-        if (k == gid) {
-            slot = (int)h;
-            break;
-        }
+        const int32_t k = keys[h];
+        if (k == gid) return (int)h;
         if (k == -1) {
-            const int32_t old = atomicCAS(&t.keys[h], -1, gid);
-            if (old == -1 || old == gid) {
-                slot = (int)h;
-                break;
-            }
+            const int32_t old = atomicCAS(&keys[h], -1, gid);
+            if (old == -1 || old == gid) return (int)h;
         }
-        h = (h + 1) & (kTableSlots - 1);
+        h = (h + 1) & (SLOTS - 1);
     }
+    return -1;
+}
+
+// Add one candidate's ten sums to the workgroup table (global atomics when
+// the table has no room for it).
+__device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, const float v[kAccVals])
+{
+    const int slot = lds_slot<kTableSlots>(t.keys, gid);
     if (slot >= 0) {
 #pragma unroll
         for (int c = 0; c < kAccVals; ++c) atomicAdd(&t.vals[c * kTableSlots + slot], v[c]);
@@ -125,10 +133,16 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
     __shared__ int32_t lds[kLdsEntries * kBlock];
     __shared__ int32_t tkeys[kTableSlots];
     __shared__ float tvals[kAccVals * kTableSlots];
+    __shared__ int32_t shkeys[kShSlots];
+    __shared__ float shvals[kShVals * kShSlots];
     Table table{tkeys, tvals};
     for (int i = threadIdx.x; i < kTableSlots; i += kBlock) {
         tkeys[i] = -1;
         for (int c = 0; c < kAccVals; ++c) tvals[c * kTableSlots + i] = 0.0f;
+    }
+    for (int i = threadIdx.x; i < kShSlots; i += kBlock) {
+        shkeys[i] = -1;
+        for (int c = 0; c < kShVals; ++c) shvals[c * kShSlots + i] = 0.0f;
     }
     __syncthreads();
     const int64_t gt = blockIdx.x * (int64_t)kBlock + threadIdx.x;
@@ -247,13 +261,12 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
                     const float t32 = (float)t;
                     if (!key_less(t32, r.gid, wt, wg)) return false;
-                    double alpha_d = 0.0;
-                    if constexpr (RB) alpha_d = (double)r.opacity * exp(-0.5 * q);
                     int nf = 0, na = 0;
                     float xs = 0.0f;
                     bool found = false;
                     uint4 w = make_uint4(0, 0, 0, 0);
                     uint32_t grp = 0xFFFFFFFFu;
+                    AlphaTest at(r.opacity, q);
 #pragma unroll
                     for (int k = 0; k < N; ++k) {
                         if (k >= n_act) continue;
@@ -273,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                                         a.k1);
                                     ++n_philox;
                                 }
-                                if (u_of_word(word_of(w, smp & 3u)) < alpha_d) {
+                                if (at.accepts(word_of(w, smp & 3u))) {
                                     tb[k] = t32;
                                     gb[k] = r.gid;
                                     found = true;
@@ -300,8 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     }
                     if (nf == 0 && na == 0) return false;
                     ++n_front;
-                    if constexpr (!RB) alpha_d = (double)r.opacity * exp(-0.5 * q);
-                    const float alpha = (float)alpha_d;
+                    // alpha only weights FP32 sums here: FP32 precision suffices
+                    const float alpha = r.opacity * expf(-0.5f * (float)q);
                     const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, r.gid, Y));
                     const float gc = g0 * c.x + g1 * c.y + g2 * c.z;
                     // plain: <g, c_k - X> / (1 - alpha_k) per front sample; RB: the
@@ -347,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                             const Record r = load_record(a.recs, (uint32_t)a.leaf_pos[ga[k]]);
                             double tm, q, p[3];
                             isect_tqp(r, rr, tm, q, p);
-                            const float alpha = (float)((double)r.opacity * exp(-0.5 * q));
+                            const float alpha = r.opacity * expf(-0.5f * (float)q);
                             const float sa = s2 * inv_spp * alpha;
                             const float p0 = (float)p[0], p1 = (float)p[1], p2 = (float)p[2];
                             const float v[kAccVals] = {sa,           sa * p0,      sa * p1,
@@ -373,11 +386,25 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     if (!first) continue;
                     const float3 pre = sh_colour_pre(a.sh, a.deg, ga[k], Y);
                     const float f = (float)mult * inv_spp;
-                    float* gs = a.g_sh + (size_t)ga[k] * (size_t)(3 * K);
-                    for (int j = 0; j < K; ++j) {
-                        if (pre.x > 0.0f) atomic_add_f32(gs + 3 * j + 0, Y[j] * g0 * f);
-                        if (pre.y > 0.0f) atomic_add_f32(gs + 3 * j + 1, Y[j] * g1 * f);
-                        if (pre.z > 0.0f) atomic_add_f32(gs + 3 * j + 2, Y[j] * g2 * f);
+                    // the clamp passes the gradient only where the colour is positive
+                    const float f0 = pre.x > 0.0f ? g0 * f : 0.0f;
+                    const float f1 = pre.y > 0.0f ? g1 * f : 0.0f;
+                    const float f2 = pre.z > 0.0f ? g2 * f : 0.0f;
+                    if (f0 == 0.0f && f1 == 0.0f && f2 == 0.0f) continue;
+                    const int slot = lds_slot<kShSlots>(shkeys, ga[k]);
+                    if (slot >= 0) {
+                        for (int j = 0; j < K; ++j) {
+                            atomicAdd(&shvals[(3 * j + 0) * kShSlots + slot], Y[j] * f0);
+                            atomicAdd(&shvals[(3 * j + 1) * kShSlots + slot], Y[j] * f1);
+                            atomicAdd(&shvals[(3 * j + 2) * kShSlots + slot], Y[j] * f2);
+                        }
+                    } else {
+                        float* gs = a.g_sh + (size_t)ga[k] * (size_t)(3 * K);
+                        for (int j = 0; j < K; ++j) {
+                            atomic_add_f32(gs + 3 * j + 0, Y[j] * f0);
+                            atomic_add_f32(gs + 3 * j + 1, Y[j] * f1);
+                            atomic_add_f32(gs + 3 * j + 2, Y[j] * f2);
+                        }
                     }
                 }
             }
@@ -393,6 +420,17 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     tvals[c * kTableSlots + i] = 0.0f;
                 }
                 tkeys[i] = -1;
+            }
+        }
+        for (int i = threadIdx.x; i < kShSlots; i += kBlock) {
+            const int32_t gid = shkeys[i];
+            if (gid >= 0) {
+                float* gs = a.g_sh + (size_t)gid * (size_t)(3 * K);
+                for (int c = 0; c < 3 * K; ++c) {
+                    atomic_add_f32(gs + c, shvals[c * kShSlots + i]);
+                    shvals[c * kShSlots + i] = 0.0f;
+                }
+                shkeys[i] = -1;
             }
         }
         __syncthreads();

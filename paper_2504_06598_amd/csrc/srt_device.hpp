@@ -106,11 +106,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a_hi = __umulhi(0xD2511F53u, c.x);
-        const uint32_t a_lo = 0xD2511F53u * c.x;
-        const uint32_t b_hi = __umulhi(0xCD9E8D57u, c.z);
-        const uint32_t b_lo = 0xCD9E8D57u * c.z;
-        c = make_uint4(b_hi ^ c.y ^ k0, b_lo, a_hi ^ c.w ^ k1, a_lo);
+        // one 32x32->64 product each (a single v_mad_u64_u32 instead of a
+        // separate low and high multiply)
+        const uint64_t pa = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(pb >> 32) ^ c.y ^ k0, (uint32_t)pb,
+                       (uint32_t)(pa >> 32) ^ c.w ^ k1, (uint32_t)pa);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -124,6 +125,36 @@ __device__ __forceinline__ uint32_t word_of(const uint4& w, uint32_t i)
 
 // u in [0, 1 - 2^-24], exact in FP32 and FP64.
 __device__ __forceinline__ double u_of_word(uint32_t w) { return (double)(w >> 8) * 0x1p-24; }
+
+// The acceptance test u < alpha = opacity * exp(-q / 2) (eqn "rr"), decided
+// exactly as in FP64 at FP32 cost: the FP32 value differs from the FP64 one
+// by well under 1e-6 relative (q rounded to FP32 moves exp(-q/2) by at most
+// 2.4e-7 relative for q <= 8, expf and the product add a few ulps), so any u
+// outside a band of 4e-6 relative around it is decided by the FP32 value;
+// inside the band (probability ~1e-5 per test) the FP64 value decides.
+struct AlphaTest {
+    float lo, hi;
+    float opacity;
+    double q;
+    double a64;
+
+    __device__ __forceinline__ AlphaTest(float op, double q_) : opacity(op), q(q_), a64(-1.0)
+    {
+        const float a32 = op * expf(-0.5f * (float)q_);
+        const float band = 4e-6f * a32 + 1e-30f;
+        lo = a32 - band;
+        hi = a32 + band;
+    }
+
+    __device__ __forceinline__ bool accepts(uint32_t word)
+    {
+        const float u = (float)(word >> 8) * 0x1p-24f;  // exact
+        if (u < lo) return true;
+        if (u >= hi) return false;
+        if (a64 < 0.0) a64 = (double)opacity * exp(-0.5 * q);
+        return (double)u < a64;
+    }
+};
 
 // --------------------------------------------------------------------------
 // Real spherical harmonics up to degree 3 at a unit direction, orthonormal,

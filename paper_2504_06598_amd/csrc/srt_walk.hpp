@@ -205,7 +205,7 @@ __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, co
     ++cnt.cands;
     const float t32 = (float)t;
     if (!key_less(t32, r.gid, st.wt, st.wg)) return false;
-    const double alpha = (double)r.opacity * exp(-0.5 * q);
+    AlphaTest at(r.opacity, q);
     uint4 w = make_uint4(0, 0, 0, 0);
     uint32_t grp = 0xFFFFFFFFu;
     bool changed = false;
@@ -218,7 +218,7 @@ __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, co
                 w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, fc.purpose), fc.k0, fc.k1);
                 ++cnt.philox;
             }
-            if (u_of_word(word_of(w, s & 3u)) < alpha) {
+            if (at.accepts(word_of(w, s & 3u))) {
                 st.bt[k] = t32;
                 st.bg[k] = r.gid;
                 changed = true;
