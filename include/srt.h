@@ -212,7 +212,15 @@ typedef struct {
  *                 <g, c_a - c_a2>, a2 the sample's next accepted candidate
  *                 behind a (bg if none; the walk goes on to find it). Both are
  *                 unbiased for the exact composite's gradient; 1 has no larger
- *                 variance (Rao-Blackwell). Colour gradients are the same.   */
+ *                 variance (Rao-Blackwell). Colour gradients are the same.
+ * rng             0: Philox numbers as described above. 1: the paper's
+ *                 stateless trigonometric hash (Sec. 4.2, eqns "hash" and
+ *                 "rng") of the candidate's hit position p = o + t* d, in
+ *                 FP32, moved by the sample index s along (1,1,1) so the N
+ *                 samples of one walk differ; frame-to-frame variation comes
+ *                 from jittered camera rays (srt_camera.jitter). Results are
+ *                 then a different realisation, correct in expectation only.
+ *                 seed and purpose are not used by the hash.                */
 typedef struct {
     uint64_t seed;
     int32_t spp;
@@ -227,6 +235,7 @@ typedef struct {
     int32_t persistent;
     int32_t refill_threshold;
     int32_t estimator;
+    int32_t rng;
 } srt_trace_opts;
 
 /* Counters accumulated (+=) into a device uint64 array of SRT_NUM_COUNTERS
@@ -312,7 +321,9 @@ typedef struct {
     float tan_half;
     int32_t width;
     int32_t height;
-    int32_t pad_;
+    float jitter[2]; /* sub-pixel offset from the pixel centre, in pixels, in
+                        [-0.5, 0.5) (0, 0 = centres); a frame's camera
+                        perturbation (Sec. 4.2) */
 } srt_camera;
 
 /* Write width*height camera rays (pixel y*width + x): origins, dirs [R,3]

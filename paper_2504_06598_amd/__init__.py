@@ -74,14 +74,18 @@ class Bvh:
     def __init__(self, handle, scene):
         self.handle = handle
         self.scene = scene
+        # held by the object: module globals may already be gone when a
+        # handle is collected at interpreter exit
+        self._destroy = _lib.load().srt_destroy_bvh
+        self._sync = torch.cuda.synchronize
 
     def __del__(self):
         if getattr(self, "handle", None):
             try:
-                torch.cuda.synchronize()
+                self._sync()
             except Exception:
                 pass
-            _lib.load().srt_destroy_bvh(self.handle)
+            self._destroy(self.handle)
             self.handle = None
 
     def info(self):
@@ -144,15 +148,19 @@ def counters_dict(c):
 
 
 ESTIMATORS = {"plain": 0, "rb": 1}
+RNGS = {"philox": 0, "hash": 1}
 
 
 def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode=0,
           depth_axis=(0.0, 0.0, 0.0), image_width=0, persistent=False, refill_threshold=0,
-          estimator="plain"):
+          estimator="plain", rng="philox"):
     o = _lib.SrtTraceOpts()
     if estimator not in ESTIMATORS:
         raise ValueError(f"estimator must be one of {sorted(ESTIMATORS)}")
+    if rng not in RNGS:
+        raise ValueError(f"rng must be one of {sorted(RNGS)}")
     o.estimator = ESTIMATORS[estimator]
+    o.rng = RNGS[rng]
     o.image_width = int(image_width)
     o.persistent = 1 if persistent else 0
     o.refill_threshold = int(refill_threshold)
@@ -174,8 +182,8 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
                       ray_ids=None, sample_ids=None, purpose=0, seed=0, spp=1,
                       n_per_traversal=1, sample_offset=0, bg=(0.0, 0.0, 0.0), any_hit=False,
                       stack_limit=0, depth_mode=0, depth_axis=(0.0, 0.0, 0.0), image_width=0,
-                      persistent=False, refill_threshold=0, want_rgb=True, want_hits=True,
-                      counters=None, out=None, workspace=None):
+                      persistent=False, refill_threshold=0, rng="philox", want_rgb=True,
+                      want_hits=True, counters=None, out=None, workspace=None):
     """Trace rays (device tensors [R,3]); returns dict(rgb [R,3], hit_gid [R,spp],
     hit_t [R,spp]). image_width > 0 declares the rays a row-major image of that
     width (traced in 8x8 tiles); persistent=True runs work-stealing waves
@@ -186,7 +194,7 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
     opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode,
-                 depth_axis, image_width, persistent, refill_threshold)
+                 depth_axis, image_width, persistent, refill_threshold, rng=rng)
     res = dict(out or {})
     if want_rgb and "rgb" not in res:
         res["rgb"] = torch.empty((R, 3), dtype=torch.float32, device=dev)
@@ -206,8 +214,8 @@ def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t
                        tmin=None, tmax=None, ignore_gid=None, ray_ids=None, sample_ids=None,
                        purpose=0, seed=0, spp=1, n_per_traversal=1, sample_offset=0,
                        bg=(0.0, 0.0, 0.0), depth_mode=0, depth_axis=(0.0, 0.0, 0.0),
-                       image_width=0, estimator="plain", grads=None, counters=None,
-                       workspace=None):
+                       image_width=0, estimator="plain", rng="philox", grads=None,
+                       counters=None, workspace=None):
     """Accumulate gradients of sum(grad_rgb * E[rgb]) into `grads` (a dict of
     tensors shaped like the scene's; zeros are allocated when absent).
     estimator: "plain" (per-sample score terms) or "rb" (each term averaged
@@ -222,7 +230,7 @@ def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
     opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0, depth_mode, depth_axis,
-                 image_width, estimator=estimator)
+                 image_width, estimator=estimator, rng=rng)
     need = lib.srt_backward_workspace_size(bvh.handle, R)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -256,7 +264,8 @@ class TraceFn(torch.autograd.Function):
                                 n_per_traversal=cfg.get("n_per_traversal", 1),
                                 sample_offset=cfg.get("sample_offset", 0),
                                 bg=cfg.get("bg", (0.0, 0.0, 0.0)),
-                                image_width=cfg.get("image_width", 0))
+                                image_width=cfg.get("image_width", 0),
+                                rng=cfg.get("rng", "philox"))
         ctx.bvh = bvh
         ctx.cfg = cfg
         ctx.save_for_backward(origins, dirs, res["hit_gid"], res["hit_t"])
@@ -272,7 +281,8 @@ class TraceFn(torch.autograd.Function):
                                sample_offset=cfg.get("sample_offset", 0),
                                bg=cfg.get("bg", (0.0, 0.0, 0.0)),
                                image_width=cfg.get("image_width", 0),
-                               estimator=cfg.get("estimator", "plain"))
+                               estimator=cfg.get("estimator", "plain"),
+                               rng=cfg.get("rng", "philox"))
         return (g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None, None,
                 None)
 
@@ -295,6 +305,9 @@ def _camera(cam):
     c.tan_half = float(cam.tan_half)
     c.width = int(cam.width)
     c.height = int(cam.height)
+    jit = getattr(cam, "jitter", (0.0, 0.0))
+    c.jitter[0] = float(jit[0])
+    c.jitter[1] = float(jit[1])
     return c
 
 
@@ -312,7 +325,7 @@ def srt_camera_rays(cam, device="cuda"):
 def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_traversal=1,
                       sample_offset=0, bg=(0.0, 0.0, 0.0), light=(5.0, 5.0, 5.0), plane_y=-2.5,
                       tmin_secondary=1e-4, stack_limit=0, persistent=False, refill_threshold=0,
-                      want_hits=True, counters=None, workspace=None, out=None):
+                      rng="philox", want_hits=True, counters=None, workspace=None, out=None):
     """Path-tracer mix of one camera; returns dict(rgb [, cam_gid, cam_t,
     shadow_vis, mirror_gid])."""
     lib = _lib.load()
@@ -320,7 +333,7 @@ def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_trav
     R = int(cam.width) * int(cam.height)
     c = _camera(cam)
     opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, stack_limit,
-                 persistent=persistent, refill_threshold=refill_threshold)
+                 persistent=persistent, refill_threshold=refill_threshold, rng=rng)
     pm = _lib.SrtPathmixOpts()
     for i in range(3):
         pm.light[i] = float(light[i])
@@ -351,6 +364,8 @@ class BatchPlan:
         self.handle = handle
         self.bvh = bvh
         self._keep = keep  # host/device objects the plan refers to
+        self._destroy = _lib.load().srt_batch_plan_destroy
+        self._sync = torch.cuda.synchronize
         rows, samples, items = C.c_int64(), C.c_int64(), C.c_int64()
         _lib.check("srt_batch_plan_info", _lib.load().srt_batch_plan_info(
             handle, C.byref(rows), C.byref(samples), C.byref(items)))
@@ -359,10 +374,10 @@ class BatchPlan:
     def __del__(self):
         if getattr(self, "handle", None):
             try:
-                torch.cuda.synchronize()
+                self._sync()
             except Exception:
                 pass
-            _lib.load().srt_batch_plan_destroy(self.handle)
+            self._destroy(self.handle)
             self.handle = None
 
     def execute(self, rgb=None, hit_gid=None, counters=None, eager=False):
@@ -381,7 +396,7 @@ def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_d
                           extra_spp=1, ray_id_base=0, seed=0, n_per_traversal=4,
                           sample_offset=0, bg=(0.0, 0.0, 0.0), stack_limit=0, persistent=True,
                           refill_threshold=16, waves_per_cu=8, depth_mode=0,
-                          depth_axis=(0.0, 0.0, 0.0)) -> BatchPlan:
+                          depth_axis=(0.0, 0.0, 0.0), rng="philox") -> BatchPlan:
     lib = _lib.load()
     nv = len(cameras)
     cams = (_lib.SrtCamera * max(nv, 1))(*[_camera(c) for c in cameras])
@@ -392,7 +407,7 @@ def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_d
     batch = _lib.SrtBatch(nv, C.cast(cams, C.c_void_p), C.cast(spp_arr, C.c_void_p), extra,
                           int(extra_spp) if n_extra else 0, int(ray_id_base))
     opts = _opts(seed, 1, n_per_traversal, sample_offset, bg, False, stack_limit, depth_mode,
-                 depth_axis)
+                 depth_axis, rng=rng)
     tun = _lib.SrtTuning(1 if persistent else 0, int(refill_threshold), int(waves_per_cu))
     h = C.c_void_p()
     _lib.check("srt_batch_plan_create", lib.srt_batch_plan_create(

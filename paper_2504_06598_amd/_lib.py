@@ -42,13 +42,13 @@ class SrtTraceOpts(C.Structure):
                 ("stack_limit", C.c_int32), ("depth_mode", C.c_int32),
                 ("depth_axis", C.c_float * 3), ("image_width", C.c_int32),
                 ("persistent", C.c_int32), ("refill_threshold", C.c_int32),
-                ("estimator", C.c_int32)]
+                ("estimator", C.c_int32), ("rng", C.c_int32)]
 
 
 class SrtCamera(C.Structure):
     _fields_ = [("eye", C.c_float * 3), ("forward", C.c_float * 3), ("right", C.c_float * 3),
                 ("up", C.c_float * 3), ("tan_half", C.c_float), ("width", C.c_int32),
-                ("height", C.c_int32), ("pad_", C.c_int32)]
+                ("height", C.c_int32), ("jitter", C.c_float * 2)]
 
 
 class SrtPathmixOpts(C.Structure):

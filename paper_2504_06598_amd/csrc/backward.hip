@@ -583,6 +583,11 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     if (opts->image_width < 0) return SRT_ERR_INVALID_ARG;
     if (opts->image_width > 0 && rays->count % opts->image_width != 0) return SRT_ERR_INVALID_ARG;
     if (opts->estimator != 0 && opts->estimator != 1) return SRT_ERR_INVALID_ARG;
+    if (opts->rng != 0 && opts->rng != 1) return SRT_ERR_INVALID_ARG;
+    // the backward draws numbers only to recompute results or to find second
+    // hits; with the hash those are not provided here
+    if (opts->rng == 1 && (hit_gid == nullptr || opts->estimator == 1))
+        return SRT_ERR_UNSUPPORTED;
     const int N = opts->n_per_traversal;
     if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
     if (rays->count < 0 || rays->count > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;

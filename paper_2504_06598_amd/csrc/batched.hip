@@ -98,9 +98,9 @@ __device__ __forceinline__ int find_seg(const BatchArgs& a, int64_t idx, bool by
 __device__ __forceinline__ void cam_ray(const srt_camera& c, int32_t x, int32_t y, float o[3], float d[3])
 {
     const float aspect = (float)c.width / (float)c.height;
-    const float px = ((float)x + 0.5f) / (float)c.width;
+    const float px = (((float)x + 0.5f) + c.jitter[0]) / (float)c.width;
     const float sx = ((px * 2.0f) - 1.0f) * c.tan_half * aspect;
-    const float py = ((float)y + 0.5f) / (float)c.height;
+    const float py = (((float)y + 0.5f) + c.jitter[1]) / (float)c.height;
     const float sy = (1.0f - (py * 2.0f)) * c.tan_half;
     float v[3];
     for (int i = 0; i < 3; ++i) {
@@ -662,6 +662,8 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
     if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
     if (opts->any_hit || opts->stack_limit < 0) return SRT_ERR_INVALID_ARG;
     if (opts->depth_mode != 0 && opts->depth_mode != 1) return SRT_ERR_INVALID_ARG;
+    if (opts->rng != 0 && opts->rng != 1) return SRT_ERR_INVALID_ARG;
+    if (opts->rng == 1) return SRT_ERR_UNSUPPORTED;  // batched plans draw Philox numbers
     if (batch->num_views < 0 || (batch->num_views > 0 && (!batch->cameras || !batch->spp)))
         return SRT_ERR_INVALID_ARG;
     if (batch->extra.count < 0 || batch->extra_spp < 0) return SRT_ERR_INVALID_ARG;

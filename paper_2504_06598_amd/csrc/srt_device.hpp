@@ -126,34 +126,32 @@ __device__ __forceinline__ uint32_t word_of(const uint4& w, uint32_t i)
 // u in [0, 1 - 2^-24], exact in FP32 and FP64.
 __device__ __forceinline__ double u_of_word(uint32_t w) { return (double)(w >> 8) * 0x1p-24; }
 
-// The acceptance test u < alpha = opacity * exp(-q / 2) (eqn "rr"), decided
-// exactly as in FP64 at FP32 cost: the FP32 value differs from the FP64 one
-// by well under 1e-6 relative (q rounded to FP32 moves exp(-q/2) by at most
-// 2.4e-7 relative for q <= 8, expf and the product add a few ulps), so any u
-// outside a band of 4e-6 relative around it is decided by the FP32 value;
-// inside the band (probability ~1e-5 per test) the FP64 value decides.
+// The paper's stateless trigonometric hash of a point (Sec. 4.2, eqns "hash"
+// and "rng", its coefficients), in FP32 as a shader evaluates it:
+// r1(q) = fract(b1 sin(a1 q)), r2(q) = fract(b2 sin(a2 . q)), xi(p) =
+// r2(p_xy + r1(p_z)). Both components of b2 are equal, so r2's two outputs
+// are equal and one is used. In FP32, b2 sin(.) ~ 4e4 leaves fract about 8
+// fractional bits; the hash's statistics, not its bits, are what it offers.
+__device__ __forceinline__ float fract(float v) { return v - floorf(v); }
+
+__device__ __forceinline__ float trig_hash(float px, float py, float pz)
+{
+    const float r1 = fract(47453.5453f * sinf(91.3458f * pz));
+    const float x = px + r1, y = py + r1;
+    return fract(43758.5453f * sinf(12.9898f * x + 78.233f * y));
+}
+
+// The acceptance test u < alpha = opacity * exp(-q / 2) (eqn "rr") in FP64,
+// for u from a Philox word (exact 24-bit) or a float. (An FP32 alpha with an
+// exact FP64 fallback band measured slower on gfx950 than the FP64 exp.)
 struct AlphaTest {
-    float lo, hi;
-    float opacity;
-    double q;
-    double a64;
+    double alpha;
 
-    __device__ __forceinline__ AlphaTest(float op, double q_) : opacity(op), q(q_), a64(-1.0)
-    {
-        const float a32 = op * expf(-0.5f * (float)q_);
-        const float band = 4e-6f * a32 + 1e-30f;
-        lo = a32 - band;
-        hi = a32 + band;
-    }
+    __device__ __forceinline__ AlphaTest(float op, double q) : alpha((double)op * exp(-0.5 * q)) {}
 
-    __device__ __forceinline__ bool accepts(uint32_t word)
-    {
-        const float u = (float)(word >> 8) * 0x1p-24f;  // exact
-        if (u < lo) return true;
-        if (u >= hi) return false;
-        if (a64 < 0.0) a64 = (double)opacity * exp(-0.5 * q);
-        return (double)u < a64;
-    }
+    __device__ __forceinline__ bool accepts(uint32_t word) const { return u_of_word(word) < alpha; }
+
+    __device__ __forceinline__ bool accepts_u(float u) const { return (double)u < alpha; }
 };
 
 // --------------------------------------------------------------------------

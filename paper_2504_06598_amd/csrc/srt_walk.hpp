@@ -182,12 +182,24 @@ struct ForwardCtx {
     uint32_t purpose, k0, k1;
 };
 
+// Hash-mode number of sample s for a candidate whose mean lies at depth t:
+// the hit position p = o + t d, moved by s along (1, 1, 1) so the samples of
+// one walk draw different numbers (the paper walks one sample per ray).
+__device__ __forceinline__ float hash_u(const Ray& ray, float t, uint32_t s)
+{
+    const float fs = (float)s;
+    return trig_hash((ray.ox + t * ray.dx) + fs, (ray.oy + t * ray.dy) + fs,
+                     (ray.oz + t * ray.dz) + fs);
+}
+
 struct FwdCounts {
     uint32_t cands = 0, philox = 0;
 };
 
-// Offer record r to the samples; true when an any-hit walk may stop.
-template <int N, bool ANY>
+// Offer record r to the samples; true when an any-hit walk may stop. HASH:
+// acceptance numbers from the trigonometric hash of the hit position instead
+// of Philox.
+template <int N, bool ANY, bool HASH = false>
 __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, const Ray& ray,
                                           const DepthCtx& dc, double tmin, double tmax,
                                           int32_t ign, uint32_t rid, uint32_t s0,
@@ -213,12 +225,19 @@ __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, co
     for (int k = 0; k < N; ++k) {
         if (k < st.n_act && key_less(t32, r.gid, st.bt[k], st.bg[k])) {
             const uint32_t s = s0 + (uint32_t)k;
-            if ((s >> 2) != grp) {
-                grp = s >> 2;
-                w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, fc.purpose), fc.k0, fc.k1);
-                ++cnt.philox;
+            bool acc;
+            if constexpr (!HASH) {
+                if ((s >> 2) != grp) {
+                    grp = s >> 2;
+                    w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, fc.purpose), fc.k0,
+                                      fc.k1);
+                    ++cnt.philox;
+                }
+                acc = at.accepts(word_of(w, s & 3u));
+            } else {
+                acc = at.accepts_u(hash_u(ray, (float)tm, s));
             }
-            if (at.accepts(word_of(w, s & 3u))) {
+            if (acc) {
                 st.bt[k] = t32;
                 st.bg[k] = r.gid;
                 changed = true;
@@ -239,7 +258,7 @@ __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, co
     return false;
 }
 
-template <int W, int N, bool ANY, class Stack>
+template <int W, int N, bool ANY, class Stack, bool HASH = false>
 __device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ nodes,
                                                const ForwardCtx& fc, const DepthCtx& dc,
                                                const Ray& ray, double tmin,
@@ -254,7 +273,7 @@ __device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ n
     FwdCounts fcnt;
     auto visit = [&](uint32_t ri) -> bool {
         const Record r = load_record(fc.recs, ri);
-        return fwd_offer<N, ANY>(st, r, ray, dc, tmin, tmax, ign, rid, s0, fc, fcnt);
+        return fwd_offer<N, ANY, HASH>(st, r, ray, dc, tmin, tmax, ign, rid, s0, fc, fcnt);
     };
     const int res = walk<W>(nodes, ray, st.tcut, dc.node_slack, stk, max_steps, n_nodes, n_prims,
                             visit);

@@ -71,7 +71,7 @@ struct Counts {
 
 // Trace every pass of one ray, shade and write its outputs. Returns false on
 // a stack overflow (nothing is written then).
-template <int W, int N, bool ANY>
+template <int W, int N, bool ANY, bool HASH>
 __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32_t* stk, int stride,
                                           int cap, Counts& cnt)
 {
@@ -99,7 +99,7 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
         int32_t bgid[N];
         if (live) {
             ++cnt.trav;
-            const int res = resolve_samples<W, N, ANY>(
+            const int res = resolve_samples<W, N, ANY, FlatStack, HASH>(
                 nodes, fc, dc, rd, (double)tmin_f, (double)tmax_f, ign, rid,
                 sbase + (uint32_t)(pass * N), n_act, stack, a.max_steps, bt, bgid, cnt.nodes,
                 cnt.prims, cnt.cands, cnt.philox);
@@ -151,7 +151,7 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
 
 // COUNT: accumulate the statistics counters (a launch without a counters
 // buffer compiles them away, which frees their registers).
-template <int W, int N, bool ANY, bool DEEP, bool COUNT>
+template <int W, int N, bool ANY, bool DEEP, bool COUNT, bool HASH>
 __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
 {
     __shared__ int32_t lds[DEEP ? 1 : LdsStack<W>::value * kBlock];
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
         for (int64_t it = gt; it < n; it += (int64_t)gridDim.x * kBlock) {
             const int64_t ray = a.ovf_list[it];
             ++deep_runs;
-            if (!trace_ray<W, N, ANY>(a, ray, stk, stride, cap, cnt)) {
+            if (!trace_ray<W, N, ANY, HASH>(a, ray, stk, stride, cap, cnt)) {
                 atomicAdd(&a.ctrl[1], 1u);
                 ++lost;
             }
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
     } else {
         const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
         const int64_t ray = a.img_w > 0 ? tile_pixel(t, a.img_w, a.R / a.img_w) : t;
-        if (ray >= 0 && ray < a.R && !trace_ray<W, N, ANY>(a, ray, stk, stride, cap, cnt)) {
+        if (ray >= 0 && ray < a.R && !trace_ray<W, N, ANY, HASH>(a, ray, stk, stride, cap, cnt)) {
             const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
             a.ovf_list[slot] = (uint32_t)ray;
         }
@@ -416,38 +416,44 @@ __global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
 
 using KernelFn = void (*)(TraceArgs);
 
-template <int W, int N, bool ANY>
+template <int W, int N, bool ANY, bool H>
 void pick(bool count, KernelFn* fast, KernelFn* deep)
 {
-    *fast = count ? k_trace<W, N, ANY, false, true> : k_trace<W, N, ANY, false, false>;
-    *deep = count ? k_trace<W, N, ANY, true, true> : k_trace<W, N, ANY, true, false>;
+    *fast = count ? k_trace<W, N, ANY, false, true, H> : k_trace<W, N, ANY, false, false, H>;
+    *deep = count ? k_trace<W, N, ANY, true, true, H> : k_trace<W, N, ANY, true, false, H>;
 }
 
-template <int W>
+template <int W, bool H>
 bool pick_w(int N, bool any, bool count, KernelFn* f, KernelFn* d)
 {
     if (any) {
         if (N != 1) return false;
-        pick<W, 1, true>(count, f, d);
+        pick<W, 1, true, H>(count, f, d);
         return true;
     }
     switch (N) {
-    case 1: pick<W, 1, false>(count, f, d); return true;
-    case 2: pick<W, 2, false>(count, f, d); return true;
-    case 4: pick<W, 4, false>(count, f, d); return true;
-    case 8: pick<W, 8, false>(count, f, d); return true;
+    case 1: pick<W, 1, false, H>(count, f, d); return true;
+    case 2: pick<W, 2, false, H>(count, f, d); return true;
+    case 4: pick<W, 4, false, H>(count, f, d); return true;
+    case 8: pick<W, 8, false, H>(count, f, d); return true;
     }
     return false;
 }
 
-bool pick_kernels(int W, int N, bool any, bool count, KernelFn* f, KernelFn* d)
+template <bool H>
+bool pick_h(int W, int N, bool any, bool count, KernelFn* f, KernelFn* d)
 {
     switch (W) {
-    case 2: return pick_w<2>(N, any, count, f, d);
-    case 4: return pick_w<4>(N, any, count, f, d);
-    case 8: return pick_w<8>(N, any, count, f, d);
+    case 2: return pick_w<2, H>(N, any, count, f, d);
+    case 4: return pick_w<4, H>(N, any, count, f, d);
+    case 8: return pick_w<8, H>(N, any, count, f, d);
     }
     return false;
+}
+
+bool pick_kernels(int W, int N, bool any, bool count, bool hash, KernelFn* f, KernelFn* d)
+{
+    return hash ? pick_h<true>(W, N, any, count, f, d) : pick_h<false>(W, N, any, count, f, d);
 }
 
 template <int W, int N, bool ANY>
@@ -503,6 +509,7 @@ srt_status validate_opts(const srt_trace_opts* o)
     if (o->image_width < 0) return SRT_ERR_INVALID_ARG;
     if (o->persistent != 0 && o->persistent != 1) return SRT_ERR_INVALID_ARG;
     if (o->refill_threshold < 0 || o->refill_threshold > 64) return SRT_ERR_INVALID_ARG;
+    if (o->rng != 0 && o->rng != 1) return SRT_ERR_INVALID_ARG;
     return SRT_OK;
 }
 
@@ -512,8 +519,10 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
                         void* workspace, hipStream_t s)
 {
     KernelFn fast = nullptr, deep = nullptr;
-    if (!pick_kernels(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr, &fast, &deep))
+    if (!pick_kernels(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr,
+                      o->rng == 1, &fast, &deep))
         return SRT_ERR_UNSUPPORTED;
+    if (o->rng == 1 && o->persistent) return SRT_ERR_UNSUPPORTED;  // Philox only
     const TraceWorkspace ws = trace_workspace(b, rays->count, workspace);
     TraceArgs a{};
     a.nodes = b->nodes;
@@ -586,9 +595,9 @@ __device__ __forceinline__ void camera_ray(const srt_camera& c, int32_t x, int32
                                            float d[3])
 {
     const float aspect = (float)c.width / (float)c.height;
-    const float px = ((float)x + 0.5f) / (float)c.width;
+    const float px = (((float)x + 0.5f) + c.jitter[0]) / (float)c.width;
     const float sx = ((px * 2.0f) - 1.0f) * c.tan_half * aspect;
-    const float py = ((float)y + 0.5f) / (float)c.height;
+    const float py = (((float)y + 0.5f) + c.jitter[1]) / (float)c.height;
     const float sy = (1.0f - (py * 2.0f)) * c.tan_half;
     float v[3];
     for (int i = 0; i < 3; ++i) {
@@ -902,7 +911,7 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
         // their start, the unoccluded ones cross the whole scene) always run on
         // work-stealing waves, which measured faster for them; camera and
         // mirror rays follow the caller's choice
-        so.persistent = pass == 0 ? 1 : opts->persistent;
+        so.persistent = pass == 0 && opts->rng == 0 ? 1 : opts->persistent;
         st = launch_trace(b, &rr, &so, nullptr, pass == 0 ? w.sh_hit : w.mr_hit, nullptr, counters,
                           w.trace_ws, s);
         if (st != SRT_OK) return st;

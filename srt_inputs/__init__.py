@@ -167,6 +167,9 @@ class Camera:
     tan_half: np.float32
     width: int
     height: int
+    # sub-pixel offset from the pixel centre, in pixels ([-0.5, 0.5); a
+    # frame's perturbation of its camera rays)
+    jitter: tuple = (0.0, 0.0)
 
     def as_array(self) -> np.ndarray:
         """Packed FP32 record [eye3, forward3, right3, up3, tan_half, 0, 0, 0]."""
@@ -206,8 +209,9 @@ def camera_rays(cam: Camera):
     Every operation is a single correctly rounded FP32 operation in the order
     written (no fused multiply-add), so a device generator that performs the
     same operations in the same order reproduces these bits exactly:
-        px = (x + 0.5) / W;  sx = ((px * 2) - 1) * tan_half * aspect
-        py = (y + 0.5) / H;  sy = (1 - (py * 2)) * tan_half
+        px = ((x + 0.5) + jx) / W;  sx = ((px * 2) - 1) * tan_half * aspect
+        py = ((y + 0.5) + jy) / H;  sy = (1 - (py * 2)) * tan_half
+    ((jx, jy) = cam.jitter, (0, 0) by default: the pixel centres.)
         v  = (f + sx * r) + sy * u;  d = v / sqrt((vx*vx + vy*vy) + vz*vz)
     Returns (origins [H*W,3], dirs [H*W,3]) as f32, pixel index y*W + x.
     """
@@ -215,9 +219,10 @@ def camera_rays(cam: Camera):
     x = np.arange(W, dtype=F32)
     y = np.arange(H, dtype=F32)
     aspect = F32(W) / F32(H)
-    px = (x + F32(0.5)) / F32(W)
+    jx, jy = F32(cam.jitter[0]), F32(cam.jitter[1])
+    px = ((x + F32(0.5)) + jx) / F32(W)
     sx = ((px * F32(2.0)) - F32(1.0)) * cam.tan_half * aspect
-    py = (y + F32(0.5)) / F32(H)
+    py = ((y + F32(0.5)) + jy) / F32(H)
     sy = (F32(1.0) - (py * F32(2.0))) * cam.tan_half
     SX = np.broadcast_to(sx[None, :], (H, W))
     SY = np.broadcast_to(sy[:, None], (H, W))
@@ -228,6 +233,42 @@ def camera_rays(cam: Camera):
     d = d / n[..., None]
     o = np.ascontiguousarray(np.broadcast_to(cam.eye, (H * W, 3)), dtype=F32)
     return o, np.ascontiguousarray(d.reshape(H * W, 3), dtype=F32)
+
+
+def sobol2(n: int) -> np.ndarray:
+    """The first n points of the two-dimensional Sobol sequence (Sobol 1967;
+    no scrambling), as [n,2] f64 in [0,1): dimension 1 is the base-2 van der
+    Corput sequence, dimension 2 uses the direction numbers of the primitive
+    polynomial x + 1 (m_1 = 1, m_k = 2 m_{k-1} xor m_{k-1}). Point i is the
+    xor of the direction numbers of the set bits of i's Gray code."""
+    bits = 32
+    v1 = [1 << (bits - 1 - k) for k in range(bits)]
+    m, v2 = 1, []
+    for k in range(bits):
+        if k > 0:
+            m = (2 * m) ^ m
+        v2.append(m << (bits - 1 - k))
+    out = np.zeros((n, 2))
+    for i in range(n):
+        g = i ^ (i >> 1)
+        x = y = 0
+        k = 0
+        while g:
+            if g & 1:
+                x ^= v1[k]
+                y ^= v2[k]
+            g >>= 1
+            k += 1
+        out[i] = (x / 2.0 ** bits, y / 2.0 ** bits)
+    return out
+
+
+def jittered(cam: Camera, frame: int) -> Camera:
+    """The camera of frame `frame`: its rays perturbed by Sobol point `frame`
+    (offset from the pixel centre), the frame-dependent camera ray generation
+    of Sec. 4.2."""
+    p = sobol2(frame + 1)[frame]
+    return dataclasses.replace(cam, jitter=(float(F32(p[0] - 0.5)), float(F32(p[1] - 0.5))))
 
 
 def ring_cameras(n_views, radius, width, height, vfov_deg=60.0):

@@ -396,3 +396,100 @@ def test_persistent_option_errors(srt):
                      device="cuda")
     assert lib.srt_trace_forward(bvh.handle, C.byref(rays), C.byref(opts), None, None, None,
                                  None, ws.data_ptr(), ws.numel(), None) == 1
+
+
+def test_camera_jitter_bit_exact(srt):
+    cam = si.look_at((0.3, 0.1, 3), (0, 0, 0), 33, 21)
+    for frame in (1, 6, 99):
+        jc = si.jittered(cam, frame)
+        o, d = srt.srt_camera_rays(jc)
+        ho, hd = si.camera_rays(jc)
+        assert np.array_equal(to_np(d), hd) and np.array_equal(to_np(o), ho)
+
+
+def test_hash_rng_accepts_with_probability_alpha(srt):
+    """One Gaussian on the axis of parallel rays (q = 0 on the axis, so alpha
+    is its opacity): the share of samples that accept it, over many rays and
+    samples, is alpha within the binomial spread plus the hash's FP32
+    resolution."""
+    from scipy.stats import binom
+    for op in (0.2, 0.55, 0.9):
+        sc = si.Scene(np.zeros((1, 3), np.float32), np.full((1, 3), np.log(0.3), np.float32),
+                      np.array([[1, 0, 0, 0]], np.float32),
+                      np.array([np.log(op / (1 - op))], np.float32),
+                      np.zeros((1, 1, 3), np.float32), 0)
+        bvh = srt.srt_build_bvh(device_scene(sc), 4, 1)
+        n = 4096
+        rng = np.random.default_rng(3)
+        o = np.zeros((n, 3), np.float32)
+        o[:, :2] = rng.uniform(-1e-3, 1e-3, (n, 2))
+        o[:, 2] = -3.0
+        d = np.tile(np.array([[0, 0, 1]], np.float32), (n, 1))
+        res = _trace(srt, bvh, o, d, spp=8, n_per_traversal=8, rng="hash")
+        hits = int((res["hit_gid"] >= 0).sum())
+        total = res["hit_gid"].size
+        alpha = float(oracle.Records(sc).op[0])
+        lo, hi = binom.ppf([1e-6, 1 - 1e-6], total, alpha)
+        slack = total / 128.0  # the FP32 hash resolves about 1/256
+        assert lo - slack <= hits <= hi + slack, (op, hits / total, alpha)
+
+
+def test_hash_rng_converges_to_the_exact_composite(srt):
+    """Frames of Sobol-jittered camera rays with hash acceptance: the frame
+    average of each pixel approaches the average of the exact composites of
+    the same jittered rays (the oracle), within the sample noise and the
+    hash's FP32 resolution."""
+    say("hash RNG: 96 jittered frames of a 24x24 view")
+    sc = tiny_scene(23, 600, (0.04, 0.12))
+    cam = si.look_at((0.1, 0.2, 3), (0, 0, 0), 24, 24)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
+    rec = oracle.Records(sc)
+    F = 96
+    acc = np.zeros((24 * 24, 3))
+    exact = np.zeros((24 * 24, 3))
+    var = np.zeros((24 * 24, 3))
+    for f in range(F):
+        jc = si.jittered(cam, f + 1)
+        o, d = si.camera_rays(jc)
+        res = _trace(srt, bvh, o, d, spp=1, rng="hash", want_hits=False)
+        acc += res["rgb"]
+        ex = oracle.composite(rec, oracle.Rays(o, d))
+        exact += ex["L"]
+        var += ex["var"]
+    acc /= F
+    exact /= F
+    se = np.sqrt(var / F / F)
+    err = np.abs(acc - exact)
+    assert np.mean(err <= 5 * se + 0.02) > 0.995, float((err / (se + 1e-3)).max())
+    # and the average error is at the level of the noise
+    assert err.mean() < 3 * se.mean() + 0.005
+
+
+def test_hash_rng_unsupported_combinations(srt):
+    sc = tiny_scene(24, 100)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    o = torch.zeros((10, 3), device="cuda")
+    d = torch.tensor([[0.0, 0.0, 1.0]] * 10, device="cuda")
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_trace_forward(bvh, o, d, rng="hash", persistent=True)
+    assert e.value.code == 4
+    g = torch.ones((10, 3), device="cuda")
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_trace_backward(bvh, o, d, g, rng="hash")  # recompute needs numbers
+    assert e.value.code == 4
+    fw = srt.srt_trace_forward(bvh, o, d, rng="hash", spp=2, n_per_traversal=2)
+    srt.srt_trace_backward(bvh, o, d, g, hit_gid=fw["hit_gid"], hit_t=fw["hit_t"], spp=2,
+                           n_per_traversal=2, rng="hash")  # stored results: fine
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_batch_plan_create(bvh, [si.look_at((0, 0, 3), (0, 0, 0), 8, 8)], [1],
+                                  rng="hash")
+    assert e.value.code == 4
+    opts = srt._opts(0, 1, 1, 0, (0, 0, 0), False, 0)
+    opts.rng = 2
+    import ctypes as C
+    lib = srt._lib.load()
+    rays = srt._lib.SrtRays(10, o.data_ptr(), d.data_ptr(), None, None, None, None, None, 0)
+    ws = torch.empty(lib.srt_trace_workspace_size(bvh.handle, 10), dtype=torch.uint8,
+                     device="cuda")
+    assert lib.srt_trace_forward(bvh.handle, C.byref(rays), C.byref(opts), None, None, None,
+                                 None, ws.data_ptr(), ws.numel(), None) == 1

@@ -91,3 +91,35 @@ def test_workload_recipes():
     sc3 = si.workload(3, small=True)["scene"]
     r3 = np.linalg.norm(sc3.means.astype(np.float64), axis=1)
     assert np.allclose(np.sort(np.unique(np.round(r3, 4))), [0.5, 1.0, 1.5, 2.0])
+
+
+def test_sobol_points_match_scipy():
+    from scipy.stats import qmc
+    ref = qmc.Sobol(d=2, scramble=False).random(512)
+    np.testing.assert_array_equal(si.sobol2(512), ref)
+
+
+def test_jittered_rays_hit_their_subpixel_positions():
+    cam = si.look_at((0.3, 0.1, 3), (0, 0, 0), 40, 24)
+    for frame in (0, 1, 5, 37):
+        jc = si.jittered(cam, frame)
+        assert -0.5 <= jc.jitter[0] < 0.5 and -0.5 <= jc.jitter[1] < 0.5
+        o, d = si.camera_rays(jc)
+        d = d.astype(np.float64)
+        f, r, u = (np.asarray(v, np.float64) for v in (cam.forward, cam.right, cam.up))
+        # back-project onto the image plane at distance 1 along forward
+        p = d / (d @ f)[:, None]
+        sx, sy = p @ r, p @ u
+        aspect = cam.width / cam.height
+        th = float(cam.tan_half)
+        px = (sx / (th * aspect) + 1) / 2 * cam.width
+        py = (1 - sy / th) / 2 * cam.height
+        x = np.tile(np.arange(cam.width), cam.height)
+        y = np.repeat(np.arange(cam.height), cam.width)
+        np.testing.assert_allclose(px, x + 0.5 + jc.jitter[0], atol=2e-4)
+        np.testing.assert_allclose(py, y + 0.5 + jc.jitter[1], atol=2e-4)
+    # no jitter: the pixel centres, bit for bit as before
+    o0, d0 = si.camera_rays(cam)
+    o1, d1 = si.camera_rays(si.Camera(cam.eye, cam.forward, cam.right, cam.up, cam.tan_half,
+                                      cam.width, cam.height, (0.0, 0.0)))
+    assert np.array_equal(d0, d1)
