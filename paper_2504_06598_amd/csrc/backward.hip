@@ -37,7 +37,7 @@ using namespace srt;
 namespace {
 
 constexpr int kBlock = 128;
-constexpr int kLdsEntries = 32;
+constexpr int kLdsEntries = 16;  // on-chip stack entries per lane (deeper ones in global memory)
 constexpr int kAccStride = 16;  // floats per Gaussian: sa, sa p (3), sa p p^T (6), pad (6)
 constexpr int kAccVals = 10;
 constexpr int kTableSlots = 128;  // LDS table of the alpha sums (a 128-ray tile of the
@@ -127,7 +127,7 @@ __device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, con
     }
 }
 
-template <int W, int N, bool COUNT, bool RB>
+template <int W, int N, bool COUNT, bool RB, int DM>
 __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
 {
     __shared__ int32_t lds[kLdsEntries * kBlock];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                 } else {
                     const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
                     uint32_t dummy_nodes = 0, dummy_prims = 0;
-                    const int res = resolve_samples<W, N, false>(
+                    const int res = resolve_samples<W, N, false, TwoTierStack, false, DM>(
                         nodes, fc, dc, rr, tmin, tmax, ign, rid, sbase + (uint32_t)(pass * N),
                         n_act, stk, a.max_steps, ta, ga, dummy_nodes, dummy_prims, n_fwd_cands,
                         n_philox);
@@ -252,12 +252,12 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                 const uint32_t s0 = sbase + (uint32_t)(pass * N);
                 auto visit = [&](uint32_t ri) -> bool {
                     const Record r = load_record(a.recs, ri);
-                    if (dc.mode == 0 ? sphere_reject(r, rr, tmin_f, tcut)
-                                     : sphere_reject(r, rr, -INFINITY, INFINITY))
+                    if (depth_mode_of<DM>(dc) == 0 ? sphere_reject(r, rr, tmin_f, tcut)
+                                                   : sphere_reject(r, rr, -INFINITY, INFINITY))
                         return false;
                     double tm, q, p[3];
                     isect_tqp(r, rr, tm, q, p);
-                    const double t = depth_of(dc, r, rr, tm);
+                    const double t = depth_of<DM>(dc, r, rr, tm);
                     if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
                     const float t32 = (float)t;
                     if (!key_less(t32, r.gid, wt, wg)) return false;
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     bool found = false;
                     uint4 w = make_uint4(0, 0, 0, 0);
                     uint32_t grp = 0xFFFFFFFFu;
-                    AlphaTest at(r.opacity, q);
+                    double alpha64 = -1.0;  // formed only if some sample needs a test
 #pragma unroll
                     for (int k = 0; k < N; ++k) {
                         if (k >= n_act) continue;
@@ -286,7 +286,8 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                                         a.k1);
                                     ++n_philox;
                                 }
-                                if (at.accepts(word_of(w, smp & 3u))) {
+                                if (alpha64 < 0.0) alpha64 = (double)r.opacity * exp(-0.5 * q);
+                                if (u_of_word(word_of(w, smp & 3u)) < alpha64) {
                                     tb[k] = t32;
                                     gb[k] = r.gid;
                                     found = true;
@@ -331,8 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     table_add(table, a.acc, r.gid, v);
                     return false;
                 };
-                const int res = walk<W>(nodes, rr, tcut, dc.node_slack, stk, a.max_steps, n_nodes,
-                                        n_prims, visit);
+                const int res = walk<W>(nodes, rr, tcut, DM == 0 ? 0.0f : dc.node_slack, stk,
+                                        a.max_steps, n_nodes, n_prims, visit);
                 if (res == kWalkOverflow) ++n_lost;
                 if constexpr (RB) {
                     // -<g, X2> on the alpha of each sample's first accepted a (X2 the
@@ -505,33 +506,39 @@ __global__ void k_chain(int64_t G, const float* __restrict__ acc, const float* _
 
 using BwdFn = void (*)(BwdArgs);
 
-template <int W, bool C, bool RB>
+template <int W, bool C, bool RB, int DM>
 BwdFn pick_n(int N)
 {
     switch (N) {
-    case 1: return k_backward<W, 1, C, RB>;
-    case 2: return k_backward<W, 2, C, RB>;
-    case 4: return k_backward<W, 4, C, RB>;
-    case 8: return k_backward<W, 8, C, RB>;
+    case 1: return k_backward<W, 1, C, RB, DM>;
+    case 2: return k_backward<W, 2, C, RB, DM>;
+    case 4: return k_backward<W, 4, C, RB, DM>;
+    case 8: return k_backward<W, 8, C, RB, DM>;
     }
     return nullptr;
 }
 
-template <int W>
+template <int W, int DM>
 BwdFn pick_w(int N, bool count, bool rb)
 {
-    if (rb) return count ? pick_n<W, true, true>(N) : pick_n<W, false, true>(N);
-    return count ? pick_n<W, true, false>(N) : pick_n<W, false, false>(N);
+    if (rb) return count ? pick_n<W, true, true, DM>(N) : pick_n<W, false, true, DM>(N);
+    return count ? pick_n<W, true, false, DM>(N) : pick_n<W, false, false, DM>(N);
 }
 
-BwdFn pick(int W, int N, bool count, bool rb)
+template <int DM>
+BwdFn pick_dm(int W, int N, bool count, bool rb)
 {
     switch (W) {
-    case 2: return pick_w<2>(N, count, rb);
-    case 4: return pick_w<4>(N, count, rb);
-    case 8: return pick_w<8>(N, count, rb);
+    case 2: return pick_w<2, DM>(N, count, rb);
+    case 4: return pick_w<4, DM>(N, count, rb);
+    case 8: return pick_w<8, DM>(N, count, rb);
     }
     return nullptr;
+}
+
+BwdFn pick(int W, int N, bool count, bool rb, int depth_mode)
+{
+    return depth_mode == 0 ? pick_dm<0>(W, N, count, rb) : pick_dm<1>(W, N, count, rb);
 }
 
 constexpr int64_t kMaxBwdBlocks = 2048;
@@ -637,7 +644,7 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     a.r_max = b->r_max;
     a.img_w = opts->image_width;
     a.leaf_pos = b->leaf_pos;
-    BwdFn fn = pick(b->W, N, counters != nullptr, opts->estimator == 1);
+    BwdFn fn = pick(b->W, N, counters != nullptr, opts->estimator == 1, opts->depth_mode);
     if (!fn) return SRT_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(fn, dim3(ws.threads / kBlock), dim3(kBlock), 0, s, a);
     SRT_HIP_TRY(hipGetLastError());

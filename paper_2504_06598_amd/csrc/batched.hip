@@ -182,7 +182,7 @@ struct LaneCounts {
 // Resolve samples [pass*N, pass*N + n_act) of ray b, shade them and add their
 // colours / spp to the output (atomically when `atomic`). Returns false on a
 // stack overflow (nothing was written).
-template <int W, int N, class Stack>
+template <int W, int N, int DM, class Stack>
 __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int pass, Stack& stk,
                                          LaneCounts& cnt, bool atomic, float acc[3])
 {
@@ -193,7 +193,7 @@ __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int 
     float bt[N];
     int32_t bg[N];
     ++cnt.trav;
-    const int res = resolve_samples<W, N, false>(
+    const int res = resolve_samples<W, N, false, Stack, false, DM>(
         static_cast<const WideNode<W>*>(a.nodes), fc, dc, ray, (double)b.tmin, (double)b.tmax, -1,
         b.rid, a.soff + (uint32_t)(pass * N), n_act, stk, a.max_steps, bt, bg, cnt.nodes, cnt.prims,
         cnt.cands, cnt.philox);
@@ -245,7 +245,7 @@ __device__ __forceinline__ void flush_counts(const BatchArgs& a, const LaneCount
 // ---------------------------------------------------------------------------
 // Plain: one lane per ray.
 // ---------------------------------------------------------------------------
-template <int W, int N, bool COUNT>
+template <int W, int N, bool COUNT, int DM>
 __global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
 {
     __shared__ int32_t lds[32 * kPlainBlock];
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
             float acc[3] = {0.0f, 0.0f, 0.0f};
             bool ok = true;
             for (int pass = 0; pass * N < b.spp && ok; ++pass)
-                ok = run_pass<W, N>(a, b, pass, stk, cnt, false, acc);
+                ok = run_pass<W, N, DM>(a, b, pass, stk, cnt, false, acc);
             if (ok) {
                 cnt.samples += (uint32_t)b.spp;
                 const float w = 1.0f / (float)b.spp;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
 }
 
 // Plain deep pass: queued rays with the global-memory stack.
-template <int W, int N, bool COUNT>
+template <int W, int N, bool COUNT, int DM>
 __global__ __launch_bounds__(kPlainBlock) void k_plain_deep(BatchArgs a)
 {
     const int64_t gt = blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_deep(BatchArgs a)
         bool ok = true;
         ++deep;
         for (int pass = 0; pass * N < b.spp && ok; ++pass)
-            ok = run_pass<W, N>(a, b, pass, stk, cnt, false, acc);
+            ok = run_pass<W, N, DM>(a, b, pass, stk, cnt, false, acc);
         if (!ok) {
             ++lost;
             atomicAdd(&a.ctrl[1], 1u);
@@ -329,7 +329,7 @@ __device__ __forceinline__ void decode_item(const BatchArgs& a, int64_t item, in
     }
 }
 
-template <int W, int N, bool COUNT>
+template <int W, int N, bool COUNT, int DM>
 __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
 {
     __shared__ int32_t lds[32 * kPersistBlock];
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
             NodeBuf<W> nb;
             load_node<W>(nodes, node, nb);
             uint32_t key[W];
-            slab_keys<W>(nb, lr, st.tcut + dc.node_slack, key);
+            slab_keys<W>(nb, lr, st.tcut + (DM == 0 ? 0.0f : dc.node_slack), key);
             sort_keys<W>(key);
             int nh = 0;
 #pragma unroll
@@ -430,7 +430,8 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
             for (uint32_t i = 0; i < count; ++i) {
                 ++cnt.prims;
                 const Record r = load_record(a.recs, first + i);
-                fwd_offer<N, false>(st, r, lr, dc, tmin_d, tmax_d, -1, b.rid, s0, fc, fcnt);
+                fwd_offer<N, false, false, DM>(st, r, lr, dc, tmin_d, tmax_d, -1, b.rid, s0, fc,
+                                                     fcnt);
             }
             cnt.cands += fcnt.cands;
             cnt.philox += fcnt.philox;
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
 }
 
 // Persistent deep pass: queued items with the global-memory stack.
-template <int W, int N, bool COUNT>
+template <int W, int N, bool COUNT, int DM>
 __global__ __launch_bounds__(kPlainBlock) void k_persistent_deep(BatchArgs a)
 {
     const int64_t gt = blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_persistent_deep(BatchArgs a)
         decode_item(a, (int64_t)a.ovf_list[it], seg, ray, pass);
         const BRay b = seg_ray(a, a.segs[seg], ray);
         ++deep;
-        if (!run_pass<W, N>(a, b, pass, stk, cnt, true, nullptr)) {
+        if (!run_pass<W, N, DM>(a, b, pass, stk, cnt, true, nullptr)) {
             ++lost;
             atomicAdd(&a.ctrl[1], 1u);
         }
@@ -515,35 +516,42 @@ __global__ void k_reset(unsigned long long* work, uint32_t* ctrl)
 
 using BatchFn = void (*)(BatchArgs);
 
-template <int W, int N, bool C>
+template <int W, int N, bool C, int DM>
 void pick4(BatchFn k[4])
 {
-    k[0] = k_plain<W, N, C>;
-    k[1] = k_plain_deep<W, N, C>;
-    k[2] = k_persistent<W, N, C>;
-    k[3] = k_persistent_deep<W, N, C>;
+    k[0] = k_plain<W, N, C, DM>;
+    k[1] = k_plain_deep<W, N, C, DM>;
+    k[2] = k_persistent<W, N, C, DM>;
+    k[3] = k_persistent_deep<W, N, C, DM>;
 }
 
-template <int W, bool C>
+template <int W, bool C, int DM>
 bool pick_w(int N, BatchFn k[4])
 {
     switch (N) {
-    case 1: pick4<W, 1, C>(k); return true;
-    case 2: pick4<W, 2, C>(k); return true;
-    case 4: pick4<W, 4, C>(k); return true;
-    case 8: pick4<W, 8, C>(k); return true;
+    case 1: pick4<W, 1, C, DM>(k); return true;
+    case 2: pick4<W, 2, C, DM>(k); return true;
+    case 4: pick4<W, 4, C, DM>(k); return true;
+    case 8: pick4<W, 8, C, DM>(k); return true;
     }
     return false;
 }
 
-bool pick(int W, int N, bool count, BatchFn k[4])
+template <int DM>
+bool pick_dm(int W, int N, bool count, BatchFn k[4])
 {
     switch (W) {
-    case 2: return count ? pick_w<2, true>(N, k) : pick_w<2, false>(N, k);
-    case 4: return count ? pick_w<4, true>(N, k) : pick_w<4, false>(N, k);
-    case 8: return count ? pick_w<8, true>(N, k) : pick_w<8, false>(N, k);
+    case 2: return count ? pick_w<2, true, DM>(N, k) : pick_w<2, false, DM>(N, k);
+    case 4: return count ? pick_w<4, true, DM>(N, k) : pick_w<4, false, DM>(N, k);
+    case 8: return count ? pick_w<8, true, DM>(N, k) : pick_w<8, false, DM>(N, k);
     }
     return false;
+}
+
+// kernels with the depth mode fixed at compile time (fewer registers)
+bool pick(int W, int N, bool count, int depth_mode, BatchFn k[4])
+{
+    return depth_mode == 0 ? pick_dm<0>(W, N, count, k) : pick_dm<1>(W, N, count, k);
 }
 
 }  // namespace
@@ -590,7 +598,8 @@ srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* count
 {
     const srt_bvh* b = p->bvh;
     BatchFn k[4];
-    if (!pick(b->W, p->opts.n_per_traversal, counters != nullptr, k)) return SRT_ERR_UNSUPPORTED;
+    if (!pick(b->W, p->opts.n_per_traversal, counters != nullptr, p->opts.depth_mode, k))
+        return SRT_ERR_UNSUPPORTED;
     BatchArgs a{};
     a.nodes = b->nodes;
     a.recs = b->recs;

@@ -138,10 +138,19 @@ __device__ __forceinline__ DepthCtx make_depth(int mode, const float axis[3], co
     return c;
 }
 
+// DM: the depth mode fixed at compile time (0 mean, 1 centre), or -1 to read
+// it from the context (one kernel for both modes, at some register cost).
+template <int DM>
+__device__ __forceinline__ int depth_mode_of(const DepthCtx& c)
+{
+    return DM < 0 ? c.mode : DM;
+}
+
+template <int DM = -1>
 __device__ __forceinline__ double depth_of(const DepthCtx& c, const Record& r, const Ray& ray,
                                            double t_mean)
 {
-    if (c.mode == 0) return t_mean;
+    if (depth_mode_of<DM>(c) == 0) return t_mean;
     const double wx = (double)r.mu[0] - (double)ray.ox;
     const double wy = (double)r.mu[1] - (double)ray.oy;
     const double wz = (double)r.mu[2] - (double)ray.oz;
@@ -199,20 +208,20 @@ struct FwdCounts {
 // Offer record r to the samples; true when an any-hit walk may stop. HASH:
 // acceptance numbers from the trigonometric hash of the hit position instead
 // of Philox.
-template <int N, bool ANY, bool HASH = false>
+template <int N, bool ANY, bool HASH = false, int DM = -1>
 __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, const Ray& ray,
                                           const DepthCtx& dc, double tmin, double tmax,
                                           int32_t ign, uint32_t rid, uint32_t s0,
                                           const ForwardCtx& fc, FwdCounts& cnt)
 {
-    if (dc.mode == 0) {
+    if (depth_mode_of<DM>(dc) == 0) {
         if (sphere_reject(r, ray, ray.tmin, st.tcut)) return false;
     } else if (sphere_reject(r, ray, -INFINITY, INFINITY)) {
         return false;
     }
     double tm, q;
     isect_tq(r, ray, tm, q);
-    const double t = depth_of(dc, r, ray, tm);
+    const double t = depth_of<DM>(dc, r, ray, tm);
     if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
     ++cnt.cands;
     const float t32 = (float)t;
@@ -258,7 +267,7 @@ __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, co
     return false;
 }
 
-template <int W, int N, bool ANY, class Stack, bool HASH = false>
+template <int W, int N, bool ANY, class Stack, bool HASH = false, int DM = -1>
 __device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ nodes,
                                                const ForwardCtx& fc, const DepthCtx& dc,
                                                const Ray& ray, double tmin,
@@ -273,10 +282,10 @@ __device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ n
     FwdCounts fcnt;
     auto visit = [&](uint32_t ri) -> bool {
         const Record r = load_record(fc.recs, ri);
-        return fwd_offer<N, ANY, HASH>(st, r, ray, dc, tmin, tmax, ign, rid, s0, fc, fcnt);
+        return fwd_offer<N, ANY, HASH, DM>(st, r, ray, dc, tmin, tmax, ign, rid, s0, fc, fcnt);
     };
-    const int res = walk<W>(nodes, ray, st.tcut, dc.node_slack, stk, max_steps, n_nodes, n_prims,
-                            visit);
+    const float slack = DM == 0 ? 0.0f : dc.node_slack;
+    const int res = walk<W>(nodes, ray, st.tcut, slack, stk, max_steps, n_nodes, n_prims, visit);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         bt[k] = st.bt[k];

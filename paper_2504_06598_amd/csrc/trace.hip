@@ -71,7 +71,7 @@ struct Counts {
 
 // Trace every pass of one ray, shade and write its outputs. Returns false on
 // a stack overflow (nothing is written then).
-template <int W, int N, bool ANY, bool HASH>
+template <int W, int N, bool ANY, bool HASH, int DM>
 __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32_t* stk, int stride,
                                           int cap, Counts& cnt)
 {
@@ -99,7 +99,7 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
         int32_t bgid[N];
         if (live) {
             ++cnt.trav;
-            const int res = resolve_samples<W, N, ANY, FlatStack, HASH>(
+            const int res = resolve_samples<W, N, ANY, FlatStack, HASH, DM>(
                 nodes, fc, dc, rd, (double)tmin_f, (double)tmax_f, ign, rid,
                 sbase + (uint32_t)(pass * N), n_act, stack, a.max_steps, bt, bgid, cnt.nodes,
                 cnt.prims, cnt.cands, cnt.philox);
@@ -151,7 +151,7 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
 
 // COUNT: accumulate the statistics counters (a launch without a counters
 // buffer compiles them away, which frees their registers).
-template <int W, int N, bool ANY, bool DEEP, bool COUNT, bool HASH>
+template <int W, int N, bool ANY, bool DEEP, bool COUNT, bool HASH, int DM>
 __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
 {
     __shared__ int32_t lds[DEEP ? 1 : LdsStack<W>::value * kBlock];
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
         for (int64_t it = gt; it < n; it += (int64_t)gridDim.x * kBlock) {
             const int64_t ray = a.ovf_list[it];
             ++deep_runs;
-            if (!trace_ray<W, N, ANY, HASH>(a, ray, stk, stride, cap, cnt)) {
+            if (!trace_ray<W, N, ANY, HASH, DM>(a, ray, stk, stride, cap, cnt)) {
                 atomicAdd(&a.ctrl[1], 1u);
                 ++lost;
             }
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
     } else {
         const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
         const int64_t ray = a.img_w > 0 ? tile_pixel(t, a.img_w, a.R / a.img_w) : t;
-        if (ray >= 0 && ray < a.R && !trace_ray<W, N, ANY, HASH>(a, ray, stk, stride, cap, cnt)) {
+        if (ray >= 0 && ray < a.R && !trace_ray<W, N, ANY, HASH, DM>(a, ray, stk, stride, cap, cnt)) {
             const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
             a.ovf_list[slot] = (uint32_t)ray;
         }
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a)
 constexpr int kPersistBlock = 64;
 constexpr int kDefaultRefill = 16;
 
-template <int W, int N, bool ANY, bool COUNT>
+template <int W, int N, bool ANY, bool COUNT, int DM>
 __global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
 {
     __shared__ int32_t lds[LdsStack<W>::value * kPersistBlock];
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
             NodeBuf<W> nb;
             load_node<W>(nodes, node, nb);
             uint32_t key[W];
-            slab_keys<W>(nb, lr, st.tcut + dc.node_slack, key);
+            slab_keys<W>(nb, lr, st.tcut + (DM == 0 ? 0.0f : dc.node_slack), key);
             sort_keys<W>(key);
             int nh = 0;
 #pragma unroll
@@ -340,8 +340,8 @@ __global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
             for (uint32_t i = 0; i < count && !stop; ++i) {
                 ++cnt.prims;
                 const Record r = load_record(a.recs, first + i);
-                stop = fwd_offer<N, ANY>(st, r, lr, dc, (double)tmin_f, (double)tmax_f, ign, rid,
-                                         s0, fc, fcnt);
+                stop = fwd_offer<N, ANY, false, DM>(st, r, lr, dc, (double)tmin_f,
+                                                    (double)tmax_f, ign, rid, s0, fc, fcnt);
             }
             cnt.cands += fcnt.cands;
             cnt.philox += fcnt.philox;
@@ -416,73 +416,85 @@ __global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
 
 using KernelFn = void (*)(TraceArgs);
 
-template <int W, int N, bool ANY, bool H>
+template <int W, int N, bool ANY, bool H, int DM>
 void pick(bool count, KernelFn* fast, KernelFn* deep)
 {
-    *fast = count ? k_trace<W, N, ANY, false, true, H> : k_trace<W, N, ANY, false, false, H>;
-    *deep = count ? k_trace<W, N, ANY, true, true, H> : k_trace<W, N, ANY, true, false, H>;
+    *fast = count ? k_trace<W, N, ANY, false, true, H, DM> : k_trace<W, N, ANY, false, false, H, DM>;
+    *deep = count ? k_trace<W, N, ANY, true, true, H, DM> : k_trace<W, N, ANY, true, false, H, DM>;
 }
 
-template <int W, bool H>
+template <int W, bool H, int DM>
 bool pick_w(int N, bool any, bool count, KernelFn* f, KernelFn* d)
 {
     if (any) {
         if (N != 1) return false;
-        pick<W, 1, true, H>(count, f, d);
+        pick<W, 1, true, H, DM>(count, f, d);
         return true;
     }
     switch (N) {
-    case 1: pick<W, 1, false, H>(count, f, d); return true;
-    case 2: pick<W, 2, false, H>(count, f, d); return true;
-    case 4: pick<W, 4, false, H>(count, f, d); return true;
-    case 8: pick<W, 8, false, H>(count, f, d); return true;
+    case 1: pick<W, 1, false, H, DM>(count, f, d); return true;
+    case 2: pick<W, 2, false, H, DM>(count, f, d); return true;
+    case 4: pick<W, 4, false, H, DM>(count, f, d); return true;
+    case 8: pick<W, 8, false, H, DM>(count, f, d); return true;
     }
     return false;
 }
 
-template <bool H>
+template <bool H, int DM>
 bool pick_h(int W, int N, bool any, bool count, KernelFn* f, KernelFn* d)
 {
     switch (W) {
-    case 2: return pick_w<2, H>(N, any, count, f, d);
-    case 4: return pick_w<4, H>(N, any, count, f, d);
-    case 8: return pick_w<8, H>(N, any, count, f, d);
+    case 2: return pick_w<2, H, DM>(N, any, count, f, d);
+    case 4: return pick_w<4, H, DM>(N, any, count, f, d);
+    case 8: return pick_w<8, H, DM>(N, any, count, f, d);
     }
     return false;
 }
 
-bool pick_kernels(int W, int N, bool any, bool count, bool hash, KernelFn* f, KernelFn* d)
+// Philox kernels come with the depth mode fixed at compile time (fewer
+// registers); the hash kernels read it at run time.
+bool pick_kernels(int W, int N, bool any, bool count, bool hash, int depth_mode, KernelFn* f,
+                  KernelFn* d)
 {
-    return hash ? pick_h<true>(W, N, any, count, f, d) : pick_h<false>(W, N, any, count, f, d);
+    if (hash) return pick_h<true, -1>(W, N, any, count, f, d);
+    return depth_mode == 0 ? pick_h<false, 0>(W, N, any, count, f, d)
+                           : pick_h<false, 1>(W, N, any, count, f, d);
 }
 
-template <int W, int N, bool ANY>
+template <int W, int N, bool ANY, int DM>
 KernelFn persist_fn(bool count)
 {
-    return count ? k_trace_persist<W, N, ANY, true> : k_trace_persist<W, N, ANY, false>;
+    return count ? k_trace_persist<W, N, ANY, true, DM> : k_trace_persist<W, N, ANY, false, DM>;
 }
 
-template <int W>
+template <int W, int DM>
 KernelFn persist_w(int N, bool any, bool count)
 {
-    if (any) return N == 1 ? persist_fn<W, 1, true>(count) : nullptr;
+    if (any) return N == 1 ? persist_fn<W, 1, true, DM>(count) : nullptr;
     switch (N) {
-    case 1: return persist_fn<W, 1, false>(count);
-    case 2: return persist_fn<W, 2, false>(count);
-    case 4: return persist_fn<W, 4, false>(count);
-    case 8: return persist_fn<W, 8, false>(count);
+    case 1: return persist_fn<W, 1, false, DM>(count);
+    case 2: return persist_fn<W, 2, false, DM>(count);
+    case 4: return persist_fn<W, 4, false, DM>(count);
+    case 8: return persist_fn<W, 8, false, DM>(count);
     }
     return nullptr;
 }
 
-KernelFn pick_persistent(int W, int N, bool any, bool count)
+template <int DM>
+KernelFn persist_dm(int W, int N, bool any, bool count)
 {
     switch (W) {
-    case 2: return persist_w<2>(N, any, count);
-    case 4: return persist_w<4>(N, any, count);
-    case 8: return persist_w<8>(N, any, count);
+    case 2: return persist_w<2, DM>(N, any, count);
+    case 4: return persist_w<4, DM>(N, any, count);
+    case 8: return persist_w<8, DM>(N, any, count);
     }
     return nullptr;
+}
+
+KernelFn pick_persistent(int W, int N, bool any, bool count, int depth_mode)
+{
+    return depth_mode == 0 ? persist_dm<0>(W, N, any, count)
+                           : persist_dm<1>(W, N, any, count);
 }
 
 // Waves a persistent launch keeps resident: its occupancy on every CU.
@@ -520,7 +532,7 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
 {
     KernelFn fast = nullptr, deep = nullptr;
     if (!pick_kernels(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr,
-                      o->rng == 1, &fast, &deep))
+                      o->rng == 1, o->depth_mode, &fast, &deep))
         return SRT_ERR_UNSUPPORTED;
     if (o->rng == 1 && o->persistent) return SRT_ERR_UNSUPPORTED;  // Philox only
     const TraceWorkspace ws = trace_workspace(b, rays->count, workspace);
@@ -564,7 +576,8 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
     KernelFn pf = nullptr;
     unsigned blocks = 0;
     if (o->persistent && rays->count > 0) {
-        pf = pick_persistent(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr);
+        pf = pick_persistent(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr,
+                             o->depth_mode);
         if (!pf) return SRT_ERR_UNSUPPORTED;
         const srt_status gs = persistent_grid(pf, &blocks);
         if (gs != SRT_OK) return gs;
