@@ -107,7 +107,8 @@ def test_refit_empty_scene(srt):
     np.testing.assert_array_equal(res["rgb"], np.tile([0.25, 0.5, 0.75], (5, 1)).astype(np.float32))
 
 
-def test_fit_recovers_perturbed_scene(srt):
+@pytest.mark.parametrize("estimator", ["plain", "rb"])
+def test_fit_recovers_perturbed_scene(srt, estimator):
     """The differentiation recipe in miniature: the tiny cube scene starts
     where it was generated; the target images are the exact composites of the
     perturbed scene on 8 ring views of 64x64; Adam on means and opacity
@@ -115,7 +116,7 @@ def test_fit_recovers_perturbed_scene(srt):
     fitted parameters) must fall well below its starting value and the means
     must move toward the target's."""
     from paper_2504_06598_amd.fit import fit
-    say("optimisation loop: 8 ring views 64x64, 4 spp, 40 Adam steps")
+    say(f"optimisation loop: 8 ring views 64x64, 4 spp, 40 Adam steps, {estimator} estimator")
     sc0 = si.workload(1)["scene"]
     tgt = si.perturbed(sc0, 104)
     cams = si.ring_cameras(8, 3.0, 64, 64)
@@ -132,7 +133,7 @@ def test_fit_recovers_perturbed_scene(srt):
     losses = fit(params, sc0.sh_degree, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(),
                  torch.from_numpy(target.astype(np.float32)).cuda(), steps=40,
                  lr={"means": 5e-4, "opacity_logits": 5e-3}, spp=4, n_per_traversal=4,
-                 image_width=64)
+                 image_width=64, estimator=estimator)
     torch.cuda.synchronize()
     fitted = sc0.copy()
     fitted.means = to_np(params["means"])
