@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--leaf", type=int, default=2)
     p.add_argument("--n-per-traversal", type=int, default=4)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--overlap", action=argparse.BooleanOptionalAction, default=True,
+                   help="run the ring views' forward + backward on a second stream")
     p.add_argument("--cpu-pixels", type=int, default=192)
     p.add_argument("--roofline-launches", type=int, default=5)
     p.add_argument("--no-batched", action="store_true",
@@ -122,30 +124,42 @@ def main():
     bws = None
     bw_counters = srt.new_counters(dev)
 
+    # the path-tracer mix and the ring views' forward + backward only share the
+    # (read-only) BVH: with --overlap they run on two streams of default
+    # priority, so each one's tail of long walks overlaps the other's work
+    side = torch.cuda.Stream(device=dev) if args.overlap else None
+
     def step(k, cnt, bcnt):
         nonlocal fws, bws
-        bvh = srt.srt_build_bvh(scene, args.width, args.leaf)
-        srt.srt_trace_pathmix(bvh, cam, seed=si.PHILOX_SEED, spp=spp, n_per_traversal=N,
-                              sample_offset=k * spp, light=si.LIGHT_POS, plane_y=si.PLANE_Y,
-                              tmin_secondary=si.SECONDARY_TMIN, want_hits=False,
-                              counters=cnt, workspace=ws, out=out)
+        main = torch.cuda.current_stream()
+        bvh = srt.srt_build_bvh(scene, args.width, args.leaf)  # synchronises
         if fws is None:
             L = srt._lib.load()
             fws = torch.empty(L.srt_trace_workspace_size(bvh.handle, Rb), dtype=torch.uint8,
                               device=dev)
             bws = torch.empty(L.srt_backward_workspace_size(bvh.handle, Rb), dtype=torch.uint8,
                               device=dev)
-        srt.srt_trace_forward(bvh, vo, vd, seed=si.PHILOX_SEED, spp=bspp, n_per_traversal=bspp,
-                              sample_offset=k * bspp, image_width=views[0].width, counters=cnt,
-                              out=bout, workspace=fws)
-        grad_rgb = (bout["rgb"] - target) * (2.0 / Rb)
-        for g in grads.values():
-            g.zero_()
-        srt.srt_trace_backward(bvh, vo, vd, grad_rgb, hit_gid=bout["hit_gid"],
-                               hit_t=bout["hit_t"], seed=si.PHILOX_SEED, spp=bspp,
-                               n_per_traversal=bspp, sample_offset=k * bspp,
-                               image_width=views[0].width, grads=grads, counters=bcnt,
-                               workspace=bws)
+        if side is not None:
+            side.wait_stream(main)
+        with torch.cuda.stream(side if side is not None else main):
+            srt.srt_trace_forward(bvh, vo, vd, seed=si.PHILOX_SEED, spp=bspp,
+                                  n_per_traversal=bspp, sample_offset=k * bspp,
+                                  image_width=views[0].width, counters=cnt, out=bout,
+                                  workspace=fws)
+            grad_rgb = (bout["rgb"] - target) * (2.0 / Rb)
+            for g in grads.values():
+                g.zero_()
+            srt.srt_trace_backward(bvh, vo, vd, grad_rgb, hit_gid=bout["hit_gid"],
+                                   hit_t=bout["hit_t"], seed=si.PHILOX_SEED, spp=bspp,
+                                   n_per_traversal=bspp, sample_offset=k * bspp,
+                                   image_width=views[0].width, grads=grads, counters=bcnt,
+                                   workspace=bws)
+        srt.srt_trace_pathmix(bvh, cam, seed=si.PHILOX_SEED, spp=spp, n_per_traversal=N,
+                              sample_offset=k * spp, light=si.LIGHT_POS, plane_y=si.PLANE_Y,
+                              tmin_secondary=si.SECONDARY_TMIN, want_hits=False,
+                              counters=cnt, workspace=ws, out=out)
+        if side is not None:
+            main.wait_stream(side)
         return bvh
 
     for k in range(args.warmup):
@@ -288,6 +302,7 @@ def main():
                                    "includes the BVH build",
                        "gaussians": sc_host.num_gaussians, "width": args.width,
                        "leaf_size": args.leaf, "n_per_traversal": N,
+                       "streams": 2 if args.overlap else 1,
                        "forward_ray_samples_per_step": int(fwd_rs),
                        "backward_ray_samples_per_step": int(bwd_rs)},
             "roofline": roof, "cpu_baseline": cpu, "persistent_vs_plain": batched,
