@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "srt_internal.hpp"
@@ -297,15 +298,18 @@ __device__ __forceinline__ int32_t bin_size(const BinTree& t, int32_t c)
 // most L (those become leaves). Internal children become the next level's
 // tasks. Boxes are filled in afterwards, bottom-up (k_wide_boxes).
 template <int W>
-__global__ void k_collapse(BinTree t, int L, const Task* __restrict__ in,
-                           const uint32_t* __restrict__ n_in, Task* __restrict__ out,
-                           uint32_t* n_out, uint32_t* node_counter, WideNode<W>* nodes,
+__global__ void k_collapse(BinTree t, int L, const Task* __restrict__ in, uint32_t* ctr,
+                           Task* __restrict__ out, WideNode<W>* nodes,
                            int32_t* __restrict__ level_nodes)
 {
+    // ctr: [0] tasks of this level, [1] tasks of the next, [2] wide nodes made,
+    // [3] where this level's node list starts in level_nodes
+    uint32_t* n_out = ctr + 1;
+    uint32_t* node_counter = ctr + 2;
     const uint32_t ti = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ti >= *n_in) return;
+    if (ti >= ctr[0]) return;
     const Task tk = in[ti];
-    level_nodes[ti] = tk.node;
+    level_nodes[ctr[3] + ti] = tk.node;
     int32_t C[W];
     int32_t sz[W];
     int nc = 2;
@@ -352,6 +356,18 @@ __global__ void k_collapse(BinTree t, int L, const Task* __restrict__ in,
         }
     }
     nodes[tk.node] = nd;
+}
+
+// Between two levels: record the level's size and start, then make the next
+// level current (one thread; the next collapse launch sees the new counts).
+__global__ void k_advance(uint32_t* ctr, uint32_t* lvl_cnt, uint32_t* lvl_base, int level)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    lvl_cnt[level] = ctr[0];
+    lvl_base[level] = ctr[3];
+    ctr[3] += ctr[0];
+    ctr[0] = ctr[1];
+    ctr[1] = 0u;
 }
 
 // Boxes of the wide nodes of one level, once the level below is complete:
@@ -444,28 +460,88 @@ __global__ void k_unpermute_records(int64_t G, const Record* __restrict__ recs, 
 }
 
 // Device allocations released on scope exit unless released to the caller.
+// Build temporaries come from a library-owned, stream-ordered memory pool per
+// device that keeps freed blocks (release threshold at its maximum), so a
+// build neither synchronises the device to free them (hipFree does) nor
+// returns to the driver for them the next time. Devices without pool support
+// use hipMalloc / hipFree.
+hipMemPool_t build_pool()
+{
+    static std::mutex mu;
+    static hipMemPool_t pools[64] = {};
+    static bool tried[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!tried[dev]) {
+        tried[dev] = true;
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess)
+                pools[dev] = pool;
+            else
+                (void)hipMemPoolDestroy(pool);
+        }
+    }
+    return pools[dev];
+}
+
+// Buffers owned by a handle: from the same pool (stream-ordered) when there
+// is one, so building and destroying handles does not synchronise the device.
+template <class T>
+hipError_t handle_alloc(srt_bvh* b, T** p, size_t bytes, hipStream_t s)
+{
+    void* q = nullptr;
+    const size_t n = bytes > 0 ? bytes : 16;
+    const hipError_t e = b->pool ? hipMallocFromPoolAsync(&q, n, static_cast<hipMemPool_t>(b->pool), s)
+                                 : hipMalloc(&q, n);
+    *p = static_cast<T*>(e == hipSuccess ? q : nullptr);
+    return e;
+}
+
+void handle_free(const srt_bvh* b, void* p)
+{
+    if (!p) return;
+    // no work on the handle is pending (the destroy contract): the null
+    // stream orders the release after everything before it
+    if (b->pool)
+        (void)hipFreeAsync(p, nullptr);
+    else
+        (void)hipFree(p);
+}
+
 struct DevAlloc {
+    hipStream_t stream;
+    hipMemPool_t pool;
     std::vector<void*> ptrs;
+    explicit DevAlloc(hipStream_t s) : stream(s), pool(build_pool()) {}
     template <class T>
     hipError_t get(T** p, size_t bytes)
     {
         void* q = nullptr;
-        const hipError_t e = hipMalloc(&q, bytes > 0 ? bytes : 16);
+        const size_t n = bytes > 0 ? bytes : 16;
+        const hipError_t e = pool ? hipMallocFromPoolAsync(&q, n, pool, stream) : hipMalloc(&q, n);
         if (e == hipSuccess) ptrs.push_back(q);
         *p = static_cast<T*>(q);
         return e;
     }
-    void release(void* p)
-    {
-        ptrs.erase(std::remove(ptrs.begin(), ptrs.end(), p), ptrs.end());
-    }
     ~DevAlloc()
     {
-        for (void* p : ptrs) (void)hipFree(p);
+        // stream-ordered: released after the work already enqueued on `stream`
+        for (void* p : ptrs) (void)(pool ? hipFreeAsync(p, stream) : hipFree(p));
     }
 };
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
+
+constexpr int kMaxLevels = 512;   // far above the depth of any tree of <= 2^28 Gaussians
+constexpr int kLevelBatch = 8;    // levels launched between two host checks
 
 template <int W>
 srt_status collapse_all(hipStream_t s, DevAlloc& tmp, const BinTree& t, int64_t n, int L,
@@ -475,36 +551,55 @@ srt_status collapse_all(hipStream_t s, DevAlloc& tmp, const BinTree& t, int64_t 
                         std::vector<uint32_t>& level_cnt)
 {
     Task *qa = nullptr, *qb = nullptr;
-    uint32_t* ctr = nullptr;  // [0] n_in, [1] n_out, [2] node counter
+    uint32_t* ctr = nullptr;  // see k_collapse
+    uint32_t *lvl_cnt = nullptr, *lvl_base = nullptr;
     int32_t* level_nodes = nullptr;
     SRT_HIP_TRY(tmp.get(&qa, sizeof(Task) * (size_t)n));
     SRT_HIP_TRY(tmp.get(&qb, sizeof(Task) * (size_t)n));
     SRT_HIP_TRY(tmp.get(&ctr, 4 * sizeof(uint32_t)));
+    SRT_HIP_TRY(tmp.get(&lvl_cnt, kMaxLevels * sizeof(uint32_t)));
+    SRT_HIP_TRY(tmp.get(&lvl_base, kMaxLevels * sizeof(uint32_t)));
     SRT_HIP_TRY(tmp.get(&level_nodes, sizeof(int32_t) * (size_t)n));
     const Task root{0, 0};
     const uint32_t init[4] = {1u, 0u, 1u, 0u};
     SRT_HIP_TRY(hipMemcpyAsync(qa, &root, sizeof(Task), hipMemcpyHostToDevice, s));
     SRT_HIP_TRY(hipMemcpyAsync(ctr, init, sizeof(init), hipMemcpyHostToDevice, s));
+    // Levels run back to back without a host round trip; the host looks at
+    // the task count only every kLevelBatch levels (launches past the last
+    // level find no tasks and return at once). A level holds at most W^l tasks.
+    int levels = 0;
+    int64_t bound = 1;
+    for (;;) {
+        if (levels + kLevelBatch > kMaxLevels) return SRT_ERR_HIP;  // not for a valid tree
+        for (int b = 0; b < kLevelBatch; ++b, ++levels) {
+            k_collapse<W><<<blocks_for(bound, 128), 128, 0, s>>>(t, L, qa, ctr, qb, nodes,
+                                                                 level_nodes);
+            SRT_HIP_TRY(hipGetLastError());
+            k_advance<<<1, 1, 0, s>>>(ctr, lvl_cnt, lvl_base, levels);
+            SRT_HIP_TRY(hipGetLastError());
+            std::swap(qa, qb);
+            bound = std::min<int64_t>(bound * W, n);
+        }
+        uint32_t pending = 0;
+        SRT_HIP_TRY(hipMemcpyAsync(&pending, ctr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SRT_HIP_TRY(hipStreamSynchronize(s));
+        if (pending == 0) break;
+    }
+    std::vector<uint32_t> cnt(levels), base(levels);
+    uint32_t made = 0;
+    SRT_HIP_TRY(hipMemcpyAsync(cnt.data(), lvl_cnt, sizeof(uint32_t) * levels,
+                               hipMemcpyDeviceToHost, s));
+    SRT_HIP_TRY(hipMemcpyAsync(base.data(), lvl_base, sizeof(uint32_t) * levels,
+                               hipMemcpyDeviceToHost, s));
+    SRT_HIP_TRY(hipMemcpyAsync(&made, ctr + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SRT_HIP_TRY(hipStreamSynchronize(s));
     level_off.clear();
     level_cnt.clear();
-    uint32_t n_level = 1, off = 0;
-    while (n_level > 0) {
-        if (level_off.size() > 4096) return SRT_ERR_HIP;  // cannot happen for a valid tree
-        level_off.push_back(off);
-        level_cnt.push_back(n_level);
-        k_fill_u32<<<1, 1, 0, s>>>(ctr + 1, 0u, 1);
-        k_collapse<W><<<blocks_for(n_level, 128), 128, 0, s>>>(t, L, qa, ctr, qb, ctr + 1, ctr + 2,
-                                                                nodes, level_nodes + off);
-        SRT_HIP_TRY(hipGetLastError());
-        SRT_HIP_TRY(hipMemcpyAsync(ctr, ctr + 1, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-        uint32_t host[3];
-        SRT_HIP_TRY(hipMemcpyAsync(host, ctr, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        SRT_HIP_TRY(hipStreamSynchronize(s));
-        off += n_level;
-        n_level = host[0];
-        *num_nodes = host[2];
-        std::swap(qa, qb);
+    for (int l = 0; l < levels && cnt[l] > 0; ++l) {
+        level_off.push_back(base[l]);
+        level_cnt.push_back(cnt[l]);
     }
+    *num_nodes = made;
     for (size_t lv = level_off.size(); lv-- > 0;) {
         k_wide_boxes<W><<<blocks_for(level_cnt[lv], 128), 128, 0, s>>>(
             level_nodes + level_off[lv], level_cnt[lv], order, lo, hi, nodes);
@@ -573,10 +668,10 @@ template <int W>
 srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s, srt_bvh* b)
 {
     const int64_t G = sc->num_gaussians;
-    DevAlloc tmp;
+    DevAlloc tmp(s);
     if (G == 0) {
         WideNode<W>* nodes = nullptr;
-        SRT_HIP_TRY(hipMalloc(&nodes, sizeof(WideNode<W>)));
+        SRT_HIP_TRY(handle_alloc(b, &nodes, sizeof(WideNode<W>), s));
         b->nodes = nodes;
         k_single_leaf<W><<<1, 1, 0, s>>>(0, nullptr, nullptr, nodes);
         SRT_HIP_TRY(hipGetLastError());
@@ -588,11 +683,11 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
     }
     Record* recs_id = nullptr;
     SRT_HIP_TRY(tmp.get(&recs_id, sizeof(Record) * (size_t)G));
-    SRT_HIP_TRY(hipMalloc(&b->box_lo, sizeof(float) * 3 * (size_t)G));
-    SRT_HIP_TRY(hipMalloc(&b->box_hi, sizeof(float) * 3 * (size_t)G));
-    SRT_HIP_TRY(hipMalloc(&b->recs, sizeof(Record) * (size_t)G));
-    SRT_HIP_TRY(hipMalloc(&b->leaf_order, sizeof(int32_t) * (size_t)G));
-    SRT_HIP_TRY(hipMalloc(&b->leaf_pos, sizeof(int32_t) * (size_t)G));
+    SRT_HIP_TRY(handle_alloc(b, &b->box_lo, sizeof(float) * 3 * (size_t)G, s));
+    SRT_HIP_TRY(handle_alloc(b, &b->box_hi, sizeof(float) * 3 * (size_t)G, s));
+    SRT_HIP_TRY(handle_alloc(b, &b->recs, sizeof(Record) * (size_t)G, s));
+    SRT_HIP_TRY(handle_alloc(b, &b->leaf_order, sizeof(int32_t) * (size_t)G, s));
+    SRT_HIP_TRY(handle_alloc(b, &b->leaf_pos, sizeof(int32_t) * (size_t)G, s));
     b->bytes = (int64_t)(sizeof(float) * 6 + sizeof(Record) + 2 * sizeof(int32_t)) * G;
 
     k_preprocess<<<blocks_for(G, 256), 256, 0, s>>>(G, sc->means, sc->log_scales, sc->quats,
@@ -600,7 +695,7 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
                                                     b->box_hi);
     SRT_HIP_TRY(hipGetLastError());
 
-    SRT_HIP_TRY(hipMalloc(&b->bounds, 8 * sizeof(uint32_t)));
+    SRT_HIP_TRY(handle_alloc(b, &b->bounds, 8 * sizeof(uint32_t), s));
     uint32_t* bounds = b->bounds;
     const uint32_t binit[8] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
     SRT_HIP_TRY(hipMemcpyAsync(bounds, binit, sizeof(binit), hipMemcpyHostToDevice, s));
@@ -656,13 +751,13 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
                                               b->level_cnt);
         if (st != SRT_OK) return st;
         const size_t listed = (size_t)b->level_off.back() + b->level_cnt.back();
-        SRT_HIP_TRY(hipMalloc(&b->level_nodes, sizeof(int32_t) * listed));
+        SRT_HIP_TRY(handle_alloc(b, &b->level_nodes, sizeof(int32_t) * listed, s));
         SRT_HIP_TRY(hipMemcpyAsync(b->level_nodes, lvl, sizeof(int32_t) * listed,
                                    hipMemcpyDeviceToDevice, s));
         b->bytes += (int64_t)(sizeof(int32_t) * listed);
     }
     WideNode<W>* nodes = nullptr;
-    SRT_HIP_TRY(hipMalloc(&nodes, sizeof(WideNode<W>) * (size_t)num_nodes));
+    SRT_HIP_TRY(handle_alloc(b, &nodes, sizeof(WideNode<W>) * (size_t)num_nodes, s));
     b->nodes = nodes;
     SRT_HIP_TRY(hipMemcpyAsync(nodes, nodes_max, sizeof(WideNode<W>) * (size_t)num_nodes,
                                hipMemcpyDeviceToDevice, s));
@@ -718,6 +813,7 @@ srt_status srt_build_bvh(const srt_scene* sc, const srt_build_opts* opts, void* 
     if (opts->size_split < 0 || opts->size_split > 16) return SRT_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     srt_bvh* b = new srt_bvh();
+    b->pool = build_pool();
     b->G = G;
     b->W = opts->width;
     b->L = opts->leaf_size;
@@ -741,14 +837,14 @@ srt_status srt_build_bvh(const srt_scene* sc, const srt_build_opts* opts, void* 
 void srt_destroy_bvh(srt_bvh* b)
 {
     if (!b) return;
-    (void)hipFree(b->nodes);
-    (void)hipFree(b->recs);
-    (void)hipFree(b->leaf_order);
-    (void)hipFree(b->leaf_pos);
-    (void)hipFree(b->box_lo);
-    (void)hipFree(b->box_hi);
-    (void)hipFree(b->level_nodes);
-    (void)hipFree(b->bounds);
+    handle_free(b, b->nodes);
+    handle_free(b, b->recs);
+    handle_free(b, b->leaf_order);
+    handle_free(b, b->leaf_pos);
+    handle_free(b, b->box_lo);
+    handle_free(b, b->box_hi);
+    handle_free(b, b->level_nodes);
+    handle_free(b, b->bounds);
     delete b;
 }
 

@@ -29,6 +29,7 @@ struct srt_bvh {
     int32_t* level_nodes = nullptr;
     std::vector<uint32_t> level_off, level_cnt;
     uint32_t* bounds = nullptr;      // [8]
+    void* pool = nullptr;            // hipMemPool_t the buffers come from (null: hipMalloc)
 };
 
 namespace srt {
