@@ -14,7 +14,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "srt_internal.hpp"
@@ -460,81 +462,96 @@ __global__ void k_unpermute_records(int64_t G, const Record* __restrict__ recs, 
 }
 
 // Device allocations released on scope exit unless released to the caller.
-// Build temporaries come from a library-owned, stream-ordered memory pool per
-// device that keeps freed blocks (release threshold at its maximum), so a
-// build neither synchronises the device to free them (hipFree does) nor
-// returns to the driver for them the next time. Devices without pool support
-// use hipMalloc / hipFree.
-hipMemPool_t build_pool()
-{
-    static std::mutex mu;
-    static hipMemPool_t pools[64] = {};
-    static bool tried[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    std::lock_guard<std::mutex> lock(mu);
-    if (!tried[dev]) {
-        tried[dev] = true;
-        hipMemPoolProps props{};
-        props.allocType = hipMemAllocationTypePinned;
-        props.handleTypes = hipMemHandleTypeNone;
-        props.location.type = hipMemLocationTypeDevice;
-        props.location.id = dev;
-        hipMemPool_t pool = nullptr;
-        if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
-            uint64_t keep = UINT64_MAX;
-            if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess)
-                pools[dev] = pool;
-            else
-                (void)hipMemPoolDestroy(pool);
+// Device blocks for builds (temporaries) and handles (their buffers) are
+// kept by the library when released and handed out again by later builds of
+// the same size: hipMalloc and, above all, hipFree (which synchronises the
+// device and measured ~0.5 ms per call) stay out of a rebuild. A block is
+// released only when no work on it can be pending: temporaries after the
+// build has synchronised its stream, a handle's buffers at destroy (whose
+// contract says no work on the handle is pending). Blocks are kept per
+// device and size class (64 KiB granules) up to 8 GiB in total; more is
+// freed at once.
+struct BlockCache {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void*>> free_blocks;
+    size_t kept = 0;
+    static constexpr size_t kGranule = size_t(1) << 16;
+    static constexpr size_t kMaxKept = size_t(8) << 30;
+
+    static size_t round(size_t bytes) { return (std::max<size_t>(bytes, 16) + kGranule - 1) / kGranule * kGranule; }
+
+    hipError_t get(void** p, size_t bytes)
+    {
+        const size_t sz = round(bytes);
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            auto it = free_blocks.find({dev, sz});
+            if (it != free_blocks.end() && !it->second.empty()) {
+                *p = it->second.back();
+                it->second.pop_back();
+                kept -= sz;
+                return hipSuccess;
+            }
         }
+        return hipMalloc(p, sz);
     }
-    return pools[dev];
+
+    void put(void* p, size_t bytes)
+    {
+        if (!p) return;
+        const size_t sz = round(bytes);
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            std::lock_guard<std::mutex> lock(mu);
+            if (kept + sz <= kMaxKept) {
+                free_blocks[{dev, sz}].push_back(p);
+                kept += sz;
+                return;
+            }
+        }
+        (void)hipFree(p);
+    }
+};
+
+BlockCache& block_cache()
+{
+    static BlockCache* c = new BlockCache();  // kept to process exit
+    return *c;
 }
 
-// Buffers owned by a handle: from the same pool (stream-ordered) when there
-// is one, so building and destroying handles does not synchronise the device.
+// A handle's buffers, with their sizes so they can go back to the cache.
 template <class T>
-hipError_t handle_alloc(srt_bvh* b, T** p, size_t bytes, hipStream_t s)
+hipError_t handle_alloc(srt_bvh* b, T** p, size_t bytes)
 {
     void* q = nullptr;
-    const size_t n = bytes > 0 ? bytes : 16;
-    const hipError_t e = b->pool ? hipMallocFromPoolAsync(&q, n, static_cast<hipMemPool_t>(b->pool), s)
-                                 : hipMalloc(&q, n);
+    const hipError_t e = block_cache().get(&q, bytes);
     *p = static_cast<T*>(e == hipSuccess ? q : nullptr);
+    if (e == hipSuccess) b->blocks.push_back({q, bytes});
     return e;
-}
-
-void handle_free(const srt_bvh* b, void* p)
-{
-    if (!p) return;
-    // no work on the handle is pending (the destroy contract): the null
-    // stream orders the release after everything before it
-    if (b->pool)
-        (void)hipFreeAsync(p, nullptr);
-    else
-        (void)hipFree(p);
 }
 
 struct DevAlloc {
     hipStream_t stream;
-    hipMemPool_t pool;
-    std::vector<void*> ptrs;
-    explicit DevAlloc(hipStream_t s) : stream(s), pool(build_pool()) {}
+    std::vector<std::pair<void*, size_t>> blocks;
+    explicit DevAlloc(hipStream_t s) : stream(s) {}
     template <class T>
     hipError_t get(T** p, size_t bytes)
     {
         void* q = nullptr;
-        const size_t n = bytes > 0 ? bytes : 16;
-        const hipError_t e = pool ? hipMallocFromPoolAsync(&q, n, pool, stream) : hipMalloc(&q, n);
-        if (e == hipSuccess) ptrs.push_back(q);
+        const hipError_t e = block_cache().get(&q, bytes);
+        if (e == hipSuccess) blocks.push_back({q, bytes});
         *p = static_cast<T*>(q);
         return e;
     }
     ~DevAlloc()
     {
-        // stream-ordered: released after the work already enqueued on `stream`
-        for (void* p : ptrs) (void)(pool ? hipFreeAsync(p, stream) : hipFree(p));
+        // no kernel of the build may still use a block handed back (a no-op
+        // wait on the success path, which has synchronised already)
+        (void)hipStreamSynchronize(stream);
+        for (auto& b : blocks) block_cache().put(b.first, b.second);
     }
 };
 
@@ -671,7 +688,7 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
     DevAlloc tmp(s);
     if (G == 0) {
         WideNode<W>* nodes = nullptr;
-        SRT_HIP_TRY(handle_alloc(b, &nodes, sizeof(WideNode<W>), s));
+        SRT_HIP_TRY(handle_alloc(b, &nodes, sizeof(WideNode<W>)));
         b->nodes = nodes;
         k_single_leaf<W><<<1, 1, 0, s>>>(0, nullptr, nullptr, nodes);
         SRT_HIP_TRY(hipGetLastError());
@@ -683,11 +700,11 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
     }
     Record* recs_id = nullptr;
     SRT_HIP_TRY(tmp.get(&recs_id, sizeof(Record) * (size_t)G));
-    SRT_HIP_TRY(handle_alloc(b, &b->box_lo, sizeof(float) * 3 * (size_t)G, s));
-    SRT_HIP_TRY(handle_alloc(b, &b->box_hi, sizeof(float) * 3 * (size_t)G, s));
-    SRT_HIP_TRY(handle_alloc(b, &b->recs, sizeof(Record) * (size_t)G, s));
-    SRT_HIP_TRY(handle_alloc(b, &b->leaf_order, sizeof(int32_t) * (size_t)G, s));
-    SRT_HIP_TRY(handle_alloc(b, &b->leaf_pos, sizeof(int32_t) * (size_t)G, s));
+    SRT_HIP_TRY(handle_alloc(b, &b->box_lo, sizeof(float) * 3 * (size_t)G));
+    SRT_HIP_TRY(handle_alloc(b, &b->box_hi, sizeof(float) * 3 * (size_t)G));
+    SRT_HIP_TRY(handle_alloc(b, &b->recs, sizeof(Record) * (size_t)G));
+    SRT_HIP_TRY(handle_alloc(b, &b->leaf_order, sizeof(int32_t) * (size_t)G));
+    SRT_HIP_TRY(handle_alloc(b, &b->leaf_pos, sizeof(int32_t) * (size_t)G));
     b->bytes = (int64_t)(sizeof(float) * 6 + sizeof(Record) + 2 * sizeof(int32_t)) * G;
 
     k_preprocess<<<blocks_for(G, 256), 256, 0, s>>>(G, sc->means, sc->log_scales, sc->quats,
@@ -695,7 +712,7 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
                                                     b->box_hi);
     SRT_HIP_TRY(hipGetLastError());
 
-    SRT_HIP_TRY(handle_alloc(b, &b->bounds, 8 * sizeof(uint32_t), s));
+    SRT_HIP_TRY(handle_alloc(b, &b->bounds, 8 * sizeof(uint32_t)));
     uint32_t* bounds = b->bounds;
     const uint32_t binit[8] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
     SRT_HIP_TRY(hipMemcpyAsync(bounds, binit, sizeof(binit), hipMemcpyHostToDevice, s));
@@ -751,13 +768,13 @@ srt_status build_impl(const srt_scene* sc, int L, int size_split, hipStream_t s,
                                               b->level_cnt);
         if (st != SRT_OK) return st;
         const size_t listed = (size_t)b->level_off.back() + b->level_cnt.back();
-        SRT_HIP_TRY(handle_alloc(b, &b->level_nodes, sizeof(int32_t) * listed, s));
+        SRT_HIP_TRY(handle_alloc(b, &b->level_nodes, sizeof(int32_t) * listed));
         SRT_HIP_TRY(hipMemcpyAsync(b->level_nodes, lvl, sizeof(int32_t) * listed,
                                    hipMemcpyDeviceToDevice, s));
         b->bytes += (int64_t)(sizeof(int32_t) * listed);
     }
     WideNode<W>* nodes = nullptr;
-    SRT_HIP_TRY(handle_alloc(b, &nodes, sizeof(WideNode<W>) * (size_t)num_nodes, s));
+    SRT_HIP_TRY(handle_alloc(b, &nodes, sizeof(WideNode<W>) * (size_t)num_nodes));
     b->nodes = nodes;
     SRT_HIP_TRY(hipMemcpyAsync(nodes, nodes_max, sizeof(WideNode<W>) * (size_t)num_nodes,
                                hipMemcpyDeviceToDevice, s));
@@ -813,7 +830,6 @@ srt_status srt_build_bvh(const srt_scene* sc, const srt_build_opts* opts, void* 
     if (opts->size_split < 0 || opts->size_split > 16) return SRT_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     srt_bvh* b = new srt_bvh();
-    b->pool = build_pool();
     b->G = G;
     b->W = opts->width;
     b->L = opts->leaf_size;
@@ -837,14 +853,7 @@ srt_status srt_build_bvh(const srt_scene* sc, const srt_build_opts* opts, void* 
 void srt_destroy_bvh(srt_bvh* b)
 {
     if (!b) return;
-    handle_free(b, b->nodes);
-    handle_free(b, b->recs);
-    handle_free(b, b->leaf_order);
-    handle_free(b, b->leaf_pos);
-    handle_free(b, b->box_lo);
-    handle_free(b, b->box_hi);
-    handle_free(b, b->level_nodes);
-    handle_free(b, b->bounds);
+    for (auto& blk : b->blocks) block_cache().put(blk.first, blk.second);
     delete b;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "srt.h"
@@ -29,7 +30,7 @@ struct srt_bvh {
     int32_t* level_nodes = nullptr;
     std::vector<uint32_t> level_off, level_cnt;
     uint32_t* bounds = nullptr;      // [8]
-    void* pool = nullptr;            // hipMemPool_t the buffers come from (null: hipMalloc)
+    std::vector<std::pair<void*, size_t>> blocks;  // device buffers owned (pointer, bytes)
 };
 
 namespace srt {
