@@ -79,6 +79,7 @@ struct BwdArgs {
     float r_max;
     int32_t img_w;  // > 0: rays are a row-major image of this width, walked in 8x8 tiles
     const int32_t* leaf_pos;  // leaf position of each Gaussian id
+    uint32_t* tile_ctr;       // [8 * 16]: tiles taken from each XCD band (64 B apart)
 };
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v)
@@ -155,9 +156,33 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
     const int64_t n_threads = a.img_w > 0 ? tile_threads(a.img_w, a.R / a.img_w) : a.R;
     const int64_t n_tiles = (n_threads + kBlock - 1) / kBlock;
 
-    // every thread of the workgroup runs the same tiles (the loop bound is
-    // per workgroup), so the barriers below are reached by all of them
-    for (int64_t tile = xcd_block(blockIdx.x, gridDim.x); tile < n_tiles; tile += gridDim.x) {
+    // Tiles are handed out dynamically: the image is cut into 8 bands, one per
+    // XCD (workgroups are dispatched to the XCDs in turn, so workgroup b runs
+    // on XCD b % 8); a workgroup takes the next tile of its own band with one
+    // atomic, and once its band is used up, of the next bands in turn. Every
+    // thread of the workgroup runs the same tiles (the tile is broadcast
+    // through LDS), so the barriers below are reached by all of them.
+    __shared__ int64_t s_tile;
+    int band = blockIdx.x & 7;
+    int bands_left = 8;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int64_t t = -1;
+            while (bands_left > 0) {
+                const int64_t b0 = n_tiles * band / 8, b1 = n_tiles * (band + 1) / 8;
+                const int64_t k = (int64_t)atomicAdd(&a.tile_ctr[16 * band], 1u);
+                if (b0 + k < b1) {
+                    t = b0 + k;
+                    break;
+                }
+                band = (band + 1) & 7;
+                --bands_left;
+            }
+            s_tile = t;
+        }
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile < 0) break;  // uniform: every thread read the same value
         const int64_t t = tile * kBlock + threadIdx.x;
         const int64_t ray = a.img_w > 0 ? tile_pixel(t, a.img_w, a.R / a.img_w) : t;
         const bool valid = ray >= 0 && ray < a.R;
@@ -544,6 +569,7 @@ BwdFn pick(int W, int N, bool count, bool rb, int depth_mode)
 constexpr int64_t kMaxBwdBlocks = 2048;
 
 struct BwdWs {
+    uint32_t* tile_ctr;  // [128]
     float* acc;
     int32_t* stack;
     int32_t threads;
@@ -558,6 +584,8 @@ BwdWs bwd_ws(const srt_bvh* b, int64_t R, void* base)
     w.threads = (int32_t)(blocks * kBlock);
     char* p = static_cast<char*>(base);
     size_t off = 0;
+    w.tile_ctr = reinterpret_cast<uint32_t*>(p ? p + off : nullptr);
+    off = align_up(off + 128 * sizeof(uint32_t), 256);
     w.acc = reinterpret_cast<float*>(p ? p + off : nullptr);
     off = align_up(off + sizeof(float) * kAccStride * (size_t)std::max<int64_t>(b->G, 1), 256);
     const int32_t extra = std::max(0, deep_stack_cap(b) - kLdsEntries);
@@ -609,6 +637,17 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     if (b->G == 0 || rays->count == 0) return SRT_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const BwdWs ws = bwd_ws(b, rays->count, workspace);
+    BwdFn fn = pick(b->W, N, counters != nullptr, opts->estimator == 1, opts->depth_mode);
+    if (!fn) return SRT_ERR_UNSUPPORTED;
+    // as many workgroups as stay resident (tiles are handed out dynamically),
+    // at most the number the workspace holds stacks for
+    int dev = 0, n_cu = 0, per_cu = 0;
+    SRT_HIP_TRY(hipGetDevice(&dev));
+    SRT_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    SRT_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(fn), kBlock, 0));
+    const unsigned blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(ws.threads / kBlock, (int64_t)n_cu * std::max(1, per_cu)));
     fill_u32(reinterpret_cast<uint32_t*>(ws.acc), 0u, (size_t)kAccStride * (size_t)b->G, s);
     BwdArgs a{};
     a.nodes = b->nodes;
@@ -644,9 +683,9 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     a.r_max = b->r_max;
     a.img_w = opts->image_width;
     a.leaf_pos = b->leaf_pos;
-    BwdFn fn = pick(b->W, N, counters != nullptr, opts->estimator == 1, opts->depth_mode);
-    if (!fn) return SRT_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(fn, dim3(ws.threads / kBlock), dim3(kBlock), 0, s, a);
+    a.tile_ctr = ws.tile_ctr;
+    fill_u32(ws.tile_ctr, 0u, 128, s);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, s, a);
     SRT_HIP_TRY(hipGetLastError());
     k_chain<<<(unsigned)((b->G + 255) / 256), 256, 0, s>>>(
         b->G, ws.acc, scene->log_scales, scene->quats, scene->opacity_logits, g_means, g_log_scales,
