@@ -20,12 +20,14 @@
 //   dloss/dlogit = (1 - o) sa,  dloss/dmu = M^T (sa p),
 //   dloss/dlog_s_i = sa p_i^2,  dloss/dR_ji = -(1/s_i) sum_k R_jk s_k sa p_i p_k,
 // so each Gaussian accumulates ten numbers: sum sa, sum sa p, sum sa p p^T.
-// A workgroup walks tiles of 128 neighbouring rays and pre-sums these in an
-// LDS hash table keyed by Gaussian id, flushed to a 64-B global slot per
-// Gaussian with FP32 atomics after each tile (coherent rays share most
-// Gaussians, so this removes most global atomic traffic). SH colour gradients
-// go straight to the caller's buffer. Kernel 2 maps each Gaussian's sums to
-// the raw parameters.
+// The grid holds as many workgroups as stay resident; each takes tiles of 128
+// neighbouring rays from a per-XCD band of the image with one atomic per
+// tile. It pre-sums these ten numbers in an LDS hash table keyed by Gaussian
+// id, and the accepted hits' SH colour gradients in a second one, flushing
+// both to global memory with FP32 atomics after each tile (coherent rays
+// share most Gaussians, so this removes most global atomic traffic; a
+// Gaussian that finds no free slot goes straight to global memory). Kernel 2
+// maps each Gaussian's sums to the raw parameters.
 #include <algorithm>
 #include <climits>
 
