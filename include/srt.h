@@ -220,7 +220,14 @@ typedef struct {
  *                 samples of one walk differ; frame-to-frame variation comes
  *                 from jittered camera rays (srt_camera.jitter). Results are
  *                 then a different realisation, correct in expectation only.
- *                 seed and purpose are not used by the hash.                */
+ *                 seed and purpose are not used by the hash.
+ * walk            0: automatic (2 where it is supported, else 1).
+ *                 1: every lane walks the BVH for its own ray.
+ *                 2: the 64 rays of a wave walk it together, one node at a
+ *                 time (a lane takes part in the nodes and leaves its own
+ *                 walk would reach); for image launches (image_width > 0) of
+ *                 closest-hit rays with Philox numbers and persistent = 0,
+ *                 else SRT_ERR_UNSUPPORTED. Results do not depend on it.   */
 typedef struct {
     uint64_t seed;
     int32_t spp;
@@ -236,6 +243,7 @@ typedef struct {
     int32_t refill_threshold;
     int32_t estimator;
     int32_t rng;
+    int32_t walk;
 } srt_trace_opts;
 
 /* Counters accumulated (+=) into a device uint64 array of SRT_NUM_COUNTERS

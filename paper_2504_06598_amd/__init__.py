@@ -149,12 +149,16 @@ def counters_dict(c):
 
 ESTIMATORS = {"plain": 0, "rb": 1}
 RNGS = {"philox": 0, "hash": 1}
+WALKS = {"auto": 0, "lane": 1, "wave": 2}
 
 
 def _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode=0,
           depth_axis=(0.0, 0.0, 0.0), image_width=0, persistent=False, refill_threshold=0,
-          estimator="plain", rng="philox"):
+          estimator="plain", rng="philox", walk="auto"):
     o = _lib.SrtTraceOpts()
+    if walk not in WALKS:
+        raise ValueError(f"walk must be one of {sorted(WALKS)}")
+    o.walk = WALKS[walk]
     if estimator not in ESTIMATORS:
         raise ValueError(f"estimator must be one of {sorted(ESTIMATORS)}")
     if rng not in RNGS:
@@ -182,19 +186,21 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
                       ray_ids=None, sample_ids=None, purpose=0, seed=0, spp=1,
                       n_per_traversal=1, sample_offset=0, bg=(0.0, 0.0, 0.0), any_hit=False,
                       stack_limit=0, depth_mode=0, depth_axis=(0.0, 0.0, 0.0), image_width=0,
-                      persistent=False, refill_threshold=0, rng="philox", want_rgb=True,
-                      want_hits=True, counters=None, out=None, workspace=None):
+                      persistent=False, refill_threshold=0, rng="philox", walk="auto",
+                      want_rgb=True, want_hits=True, counters=None, out=None, workspace=None):
     """Trace rays (device tensors [R,3]); returns dict(rgb [R,3], hit_gid [R,spp],
     hit_t [R,spp]). image_width > 0 declares the rays a row-major image of that
     width (traced in 8x8 tiles); persistent=True runs work-stealing waves
-    (refilled once refill_threshold lanes are idle). Neither changes results."""
+    (refilled once refill_threshold lanes are idle); walk="wave" makes the 64 rays
+    of a tile walk the BVH together ("auto": wherever supported, "lane": one
+    walk per ray). None of these changes results."""
     lib = _lib.load()
     R = int(origins.shape[0])
     dev = origins.device
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
     opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode,
-                 depth_axis, image_width, persistent, refill_threshold, rng=rng)
+                 depth_axis, image_width, persistent, refill_threshold, rng=rng, walk=walk)
     res = dict(out or {})
     if want_rgb and "rgb" not in res:
         res["rgb"] = torch.empty((R, 3), dtype=torch.float32, device=dev)
@@ -325,15 +331,16 @@ def srt_camera_rays(cam, device="cuda"):
 def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_traversal=1,
                       sample_offset=0, bg=(0.0, 0.0, 0.0), light=(5.0, 5.0, 5.0), plane_y=-2.5,
                       tmin_secondary=1e-4, stack_limit=0, persistent=False, refill_threshold=0,
-                      rng="philox", want_hits=True, counters=None, workspace=None, out=None):
+                      rng="philox", walk="auto", want_hits=True, counters=None, workspace=None,
+                      out=None):
     """Path-tracer mix of one camera; returns dict(rgb [, cam_gid, cam_t,
-    shadow_vis, mirror_gid])."""
+    shadow_vis, mirror_gid]). walk applies to the camera rays."""
     lib = _lib.load()
     dev = bvh.scene.means.device
     R = int(cam.width) * int(cam.height)
     c = _camera(cam)
     opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, stack_limit,
-                 persistent=persistent, refill_threshold=refill_threshold, rng=rng)
+                 persistent=persistent, refill_threshold=refill_threshold, rng=rng, walk=walk)
     pm = _lib.SrtPathmixOpts()
     for i in range(3):
         pm.light[i] = float(light[i])

@@ -42,7 +42,8 @@ class SrtTraceOpts(C.Structure):
                 ("stack_limit", C.c_int32), ("depth_mode", C.c_int32),
                 ("depth_axis", C.c_float * 3), ("image_width", C.c_int32),
                 ("persistent", C.c_int32), ("refill_threshold", C.c_int32),
-                ("estimator", C.c_int32), ("rng", C.c_int32)]
+                ("estimator", C.c_int32), ("rng", C.c_int32),
+                ("walk", C.c_int32)]
 
 
 class SrtCamera(C.Structure):

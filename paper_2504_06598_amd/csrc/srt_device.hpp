@@ -278,6 +278,24 @@ __device__ __forceinline__ void slab_keys(const NodeBuf<W>& b, const Ray& r, flo
     }
 }
 
+// Entry depth of each child box (clamped at 0), or +inf where the ray misses
+// it or enters beyond tcut; the same test as slab_keys.
+template <int W>
+__device__ __forceinline__ void slab_entry(const NodeBuf<W>& b, const Ray& r, float tcut,
+                                           float te[W])
+{
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        const float ax = (b.n.lo[0][c] - r.ox) * r.ix, bx = (b.n.hi[0][c] - r.ox) * r.ix;
+        const float ay = (b.n.lo[1][c] - r.oy) * r.iy, by = (b.n.hi[1][c] - r.oy) * r.iy;
+        const float az = (b.n.lo[2][c] - r.oz) * r.iz, bz = (b.n.hi[2][c] - r.oz) * r.iz;
+        const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
+        const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz)) * kIzeFactor;
+        const bool hit = (t0 <= t1) & (t0 <= tcut) & (t1 >= r.tmin) & (b.n.child[c] != kEmptyChild);
+        te[c] = hit ? fminf(fmaxf(t0, 0.0f), 0x1.fffffep127f) : INFINITY;
+    }
+}
+
 __device__ __forceinline__ void cswap(uint32_t& a, uint32_t& b)
 {
     const uint32_t lo = min(a, b), hi = max(a, b);

@@ -88,6 +88,91 @@ __device__ __forceinline__ int walk(const WideNode<W>* __restrict__ nodes, const
     }
 }
 
+// One walk shared by the 64 rays of a wave (the rays of an 8x8 pixel tile
+// are coherent, so they need nearly the same nodes). The wave pops one node
+// at a time, in uniform control flow; a lane takes part when its ray entered
+// the node's box no farther than its own depth cut (plus slack), so each lane
+// sees exactly the nodes and leaves its own walk would reach, in another
+// order. Children go on the stack when any lane hit them, in the near-to-far
+// order of the first lane that takes part. The stack's node ids sit one per
+// lane of a register (entry i in lane i, so cap <= 64); each lane's entry
+// depth of every stacked node sits in LDS at t[i * 64 + lane] (+inf for
+// lanes that missed it). Node and record addresses are uniform, so they are
+// fetched once per wave. visit(record_index, on) is called by every lane for
+// each record of a reached leaf; only lanes with `on` may act on it. Returns
+// kWalkDone or kWalkOverflow (wave-uniform).
+template <int W, class Visit>
+__device__ __forceinline__ int walk_wave(const WideNode<W>* __restrict__ nodes, const Ray& rf,
+                                         bool live, float& tcut, float slack, float* lds_t,
+                                         int cap, int64_t max_steps, uint32_t& n_nodes,
+                                         uint32_t& n_prims, Visit&& visit)
+{
+    const int lane = (int)__lane_id();
+    int32_t stk_node = 0;
+    int sp = 0;
+    int32_t node = 0;
+    float t_in = -INFINITY;
+    for (int64_t step = 0;; ++step) {
+        if (step > max_steps) return kWalkOverflow;
+        const bool on = live && t_in <= tcut + slack;
+        const uint64_t act = __ballot(on);
+        if (act != 0) {
+            if (node >= 0) {
+                n_nodes += on ? 1u : 0u;
+                NodeBuf<W> b;
+                load_node<W>(nodes, node, b);
+                float te[W];
+                slab_entry<W>(b, rf, tcut + slack, te);
+                const int rep = __builtin_ctzll(act);
+                uint32_t key[W];
+#pragma unroll
+                for (int c = 0; c < W; ++c) {
+                    const bool hit = on && te[c] != INFINITY;
+                    if (!on) te[c] = INFINITY;
+                    const uint32_t k =
+                        (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(te[c]), rep);
+                    key[c] = __ballot(hit) != 0 ? ((k & ~7u) | (uint32_t)c) : 0xFFFFFFFFu;
+                }
+                sort_keys<W>(key);
+                int nh = 0;
+#pragma unroll
+                for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
+                if (nh > 0) {
+                    if (sp + nh - 1 > cap) return kWalkOverflow;
+#pragma unroll
+                    for (int c = W - 1; c >= 1; --c)
+                        if (key[c] != 0xFFFFFFFFu) {
+                            const uint32_t slot = key[c] & 7u;
+                            float tv = te[0];
+#pragma unroll
+                            for (int j = 1; j < W; ++j) tv = slot == (uint32_t)j ? te[j] : tv;
+                            lds_t[sp * 64 + lane] = tv;
+                            stk_node = lane == sp ? child_at<W>(b, slot) : stk_node;
+                            ++sp;
+                        }
+                    const uint32_t s0 = key[0] & 7u;
+                    float tv = te[0];
+#pragma unroll
+                    for (int j = 1; j < W; ++j) tv = s0 == (uint32_t)j ? te[j] : tv;
+                    t_in = tv;
+                    node = child_at<W>(b, s0);
+                    continue;
+                }
+            } else {
+                const uint32_t first = leaf_first(node), count = leaf_count(node);
+                for (uint32_t i = 0; i < count; ++i) {
+                    n_prims += on ? 1u : 0u;
+                    visit(first + i, on);
+                }
+            }
+        }
+        if (sp == 0) return kWalkDone;
+        --sp;
+        node = __builtin_amdgcn_readlane(stk_node, sp);
+        t_in = lds_t[sp * 64 + lane];
+    }
+}
+
 // Depth cut just beyond the key depth t: the entry distance of a box that
 // holds a candidate of depth <= t is computed within a few ulps of it.
 __device__ __forceinline__ float cut_after(float t)

@@ -1,8 +1,12 @@
 // Forward stochastic ray tracing on gfx950.
 //
-// One lane per ray. The lane walks the W-wide BVH with a per-lane stack in
-// LDS (stride = block size, so the 64 lanes of a wave hit 64 distinct banks
-// whatever their depths), visiting hit children near to far. Each Gaussian of
+// One lane per ray. For an image launch of closest-hit rays the 64 rays of
+// an 8x8 pixel tile walk the BVH together (k_trace_wave: one shared stack,
+// node and record fetches once per wave, each lane acting only on the nodes
+// and Gaussians its own walk would reach). Otherwise each lane walks the
+// W-wide BVH with a per-lane stack in LDS (stride = block size, so the 64
+// lanes of a wave hit 64 distinct banks whatever their depths), visiting hit
+// children near to far. Each Gaussian of
 // a reached leaf is tested in FP64 (Sec. 3.1, eqn "cuboid"); a valid one
 // draws u from Philox per sample and is accepted iff u < alpha (eqn "rr");
 // each of the N samples of the traversal keeps its closest accepted
@@ -414,6 +418,151 @@ __global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
     }
 }
 
+// Wave-shared walks for image launches of closest-hit rays (same outputs as
+// k_trace, bit for bit): each wave is one workgroup and one 8x8 pixel tile,
+// and the 64 rays of the tile traverse the BVH together (walk_wave), so the
+// wave never diverges between node steps and leaf tests and reads each node
+// and record once instead of once per lane. Lanes keep their own samples,
+// depth cuts and candidate tests. When the shared stack would exceed
+// kWaveCap the whole tile is queued for the deep pass (k_trace with DEEP),
+// which reruns all passes of its rays.
+constexpr int kWaveCap = 48;
+
+template <int W, int N, bool COUNT, int DM>
+__global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __restrict__ nodes_v,
+                                                   const Record* __restrict__ recs)
+{
+    __shared__ float lds_t[kWaveCap * 64];
+    const WideNode<W>* __restrict__ nodes = static_cast<const WideNode<W>*>(nodes_v);
+    const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 64 + threadIdx.x;
+    const int64_t ray = tile_pixel(t, a.img_w, a.R / a.img_w);
+    const bool valid = ray >= 0;
+    const int64_t rr = valid ? ray : 0;
+    const float ox = a.o[3 * rr], oy = a.o[3 * rr + 1], oz = a.o[3 * rr + 2];
+    const float dx = a.d[3 * rr], dy = a.d[3 * rr + 1], dz = a.d[3 * rr + 2];
+    const float tmin_f = a.tmin ? a.tmin[rr] : 0.0f;
+    const float tmax_f = a.tmax ? a.tmax[rr] : INFINITY;
+    const int32_t ign = a.ign ? a.ign[rr] : -1;
+    const uint32_t rid = a.rid ? a.rid[rr] : (uint32_t)rr;
+    const uint32_t sbase = (a.sid ? a.sid[rr] : 0u) + a.soff;
+    const bool live = valid && tmax_f > tmin_f;
+
+    const Ray rd = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
+    const ForwardCtx fc{recs, a.purpose, a.k0, a.k1};
+    const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rd, a.r_max);
+    const float slack = DM == 0 ? 0.0f : dc.node_slack;
+    const bool shade = a.rgb != nullptr;
+    const int cap = min(kWaveCap, a.stack_cap);
+
+    Counts cnt;
+    uint32_t samples = 0;
+    float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+    bool overflow = false;
+    for (int pass = 0; pass * N < a.spp; ++pass) {
+        const int n_act = min(N, a.spp - pass * N);
+        const uint32_t s0 = sbase + (uint32_t)(pass * N);
+        FwdSamples<N> st;
+        st.reset(n_act, tmax_f);
+        FwdCounts fcnt;
+        auto visit = [&](uint32_t ri, bool on) {
+            const Record r = load_record(recs, ri);
+            if (on)
+                fwd_offer<N, false, false, DM>(st, r, rd, dc, (double)tmin_f, (double)tmax_f, ign,
+                                               rid, s0, fc, fcnt);
+        };
+        uint32_t n_nodes = 0, n_prims = 0;
+        const int res = walk_wave<W>(nodes, rd, live, st.tcut, slack, lds_t, cap, a.max_steps,
+                                     n_nodes, n_prims, visit);
+        if (live) {
+            ++cnt.trav;
+            cnt.nodes += n_nodes;
+            cnt.prims += n_prims;
+            cnt.cands += fcnt.cands;
+            cnt.philox += fcnt.philox;
+        }
+        if (res == kWalkOverflow) {
+            overflow = true;
+            break;
+        }
+        if (!valid) continue;
+        samples += live ? (uint32_t)n_act : 0u;
+        float Y[16];
+        if (shade) {
+            const float ex = opaque(dx), ey = opaque(dy), ez = opaque(dz);
+            const float n = sqrtf(ex * ex + ey * ey + ez * ez);
+            sh_eval(a.deg, ex / n, ey / n, ez / n, Y);
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (k >= n_act) continue;
+            const bool hit = st.bg[k] != INT_MAX;
+            const int64_t o = ray * a.spp + pass * N + k;
+            if (a.hit_gid) a.hit_gid[o] = hit ? st.bg[k] : -1;
+            if (a.hit_t) a.hit_t[o] = hit ? st.bt[k] : INFINITY;
+            if (shade) {
+                if (hit) {
+                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, st.bg[k], Y));
+                    acc0 += c.x; acc1 += c.y; acc2 += c.z;
+                } else {
+                    acc0 += a.bg[0]; acc1 += a.bg[1]; acc2 += a.bg[2];
+                }
+            }
+        }
+    }
+    if (overflow) {
+        if (valid) {
+            const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+            a.ovf_list[slot] = (uint32_t)ray;
+        }
+    } else if (valid) {
+        if (a.rgb) {
+            const float inv = 1.0f / (float)a.spp;
+            a.rgb[3 * ray] = acc0 * inv;
+            a.rgb[3 * ray + 1] = acc1 * inv;
+            a.rgb[3 * ray + 2] = acc2 * inv;
+        }
+        cnt.samples += samples;
+    }
+    if (COUNT && a.counters) {
+        wave_add_u64(a.counters + SRT_CNT_TRAVERSALS, cnt.trav);
+        wave_add_u64(a.counters + SRT_CNT_NODES, cnt.nodes);
+        wave_add_u64(a.counters + SRT_CNT_PRIMS, cnt.prims);
+        wave_add_u64(a.counters + SRT_CNT_CANDIDATES, cnt.cands);
+        wave_add_u64(a.counters + SRT_CNT_PHILOX, cnt.philox);
+        wave_add_u64(a.counters + SRT_CNT_RAY_SAMPLES, cnt.samples);
+    }
+}
+
+using WaveFn = void (*)(TraceArgs, const void*, const Record*);
+
+template <int W, int DM>
+WaveFn wave_w(int N, bool count)
+{
+    switch (N) {
+    case 1: return count ? k_trace_wave<W, 1, true, DM> : k_trace_wave<W, 1, false, DM>;
+    case 2: return count ? k_trace_wave<W, 2, true, DM> : k_trace_wave<W, 2, false, DM>;
+    case 4: return count ? k_trace_wave<W, 4, true, DM> : k_trace_wave<W, 4, false, DM>;
+    case 8: return count ? k_trace_wave<W, 8, true, DM> : k_trace_wave<W, 8, false, DM>;
+    }
+    return nullptr;
+}
+
+template <int DM>
+WaveFn wave_dm(int W, int N, bool count)
+{
+    switch (W) {
+    case 2: return wave_w<2, DM>(N, count);
+    case 4: return wave_w<4, DM>(N, count);
+    case 8: return wave_w<8, DM>(N, count);
+    }
+    return nullptr;
+}
+
+WaveFn pick_wave(int W, int N, bool count, int depth_mode)
+{
+    return depth_mode == 0 ? wave_dm<0>(W, N, count) : wave_dm<1>(W, N, count);
+}
+
 using KernelFn = void (*)(TraceArgs);
 
 template <int W, int N, bool ANY, bool H, int DM>
@@ -522,6 +671,7 @@ srt_status validate_opts(const srt_trace_opts* o)
     if (o->persistent != 0 && o->persistent != 1) return SRT_ERR_INVALID_ARG;
     if (o->refill_threshold < 0 || o->refill_threshold > 64) return SRT_ERR_INVALID_ARG;
     if (o->rng != 0 && o->rng != 1) return SRT_ERR_INVALID_ARG;
+    if (o->walk < 0 || o->walk > 2) return SRT_ERR_INVALID_ARG;
     return SRT_OK;
 }
 
@@ -573,6 +723,14 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
     // ctrl[0] overflow count, ctrl[1] rays lost, ctrl[2..3] the persistent work counter
     a.work = reinterpret_cast<unsigned long long*>(ws.ctrl + 2);
     a.threshold = o->refill_threshold > 0 ? o->refill_threshold : kDefaultRefill;
+    // wave-shared walks: image launches of closest-hit Philox rays, not persistent
+    const bool wave_ok = a.img_w > 0 && !o->any_hit && o->rng == 0 && !o->persistent;
+    if (o->walk == 2 && !wave_ok) return SRT_ERR_UNSUPPORTED;
+    WaveFn wf = nullptr;
+    if (o->walk != 1 && wave_ok) {
+        wf = pick_wave(b->W, o->n_per_traversal, counters != nullptr, o->depth_mode);
+        if (!wf) return SRT_ERR_UNSUPPORTED;
+    }
     KernelFn pf = nullptr;
     unsigned blocks = 0;
     if (o->persistent && rays->count > 0) {
@@ -586,6 +744,10 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
     if (rays->count > 0) {
         if (pf) {
             hipLaunchKernelGGL(pf, dim3(blocks), dim3(kPersistBlock), 0, s, a);
+        } else if (wf) {
+            const int64_t tiles = tile_threads(a.img_w, rays->count / a.img_w) / 64;
+            hipLaunchKernelGGL(wf, dim3((unsigned)tiles), dim3(64), 0, s, a,
+                               static_cast<const void*>(b->nodes), b->recs);
         } else {
             const int64_t threads =
                 a.img_w > 0 ? tile_threads(a.img_w, rays->count / a.img_w) : rays->count;
@@ -907,6 +1069,7 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
     so.n_per_traversal = 1;
     so.sample_offset = opts->sample_offset;
     so.image_width = 0;
+    so.walk = opts->walk == 1 ? 1 : 0;  // secondary rays are not an image
     for (int pass = 0; pass < 2; ++pass) {
         const SecRays& sr = pass == 0 ? w.sh : w.mr;
         srt_rays rr{};

@@ -493,3 +493,88 @@ def test_hash_rng_unsupported_combinations(srt):
                      device="cuda")
     assert lib.srt_trace_forward(bvh.handle, C.byref(rays), C.byref(opts), None, None, None,
                                  None, ws.data_ptr(), ws.numel(), None) == 1
+
+
+@pytest.mark.parametrize("W,L,N,spp,mode,lim", [(4, 2, 4, 8, 0, 0), (2, 1, 1, 3, 0, 0),
+                                                (8, 4, 8, 8, 0, 0), (4, 4, 2, 6, 1, 0),
+                                                (4, 2, 4, 8, 0, 5), (8, 1, 4, 4, 1, 2)])
+def test_wave_walk_equals_lane_walk(srt, W, L, N, spp, mode, lim):
+    """The 64 rays of a tile walking the BVH together reach, per ray, the same
+    candidates as the ray's own walk: outputs equal bit for bit, with ragged
+    tiles, empty rays, ignored ids and (lim > 0) tiles whose shared stack
+    overflows into the deep pass."""
+    say(f"wave-shared walk vs lane walk: W={W} L={L} N={N} spp={spp} depth mode {mode} "
+        f"stack limit {lim}")
+    sc = tiny_scene(23, 3000, (0.02, 0.08))
+    cam = si.look_at((0.1, 0.3, 2.8), (0, 0, 0), 37, 29)
+    o, d = si.camera_rays(cam)
+    R = len(o)
+    rng = np.random.default_rng(9)
+    tmin = rng.uniform(0.0, 1.5, R).astype(np.float32)
+    tmax = (tmin + rng.uniform(-0.2, 4.0, R)).astype(np.float32)
+    tmax[::7] = np.inf
+    ign = rng.integers(-1, 3000, R).astype(np.int32)
+    kw = dict(seed=13, spp=spp, n_per_traversal=N, bg=(0.2, 0.1, 0.7), tmin=_cuda(tmin),
+              tmax=_cuda(tmax), ignore_gid=_cuda(ign), sample_offset=3, depth_mode=mode,
+              image_width=cam.width, stack_limit=lim)
+    bvh = srt.srt_build_bvh(device_scene(sc), W, L)
+    lane = _trace(srt, bvh, o, d, walk="lane", **kw)
+    cnt = srt.new_counters()
+    wave = _trace(srt, bvh, o, d, walk="wave", counters=cnt, **kw)
+    for k in ("hit_gid", "hit_t", "rgb"):
+        np.testing.assert_array_equal(wave[k], lane[k], err_msg=k)
+    c = srt.counters_dict(cnt)
+    assert c["lost"] == 0
+    assert c["ray_samples"] == int((tmax > tmin).sum()) * spp
+    if lim:
+        assert c["deep"] > 0
+    if (W, L, N, mode, lim) == (4, 2, 4, 0, 0):
+        rays = oracle.Rays(o, d, tmin, tmax, ign, sample_base=np.full(R, 3, np.uint32))
+        ora = oracle.trace(oracle.Records(sc), rays, spp=spp, seed=13)
+        compare_ids(wave["hit_gid"], ora["hit_gid"], ora["flags"])
+
+
+def test_wave_walk_on_the_four_shell_scene(srt):
+    """Camera tiles of the path-tracer scene (small variant): the wave-shared
+    walk equals the lane walk. (Its per-ray node and Gaussian counts differ:
+    the tile visits children in one lane's near-to-far order, so the other
+    lanes' depth cuts shrink at other times.)"""
+    say("wave-shared walk on the four-shell scene, 160x96, 8 spp")
+    w = si.workload(3, small=True)
+    cam = si.look_at((0.0, 0.0, 4.0), (0, 0, 0), 160, 96)
+    o, d = si.camera_rays(cam)
+    bvh = srt.srt_build_bvh(device_scene(w["scene"]), 4, 2)
+    res, cnts = {}, {}
+    for walk in ("lane", "wave"):
+        cnt = srt.new_counters()
+        res[walk] = _trace(srt, bvh, o, d, seed=4, spp=8, n_per_traversal=4,
+                           image_width=cam.width, walk=walk, counters=cnt)
+        cnts[walk] = srt.counters_dict(cnt)
+    for k in ("hit_gid", "hit_t", "rgb"):
+        np.testing.assert_array_equal(res["wave"][k], res["lane"][k], err_msg=k)
+    say(f"counters lane {cnts['lane']} wave {cnts['wave']}")
+    for k in ("traversals", "ray_samples"):
+        assert cnts["wave"][k] == cnts["lane"][k]
+
+
+def test_walk_option_errors(srt):
+    sc = tiny_scene(24, 100)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    o = torch.zeros((16, 3), device="cuda")
+    d = torch.tensor([[0.0, 0.0, 1.0]] * 16, device="cuda")
+    for kw in (dict(), dict(image_width=4, any_hit=True), dict(image_width=4, persistent=True),
+               dict(image_width=4, rng="hash")):
+        with pytest.raises(srt.SrtError) as e:
+            srt.srt_trace_forward(bvh, o, d, walk="wave", **kw)
+        assert e.value.code == 4, kw
+    with pytest.raises(ValueError):
+        srt.srt_trace_forward(bvh, o, d, walk="tile")
+    opts = srt._opts(0, 1, 1, 0, (0, 0, 0), False, 0)
+    opts.walk = 3
+    import ctypes as C
+    lib = srt._lib.load()
+    rays = srt._lib.SrtRays(16, o.data_ptr(), d.data_ptr(), None, None, None, None, None, 0)
+    ws = torch.empty(lib.srt_trace_workspace_size(bvh.handle, 16), dtype=torch.uint8,
+                     device="cuda")
+    assert lib.srt_trace_forward(bvh.handle, C.byref(rays), C.byref(opts), None, None, None,
+                                 None, ws.data_ptr(), ws.numel(), None) == 1
