@@ -184,7 +184,8 @@ typedef struct {
  *                 in all three channels and hit_gid is any accepted id.
  *                 Requires n_per_traversal == 1.
  * stack_limit     0 = default; otherwise caps the on-chip traversal stack
- *                 (testing: forces the deep-stack path).
+ *                 (testing: forces the deep-stack path in the forward, and
+ *                 the global-memory part of the stacks in the backward).
  * depth_mode      0: a candidate's depth is the mean of the 1D Gaussian along
  *                 the ray (Sec. 3.1). 1: the Gaussian centre projected onto
  *                 depth_axis, as the ray parameter of the same depth along
@@ -226,8 +227,10 @@ typedef struct {
  *                 2: the 64 rays of a wave walk it together, one node at a
  *                 time (a lane takes part in the nodes and leaves its own
  *                 walk would reach); for image launches (image_width > 0) of
- *                 closest-hit rays with Philox numbers and persistent = 0,
- *                 else SRT_ERR_UNSUPPORTED. Results do not depend on it.   */
+ *                 closest-hit rays with Philox numbers and persistent = 0 in
+ *                 the forward, image launches in the backward, else
+ *                 SRT_ERR_UNSUPPORTED. Results do not depend on it (backward
+ *                 gradients up to the order of FP32 atomic additions).     */
 typedef struct {
     uint64_t seed;
     int32_t spp;

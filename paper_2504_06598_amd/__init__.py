@@ -220,12 +220,13 @@ def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t
                        tmin=None, tmax=None, ignore_gid=None, ray_ids=None, sample_ids=None,
                        purpose=0, seed=0, spp=1, n_per_traversal=1, sample_offset=0,
                        bg=(0.0, 0.0, 0.0), depth_mode=0, depth_axis=(0.0, 0.0, 0.0),
-                       image_width=0, estimator="plain", rng="philox", grads=None,
-                       counters=None, workspace=None):
+                       image_width=0, estimator="plain", rng="philox", walk="auto",
+                       stack_limit=0, grads=None, counters=None, workspace=None):
     """Accumulate gradients of sum(grad_rgb * E[rgb]) into `grads` (a dict of
     tensors shaped like the scene's; zeros are allocated when absent).
     estimator: "plain" (per-sample score terms) or "rb" (each term averaged
-    over its own acceptance number; no larger variance)."""
+    over its own acceptance number; no larger variance). walk: as in
+    srt_trace_forward (wave-shared walks for image launches by default)."""
     lib = _lib.load()
     sc = bvh.scene
     R = int(origins.shape[0])
@@ -235,8 +236,8 @@ def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t
                  ("means", "log_scales", "quats", "opacity_logits", "sh")}
     rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
                         _ptr(ray_ids), _ptr(sample_ids), int(purpose))
-    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, 0, depth_mode, depth_axis,
-                 image_width, estimator=estimator, rng=rng)
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, False, stack_limit, depth_mode,
+                 depth_axis, image_width, estimator=estimator, rng=rng, walk=walk)
     need = lib.srt_backward_workspace_size(bvh.handle, R)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)

@@ -73,6 +73,7 @@ struct BwdArgs {
     float* g_sh;
     int32_t* glb_stack;
     int32_t glb_stride;
+    int32_t lds_cap;  // stack entries kept in LDS (<= kLdsEntries); the rest in glb_stack
     int32_t cap;
     int64_t max_steps;
     unsigned long long* counters;
@@ -130,8 +131,11 @@ __device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, con
     }
 }
 
-template <int W, int N, bool COUNT, bool RB, int DM>
-__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
+// WV: the 64 rays of each 8x8 tile re-traverse together (walk_wave; image
+// launches), else each lane walks for its own ray.
+template <int W, int N, bool COUNT, bool RB, int DM, bool WV>
+__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a, const void* __restrict__ nodes_v,
+                                                     const Record* __restrict__ recs_r)
 {
     __shared__ int32_t lds[kLdsEntries * kBlock];
     __shared__ int32_t tkeys[kTableSlots];
@@ -149,8 +153,14 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
     }
     __syncthreads();
     const int64_t gt = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    TwoTierStack stk{lds + threadIdx.x, kBlock, kLdsEntries, a.glb_stack + gt, a.glb_stride, a.cap};
+    TwoTierStack stk{lds + threadIdx.x, kBlock, a.lds_cap, a.glb_stack + gt, a.glb_stride, a.cap};
+    // wave-shared stack: entry depths in this wave's half of the same LDS, then
+    // in the lane's global stack
+    WaveStack wstk{reinterpret_cast<float*>(lds) + (threadIdx.x >> 6) * (kLdsEntries * 64),
+                   a.lds_cap, reinterpret_cast<float*>(a.glb_stack + gt), a.glb_stride,
+                   min(128, a.cap)};
     const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
+    const WideNode<W>* __restrict__ wnodes = static_cast<const WideNode<W>*>(nodes_v);
     const int K = (a.deg + 1) * (a.deg + 1);
     const float inv_spp = 1.0f / (float)a.spp;
     uint32_t n_trav = 0, n_nodes = 0, n_prims = 0, n_front = 0, n_samples = 0, n_lost = 0,
@@ -198,19 +208,21 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
             tmax_f = a.tmax ? a.tmax[ray] : INFINITY;
         }
         const bool work = valid && (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f) && tmax_f > tmin_f;
-        if (work) {
-            const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
-            const float dx = a.d[3 * ray], dy = a.d[3 * ray + 1], dz = a.d[3 * ray + 2];
-            const int32_t ign = a.ign ? a.ign[ray] : -1;
-            const uint32_t rid = a.rid ? a.rid[ray] : (uint32_t)ray;
-            const uint32_t sbase = (a.sid ? a.sid[ray] : 0u) + a.soff;
+        // WV: lanes without work take part in the shared walks with no samples
+        if (WV || work) {
+            const int64_t rq = work ? ray : 0;
+            const float ox = a.o[3 * rq], oy = a.o[3 * rq + 1], oz = a.o[3 * rq + 2];
+            const float dx = a.d[3 * rq], dy = a.d[3 * rq + 1], dz = a.d[3 * rq + 2];
+            const int32_t ign = a.ign ? a.ign[rq] : -1;
+            const uint32_t rid = a.rid ? a.rid[rq] : (uint32_t)rq;
+            const uint32_t sbase = (a.sid ? a.sid[rq] : 0u) + a.soff;
             const Ray rr = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
             const double tmin = tmin_f, tmax = tmax_f;
             const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rr, a.r_max);
             float Y[16];
             sh_eval(a.deg, dx * rr.inv_len, dy * rr.inv_len, dz * rr.inv_len, Y);
             for (int pass = 0; pass * N < a.spp; ++pass) {
-                const int n_act = min(N, a.spp - pass * N);
+                const int n_act = work ? min(N, a.spp - pass * N) : 0;
                 float ta[N];
                 int32_t ga[N];
                 if (a.hit_gid) {
@@ -227,14 +239,21 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                         }
                     }
                 } else {
-                    const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
+                    const ForwardCtx fc{WV ? recs_r : a.recs, a.purpose, a.k0, a.k1};
                     uint32_t dummy_nodes = 0, dummy_prims = 0;
-                    const int res = resolve_samples<W, N, false, TwoTierStack, false, DM>(
-                        nodes, fc, dc, rr, tmin, tmax, ign, rid, sbase + (uint32_t)(pass * N),
-                        n_act, stk, a.max_steps, ta, ga, dummy_nodes, dummy_prims, n_fwd_cands,
-                        n_philox);
-                    if (res == kWalkOverflow) {
-                        ++n_lost;
+                    int res;
+                    if constexpr (WV)
+                        res = resolve_samples_wave<W, N, DM>(
+                            wnodes, recs_r, fc, dc, rr, work, tmin, tmax, ign, rid,
+                            sbase + (uint32_t)(pass * N), n_act, wstk, a.max_steps, ta, ga,
+                            dummy_nodes, dummy_prims, n_fwd_cands, n_philox);
+                    else
+                        res = resolve_samples<W, N, false, TwoTierStack, false, DM>(
+                            nodes, fc, dc, rr, tmin, tmax, ign, rid, sbase + (uint32_t)(pass * N),
+                            n_act, stk, a.max_steps, ta, ga, dummy_nodes, dummy_prims,
+                            n_fwd_cands, n_philox);
+                    if (res == kWalkOverflow) {  // wave-uniform under WV
+                        n_lost += work ? 1u : 0u;
                         continue;
                     }
                 }
@@ -274,11 +293,10 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     }
                 }
                 n_samples += (uint32_t)n_act;
-                ++n_trav;
+                n_trav += work ? 1u : 0u;
                 float tcut = fminf(cut_after(wt), tmax_f);
                 const uint32_t s0 = sbase + (uint32_t)(pass * N);
-                auto visit = [&](uint32_t ri) -> bool {
-                    const Record r = load_record(a.recs, ri);
+                auto visit_rec = [&](const Record& r) -> bool {
                     if (depth_mode_of<DM>(dc) == 0 ? sphere_reject(r, rr, tmin_f, tcut)
                                                    : sphere_reject(r, rr, -INFINITY, INFINITY))
                         return false;
@@ -359,9 +377,22 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a)
                     table_add(table, a.acc, r.gid, v);
                     return false;
                 };
-                const int res = walk<W>(nodes, rr, tcut, DM == 0 ? 0.0f : dc.node_slack, stk,
-                                        a.max_steps, n_nodes, n_prims, visit);
-                if (res == kWalkOverflow) ++n_lost;
+                const float slack = DM == 0 ? 0.0f : dc.node_slack;
+                int res;
+                if constexpr (WV) {
+                    auto visit = [&](uint32_t ri, bool on) {
+                        const Record r = load_record(recs_r, ri);
+                        if (on) visit_rec(r);
+                    };
+                    res = walk_wave<W>(wnodes, rr, work, tcut, slack, wstk, a.max_steps, n_nodes,
+                                       n_prims, visit);
+                } else {
+                    auto visit = [&](uint32_t ri) -> bool {
+                        return visit_rec(load_record(a.recs, ri));
+                    };
+                    res = walk<W>(nodes, rr, tcut, slack, stk, a.max_steps, n_nodes, n_prims, visit);
+                }
+                if (res == kWalkOverflow) n_lost += work ? 1u : 0u;
                 if constexpr (RB) {
                     // -<g, X2> on the alpha of each sample's first accepted a (X2 the
                     // colour of its second accepted, bg if none), samples sharing a merged
@@ -531,41 +562,45 @@ __global__ void k_chain(int64_t G, const float* __restrict__ acc, const float* _
     g_logits[g] += (float)((1.0 - o) * A);
 }
 
-using BwdFn = void (*)(BwdArgs);
+using BwdFn = void (*)(BwdArgs, const void*, const Record*);
 
-template <int W, bool C, bool RB, int DM>
+template <int W, bool C, bool RB, int DM, bool WV>
 BwdFn pick_n(int N)
 {
     switch (N) {
-    case 1: return k_backward<W, 1, C, RB, DM>;
-    case 2: return k_backward<W, 2, C, RB, DM>;
-    case 4: return k_backward<W, 4, C, RB, DM>;
-    case 8: return k_backward<W, 8, C, RB, DM>;
+    case 1: return k_backward<W, 1, C, RB, DM, WV>;
+    case 2: return k_backward<W, 2, C, RB, DM, WV>;
+    case 4: return k_backward<W, 4, C, RB, DM, WV>;
+    case 8: return k_backward<W, 8, C, RB, DM, WV>;
     }
     return nullptr;
 }
 
-template <int W, int DM>
+template <int W, int DM, bool WV>
 BwdFn pick_w(int N, bool count, bool rb)
 {
-    if (rb) return count ? pick_n<W, true, true, DM>(N) : pick_n<W, false, true, DM>(N);
-    return count ? pick_n<W, true, false, DM>(N) : pick_n<W, false, false, DM>(N);
+    if (rb) return count ? pick_n<W, true, true, DM, WV>(N) : pick_n<W, false, true, DM, WV>(N);
+    return count ? pick_n<W, true, false, DM, WV>(N) : pick_n<W, false, false, DM, WV>(N);
 }
 
-template <int DM>
+template <int DM, bool WV>
 BwdFn pick_dm(int W, int N, bool count, bool rb)
 {
     switch (W) {
-    case 2: return pick_w<2, DM>(N, count, rb);
-    case 4: return pick_w<4, DM>(N, count, rb);
-    case 8: return pick_w<8, DM>(N, count, rb);
+    case 2: return pick_w<2, DM, WV>(N, count, rb);
+    case 4: return pick_w<4, DM, WV>(N, count, rb);
+    case 8: return pick_w<8, DM, WV>(N, count, rb);
     }
     return nullptr;
 }
 
-BwdFn pick(int W, int N, bool count, bool rb, int depth_mode)
+BwdFn pick(int W, int N, bool count, bool rb, int depth_mode, bool wave)
 {
-    return depth_mode == 0 ? pick_dm<0>(W, N, count, rb) : pick_dm<1>(W, N, count, rb);
+    if (wave)
+        return depth_mode == 0 ? pick_dm<0, true>(W, N, count, rb)
+                               : pick_dm<1, true>(W, N, count, rb);
+    return depth_mode == 0 ? pick_dm<0, false>(W, N, count, rb)
+                           : pick_dm<1, false>(W, N, count, rb);
 }
 
 constexpr int64_t kMaxBwdBlocks = 2048;
@@ -590,9 +625,9 @@ BwdWs bwd_ws(const srt_bvh* b, int64_t R, void* base)
     off = align_up(off + 128 * sizeof(uint32_t), 256);
     w.acc = reinterpret_cast<float*>(p ? p + off : nullptr);
     off = align_up(off + sizeof(float) * kAccStride * (size_t)std::max<int64_t>(b->G, 1), 256);
-    const int32_t extra = std::max(0, deep_stack_cap(b) - kLdsEntries);
+    // a whole stack per thread, so that any split between LDS and global fits
     w.stack = reinterpret_cast<int32_t*>(p ? p + off : nullptr);
-    off = align_up(off + sizeof(int32_t) * (size_t)w.threads * (size_t)std::max(extra, 1), 256);
+    off = align_up(off + sizeof(int32_t) * (size_t)w.threads * (size_t)deep_stack_cap(b), 256);
     w.bytes = off;
     return w;
 }
@@ -621,6 +656,10 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     if (opts->image_width > 0 && rays->count % opts->image_width != 0) return SRT_ERR_INVALID_ARG;
     if (opts->estimator != 0 && opts->estimator != 1) return SRT_ERR_INVALID_ARG;
     if (opts->rng != 0 && opts->rng != 1) return SRT_ERR_INVALID_ARG;
+    if (opts->walk < 0 || opts->walk > 2) return SRT_ERR_INVALID_ARG;
+    if (opts->stack_limit < 0) return SRT_ERR_INVALID_ARG;
+    // wave-shared walks need an image launch (tiles of neighbouring rays)
+    if (opts->walk == 2 && opts->image_width == 0) return SRT_ERR_UNSUPPORTED;
     // the backward draws numbers only to recompute results or to find second
     // hits; with the hash those are not provided here
     if (opts->rng == 1 && (hit_gid == nullptr || opts->estimator == 1))
@@ -639,7 +678,8 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     if (b->G == 0 || rays->count == 0) return SRT_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const BwdWs ws = bwd_ws(b, rays->count, workspace);
-    BwdFn fn = pick(b->W, N, counters != nullptr, opts->estimator == 1, opts->depth_mode);
+    const bool wave = opts->walk != 1 && opts->image_width > 0;
+    BwdFn fn = pick(b->W, N, counters != nullptr, opts->estimator == 1, opts->depth_mode, wave);
     if (!fn) return SRT_ERR_UNSUPPORTED;
     // as many workgroups as stay resident (tiles are handed out dynamically),
     // at most the number the workspace holds stacks for
@@ -677,7 +717,8 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     a.g_sh = g_sh;
     a.glb_stack = ws.stack;
     a.glb_stride = ws.threads;
-    a.cap = kLdsEntries + std::max(0, deep_stack_cap(b) - kLdsEntries);
+    a.lds_cap = opts->stack_limit > 0 ? std::min(kLdsEntries, opts->stack_limit) : kLdsEntries;
+    a.cap = std::max(a.lds_cap, deep_stack_cap(b));
     a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
     a.counters = reinterpret_cast<unsigned long long*>(counters);
     a.depth_mode = opts->depth_mode;
@@ -687,7 +728,8 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     a.leaf_pos = b->leaf_pos;
     a.tile_ctr = ws.tile_ctr;
     fill_u32(ws.tile_ctr, 0u, 128, s);
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, s, a, static_cast<const void*>(b->nodes),
+                       static_cast<const Record*>(b->recs));
     SRT_HIP_TRY(hipGetLastError());
     k_chain<<<(unsigned)((b->G + 255) / 256), 256, 0, s>>>(
         b->G, ws.acc, scene->log_scales, scene->quats, scene->opacity_logits, g_means, g_log_scales,

@@ -88,27 +88,60 @@ __device__ __forceinline__ int walk(const WideNode<W>* __restrict__ nodes, const
     }
 }
 
+// Stack of a walk shared by the 64 lanes of a wave. Node ids are uniform:
+// entry i sits in lane i % 64 of register ids[i / 64] (so cap <= 128). Each
+// lane's entry depth of entry i sits in LDS at lds[i * 64 + lane] for
+// i < lds_cap, beyond that in global memory at glb[(i - lds_cap) * stride]
+// (a per-lane base, as TwoTierStack; null when there is no second tier).
+struct WaveStack {
+    float* lds;
+    int lds_cap;
+    float* glb;
+    int64_t glb_stride;
+    int cap;
+    int32_t ids[2] = {0, 0};
+
+    __device__ __forceinline__ void push(int i, int32_t id, float t, int lane)
+    {
+        if (i < 64)
+            ids[0] = lane == i ? id : ids[0];
+        else
+            ids[1] = lane == i - 64 ? id : ids[1];
+        if (i < lds_cap)
+            lds[i * 64 + lane] = t;
+        else
+            glb[(int64_t)(i - lds_cap) * glb_stride] = t;
+    }
+    __device__ __forceinline__ int32_t id(int i) const
+    {
+        return i < 64 ? __builtin_amdgcn_readlane(ids[0], i)
+                      : __builtin_amdgcn_readlane(ids[1], i - 64);
+    }
+    __device__ __forceinline__ float depth(int i, int lane) const
+    {
+        return i < lds_cap ? lds[i * 64 + lane] : glb[(int64_t)(i - lds_cap) * glb_stride];
+    }
+};
+
 // One walk shared by the 64 rays of a wave (the rays of an 8x8 pixel tile
 // are coherent, so they need nearly the same nodes). The wave pops one node
 // at a time, in uniform control flow; a lane takes part when its ray entered
 // the node's box no farther than its own depth cut (plus slack), so each lane
-// sees exactly the nodes and leaves its own walk would reach, in another
-// order. Children go on the stack when any lane hit them, in the near-to-far
-// order of the first lane that takes part. The stack's node ids sit one per
-// lane of a register (entry i in lane i, so cap <= 64); each lane's entry
-// depth of every stacked node sits in LDS at t[i * 64 + lane] (+inf for
-// lanes that missed it). Node and record addresses are uniform, so they are
-// fetched once per wave. visit(record_index, on) is called by every lane for
-// each record of a reached leaf; only lanes with `on` may act on it. Returns
-// kWalkDone or kWalkOverflow (wave-uniform).
+// sees only nodes and leaves its own walk would reach, in another order
+// (results do not depend on the order). Children go on the stack when any
+// lane hit them, in the near-to-far order of the first lane that takes part
+// (+inf entry depth for the lanes that missed them). Node and record
+// addresses are uniform, so they are fetched once per wave. visit(record
+// index, on) is called by every lane for each record of a reached leaf; only
+// lanes with `on` may act on it. Returns kWalkDone or kWalkOverflow
+// (wave-uniform).
 template <int W, class Visit>
 __device__ __forceinline__ int walk_wave(const WideNode<W>* __restrict__ nodes, const Ray& rf,
-                                         bool live, float& tcut, float slack, float* lds_t,
-                                         int cap, int64_t max_steps, uint32_t& n_nodes,
+                                         bool live, float& tcut, float slack, WaveStack& stk,
+                                         int64_t max_steps, uint32_t& n_nodes,
                                          uint32_t& n_prims, Visit&& visit)
 {
     const int lane = (int)__lane_id();
-    int32_t stk_node = 0;
     int sp = 0;
     int32_t node = 0;
     float t_in = -INFINITY;
@@ -138,7 +171,7 @@ __device__ __forceinline__ int walk_wave(const WideNode<W>* __restrict__ nodes, 
 #pragma unroll
                 for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
                 if (nh > 0) {
-                    if (sp + nh - 1 > cap) return kWalkOverflow;
+                    if (sp + nh - 1 > stk.cap) return kWalkOverflow;
 #pragma unroll
                     for (int c = W - 1; c >= 1; --c)
                         if (key[c] != 0xFFFFFFFFu) {
@@ -146,8 +179,7 @@ __device__ __forceinline__ int walk_wave(const WideNode<W>* __restrict__ nodes, 
                             float tv = te[0];
 #pragma unroll
                             for (int j = 1; j < W; ++j) tv = slot == (uint32_t)j ? te[j] : tv;
-                            lds_t[sp * 64 + lane] = tv;
-                            stk_node = lane == sp ? child_at<W>(b, slot) : stk_node;
+                            stk.push(sp, child_at<W>(b, slot), tv, lane);
                             ++sp;
                         }
                     const uint32_t s0 = key[0] & 7u;
@@ -168,8 +200,8 @@ __device__ __forceinline__ int walk_wave(const WideNode<W>* __restrict__ nodes, 
         }
         if (sp == 0) return kWalkDone;
         --sp;
-        node = __builtin_amdgcn_readlane(stk_node, sp);
-        t_in = lds_t[sp * 64 + lane];
+        node = stk.id(sp);
+        t_in = stk.depth(sp, lane);
     }
 }
 
@@ -371,6 +403,41 @@ __device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ n
     };
     const float slack = DM == 0 ? 0.0f : dc.node_slack;
     const int res = walk<W>(nodes, ray, st.tcut, slack, stk, max_steps, n_nodes, n_prims, visit);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        bt[k] = st.bt[k];
+        bg[k] = st.bg[k];
+    }
+    n_cands += fcnt.cands;
+    n_philox += fcnt.philox;
+    return res;
+}
+
+// resolve_samples over a walk shared by the wave (closest-hit only); lanes
+// that are not live take part in the control flow and keep no hits.
+template <int W, int N, int DM = -1>
+__device__ __forceinline__ int resolve_samples_wave(const WideNode<W>* __restrict__ nodes,
+                                                    const Record* __restrict__ recs,
+                                                    const ForwardCtx& fc, const DepthCtx& dc,
+                                                    const Ray& ray, bool live, double tmin,
+                                                    double tmax, int32_t ign, uint32_t rid,
+                                                    uint32_t s0, int n_act, WaveStack& stk,
+                                                    int64_t max_steps, float (&bt)[N],
+                                                    int32_t (&bg)[N], uint32_t& n_nodes,
+                                                    uint32_t& n_prims, uint32_t& n_cands,
+                                                    uint32_t& n_philox)
+{
+    FwdSamples<N> st;
+    st.reset(n_act, (float)tmax);
+    FwdCounts fcnt;
+    auto visit = [&](uint32_t ri, bool on) {
+        const Record r = load_record(recs, ri);
+        if (on)
+            fwd_offer<N, false, false, DM>(st, r, ray, dc, tmin, tmax, ign, rid, s0, fc, fcnt);
+    };
+    const float slack = DM == 0 ? 0.0f : dc.node_slack;
+    const int res = walk_wave<W>(nodes, ray, live, st.tcut, slack, stk, max_steps, n_nodes,
+                                 n_prims, visit);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         bt[k] = st.bt[k];

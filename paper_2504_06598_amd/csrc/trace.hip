@@ -471,8 +471,9 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
                                                rid, s0, fc, fcnt);
         };
         uint32_t n_nodes = 0, n_prims = 0;
-        const int res = walk_wave<W>(nodes, rd, live, st.tcut, slack, lds_t, cap, a.max_steps,
-                                     n_nodes, n_prims, visit);
+        WaveStack stk{lds_t, kWaveCap, nullptr, 0, cap};
+        const int res = walk_wave<W>(nodes, rd, live, st.tcut, slack, stk, a.max_steps, n_nodes,
+                                     n_prims, visit);
         if (live) {
             ++cnt.trav;
             cnt.nodes += n_nodes;

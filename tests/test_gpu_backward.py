@@ -250,3 +250,73 @@ def test_rb_estimator_has_lower_variance_on_gpu(srt):
         assert np.mean(np.abs(a.mean(0) - b.mean(0)) <= 4 * se + 1e-9) > 0.97, name
     say(f"variance sum: plain {var['plain']:.4e}, rb {var['rb']:.4e}")
     assert var["rb"] < 0.8 * var["plain"], var
+
+
+@pytest.mark.parametrize("N,est,mode,stored,lim", [(4, "plain", 0, True, 0), (4, "rb", 0, True, 0),
+                                                   (1, "plain", 1, False, 0),
+                                                   (8, "rb", 0, False, 2),
+                                                   (2, "plain", 0, True, 1)])
+def test_wave_walk_backward_equals_lane_walk(srt, N, est, mode, stored, lim):
+    """Re-traversing each 8x8 tile as one wave-shared walk reaches, per ray,
+    the same candidates as the lane walk: gradients equal up to the order of
+    the FP32 sums, with ragged tiles, empty rays, ignored ids, results
+    recomputed in the backward (stored=False) and stacks pushed into global
+    memory (lim > 0)."""
+    say(f"backward wave walk vs lane walk: N={N} {est} depth mode {mode} stored={stored} "
+        f"lds stack {lim or 'default'}")
+    sc = tiny_scene(61, 2500, (0.02, 0.08), deg=2)
+    cam = si.look_at((0.1, 0.2, 2.9), (0, 0, 0), 37, 29)
+    o, d = si.camera_rays(cam)
+    R = len(o)
+    rng = np.random.default_rng(12)
+    tmin = rng.uniform(0.0, 1.0, R).astype(np.float32)
+    tmax = (tmin + rng.uniform(-0.2, 4.0, R)).astype(np.float32)
+    tmax[::5] = np.inf
+    ign = rng.integers(-1, 2500, R).astype(np.int32)
+    dLc = _cu(rng.normal(0, 1, (R, 3)).astype(np.float32))
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
+    oc, dc = _cu(o), _cu(d)
+    kw = dict(seed=21, spp=8, n_per_traversal=N, bg=(0.2, 0.1, 0.3), tmin=_cu(tmin),
+              tmax=_cu(tmax), ignore_gid=_cu(ign), depth_mode=mode, estimator=est,
+              image_width=cam.width, stack_limit=lim)
+    if stored:
+        fw = srt.srt_trace_forward(bvh, oc, dc, seed=21, spp=8, n_per_traversal=N,
+                                   tmin=kw["tmin"], tmax=kw["tmax"], ignore_gid=kw["ignore_gid"],
+                                   depth_mode=mode)
+        kw.update(hit_gid=fw["hit_gid"], hit_t=fw["hit_t"])
+    out, cnts = {}, {}
+    for walk in ("lane", "wave"):
+        cnt = srt.new_counters()
+        out[walk] = srt.srt_trace_backward(bvh, oc, dc, dLc, walk=walk, counters=cnt, **kw)
+        torch.cuda.synchronize()
+        cnts[walk] = srt.counters_dict(cnt)
+    for name in NAMES:
+        a, b = to_np(out["lane"][name]), to_np(out["wave"][name])
+        assert np.abs(a - b).max() <= 2e-5 * max(np.abs(a).max(), 1e-12), name
+    for k in ("ray_samples", "traversals", "lost"):
+        assert cnts["wave"][k] == cnts["lane"][k], (k, cnts)
+    assert cnts["wave"]["lost"] == 0
+    if (N, est, stored) == (4, "plain", True):
+        rays = oracle.Rays(o, d, tmin, tmax, ign)
+        ora_f = oracle.trace(oracle.Records(sc), rays, spp=8, seed=21, bg=kw["bg"])
+        dL = to_np(dLc).astype(np.float64)
+        dL[(ora_f["flags"] != 0).any(1)] = 0.0
+        g = srt.srt_trace_backward(bvh, oc, dc, _cu(dL.astype(np.float32)), walk="wave", **kw)
+        torch.cuda.synchronize()
+        ora = oracle.estimator_grad(oracle.Records(sc), rays, dL, spp=8, seed=21, bg=kw["bg"])
+        for name in NAMES:
+            _close(to_np(g[name]).reshape(ora[name].shape), ora[name], name)
+
+
+def test_backward_walk_option_errors(srt):
+    sc = tiny_scene(62, 100)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+    o = torch.zeros((16, 3), device="cuda")
+    d = torch.tensor([[0.0, 0.0, 1.0]] * 16, device="cuda")
+    g = torch.ones((16, 3), device="cuda")
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_trace_backward(bvh, o, d, g, walk="wave")
+    assert e.value.code == 4
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_trace_backward(bvh, o, d, g, stack_limit=-1)
+    assert e.value.code == 1
