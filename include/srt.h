@@ -224,13 +224,16 @@ typedef struct {
  *                 seed and purpose are not used by the hash.
  * walk            0: automatic (2 where it is supported, else 1).
  *                 1: every lane walks the BVH for its own ray.
- *                 2: the 64 rays of a wave walk it together, one node at a
+ *                 2: the 64 rays of a wave (an 8x8 tile of an image launch,
+ *                 else 64 consecutive rays) walk it together, one node at a
  *                 time (a lane takes part in the nodes and leaves its own
- *                 walk would reach); for image launches (image_width > 0) of
- *                 closest-hit rays with Philox numbers and persistent = 0 in
- *                 the forward, image launches in the backward, else
- *                 SRT_ERR_UNSUPPORTED. Results do not depend on it (backward
- *                 gradients up to the order of FP32 atomic additions).     */
+ *                 walk would reach); forward: Philox numbers and
+ *                 persistent = 0; backward: image launches; else
+ *                 SRT_ERR_UNSUPPORTED. Automatic: image launches of
+ *                 closest-hit rays. Results do not depend on it, except
+ *                 which accepted id an any-hit ray reports and the order of
+ *                 the backward's FP32 atomic additions. In srt_trace_pathmix
+ *                 it applies to the camera rays.                           */
 typedef struct {
     uint64_t seed;
     int32_t spp;

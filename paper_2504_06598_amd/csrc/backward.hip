@@ -132,9 +132,10 @@ __device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, con
 }
 
 // WV: the 64 rays of each 8x8 tile re-traverse together (walk_wave; image
-// launches), else each lane walks for its own ray.
+// launches), else each lane walks for its own ray. Registers are capped for 3
+// waves per SIMD (a few spill to scratch; measured faster than 2 waves).
 template <int W, int N, bool COUNT, bool RB, int DM, bool WV>
-__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a, const void* __restrict__ nodes_v,
+__global__ __launch_bounds__(kBlock, 3) void k_backward(BwdArgs a, const void* __restrict__ nodes_v,
                                                      const Record* __restrict__ recs_r)
 {
     __shared__ int32_t lds[kLdsEntries * kBlock];
@@ -380,9 +381,10 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a, const void* __re
                 const float slack = DM == 0 ? 0.0f : dc.node_slack;
                 int res;
                 if constexpr (WV) {
-                    auto visit = [&](uint32_t ri, bool on) {
+                    auto visit = [&](uint32_t ri, bool on) -> bool {
                         const Record r = load_record(recs_r, ri);
                         if (on) visit_rec(r);
+                        return false;
                     };
                     res = walk_wave<W>(wnodes, rr, work, tcut, slack, wstk, a.max_steps, n_nodes,
                                        n_prims, visit);

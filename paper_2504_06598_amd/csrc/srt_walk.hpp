@@ -133,9 +133,11 @@ struct WaveStack {
 // (+inf entry depth for the lanes that missed them). Node and record
 // addresses are uniform, so they are fetched once per wave. visit(record
 // index, on) is called by every lane for each record of a reached leaf; only
-// lanes with `on` may act on it. Returns kWalkDone or kWalkOverflow
-// (wave-uniform).
-template <int W, class Visit>
+// lanes with `on` may act on it. ANY: visit returns true when the lane's ray
+// is resolved (any-hit), and the lane takes part in nothing after that; the
+// walk ends once every lane is resolved. Returns kWalkDone, kWalkStopped (ANY)
+// or kWalkOverflow (wave-uniform).
+template <int W, bool ANY = false, class Visit>
 __device__ __forceinline__ int walk_wave(const WideNode<W>* __restrict__ nodes, const Ray& rf,
                                          bool live, float& tcut, float slack, WaveStack& stk,
                                          int64_t max_steps, uint32_t& n_nodes,
@@ -192,10 +194,15 @@ __device__ __forceinline__ int walk_wave(const WideNode<W>* __restrict__ nodes, 
                 }
             } else {
                 const uint32_t first = leaf_first(node), count = leaf_count(node);
+                bool lon = on;
                 for (uint32_t i = 0; i < count; ++i) {
-                    n_prims += on ? 1u : 0u;
-                    visit(first + i, on);
+                    n_prims += lon ? 1u : 0u;
+                    if (visit(first + i, lon) && ANY) {
+                        lon = false;
+                        live = false;
+                    }
                 }
+                if (ANY && __ballot(live) == 0) return kWalkStopped;
             }
         }
         if (sp == 0) return kWalkDone;
@@ -430,10 +437,10 @@ __device__ __forceinline__ int resolve_samples_wave(const WideNode<W>* __restric
     FwdSamples<N> st;
     st.reset(n_act, (float)tmax);
     FwdCounts fcnt;
-    auto visit = [&](uint32_t ri, bool on) {
+    auto visit = [&](uint32_t ri, bool on) -> bool {
         const Record r = load_record(recs, ri);
-        if (on)
-            fwd_offer<N, false, false, DM>(st, r, ray, dc, tmin, tmax, ign, rid, s0, fc, fcnt);
+        if (on) fwd_offer<N, false, false, DM>(st, r, ray, dc, tmin, tmax, ign, rid, s0, fc, fcnt);
+        return false;
     };
     const float slack = DM == 0 ? 0.0f : dc.node_slack;
     const int res = walk_wave<W>(nodes, ray, live, st.tcut, slack, stk, max_steps, n_nodes,

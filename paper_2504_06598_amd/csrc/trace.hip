@@ -418,24 +418,25 @@ __global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
     }
 }
 
-// Wave-shared walks for image launches of closest-hit rays (same outputs as
-// k_trace, bit for bit): each wave is one workgroup and one 8x8 pixel tile,
-// and the 64 rays of the tile traverse the BVH together (walk_wave), so the
-// wave never diverges between node steps and leaf tests and reads each node
-// and record once instead of once per lane. Lanes keep their own samples,
-// depth cuts and candidate tests. When the shared stack would exceed
-// kWaveCap the whole tile is queued for the deep pass (k_trace with DEEP),
-// which reruns all passes of its rays.
+// Wave-shared walks (same outputs as k_trace, bit for bit, except which
+// accepted id an any-hit ray reports): each wave is one workgroup and takes
+// one 8x8 pixel tile of an image launch, else 64 consecutive rays, and its
+// rays traverse the BVH together (walk_wave), so the wave never diverges
+// between node steps and leaf tests and reads each node and record once
+// instead of once per lane. Lanes keep their own samples, depth cuts and
+// candidate tests. When the shared stack would exceed kWaveCap the whole
+// group is queued for the deep pass (k_trace with DEEP), which reruns all
+// passes of its rays.
 constexpr int kWaveCap = 48;
 
-template <int W, int N, bool COUNT, int DM>
+template <int W, int N, bool ANY, bool COUNT, int DM>
 __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __restrict__ nodes_v,
                                                    const Record* __restrict__ recs)
 {
     __shared__ float lds_t[kWaveCap * 64];
     const WideNode<W>* __restrict__ nodes = static_cast<const WideNode<W>*>(nodes_v);
     const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 64 + threadIdx.x;
-    const int64_t ray = tile_pixel(t, a.img_w, a.R / a.img_w);
+    const int64_t ray = a.img_w > 0 ? tile_pixel(t, a.img_w, a.R / a.img_w) : (t < a.R ? t : -1);
     const bool valid = ray >= 0;
     const int64_t rr = valid ? ray : 0;
     const float ox = a.o[3 * rr], oy = a.o[3 * rr + 1], oz = a.o[3 * rr + 2];
@@ -451,7 +452,7 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
     const ForwardCtx fc{recs, a.purpose, a.k0, a.k1};
     const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rd, a.r_max);
     const float slack = DM == 0 ? 0.0f : dc.node_slack;
-    const bool shade = a.rgb != nullptr;
+    const bool shade = a.rgb != nullptr && !ANY;
     const int cap = min(kWaveCap, a.stack_cap);
 
     Counts cnt;
@@ -464,16 +465,15 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
         FwdSamples<N> st;
         st.reset(n_act, tmax_f);
         FwdCounts fcnt;
-        auto visit = [&](uint32_t ri, bool on) {
+        auto visit = [&](uint32_t ri, bool on) -> bool {
             const Record r = load_record(recs, ri);
-            if (on)
-                fwd_offer<N, false, false, DM>(st, r, rd, dc, (double)tmin_f, (double)tmax_f, ign,
-                                               rid, s0, fc, fcnt);
+            return on && fwd_offer<N, ANY, false, DM>(st, r, rd, dc, (double)tmin_f,
+                                                      (double)tmax_f, ign, rid, s0, fc, fcnt);
         };
         uint32_t n_nodes = 0, n_prims = 0;
         WaveStack stk{lds_t, kWaveCap, nullptr, 0, cap};
-        const int res = walk_wave<W>(nodes, rd, live, st.tcut, slack, stk, a.max_steps, n_nodes,
-                                     n_prims, visit);
+        const int res = walk_wave<W, ANY>(nodes, rd, live, st.tcut, slack, stk, a.max_steps,
+                                          n_nodes, n_prims, visit);
         if (live) {
             ++cnt.trav;
             cnt.nodes += n_nodes;
@@ -500,7 +500,10 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
             const int64_t o = ray * a.spp + pass * N + k;
             if (a.hit_gid) a.hit_gid[o] = hit ? st.bg[k] : -1;
             if (a.hit_t) a.hit_t[o] = hit ? st.bt[k] : INFINITY;
-            if (shade) {
+            if (ANY) {
+                const float v = hit ? 0.0f : 1.0f;
+                acc0 += v; acc1 += v; acc2 += v;
+            } else if (shade) {
                 if (hit) {
                     const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, st.bg[k], Y));
                     acc0 += c.x; acc1 += c.y; acc2 += c.z;
@@ -537,31 +540,35 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
 using WaveFn = void (*)(TraceArgs, const void*, const Record*);
 
 template <int W, int DM>
-WaveFn wave_w(int N, bool count)
+WaveFn wave_w(int N, bool any, bool count)
 {
+    if (any) {
+        if (N != 1) return nullptr;
+        return count ? k_trace_wave<W, 1, true, true, DM> : k_trace_wave<W, 1, true, false, DM>;
+    }
     switch (N) {
-    case 1: return count ? k_trace_wave<W, 1, true, DM> : k_trace_wave<W, 1, false, DM>;
-    case 2: return count ? k_trace_wave<W, 2, true, DM> : k_trace_wave<W, 2, false, DM>;
-    case 4: return count ? k_trace_wave<W, 4, true, DM> : k_trace_wave<W, 4, false, DM>;
-    case 8: return count ? k_trace_wave<W, 8, true, DM> : k_trace_wave<W, 8, false, DM>;
+    case 1: return count ? k_trace_wave<W, 1, false, true, DM> : k_trace_wave<W, 1, false, false, DM>;
+    case 2: return count ? k_trace_wave<W, 2, false, true, DM> : k_trace_wave<W, 2, false, false, DM>;
+    case 4: return count ? k_trace_wave<W, 4, false, true, DM> : k_trace_wave<W, 4, false, false, DM>;
+    case 8: return count ? k_trace_wave<W, 8, false, true, DM> : k_trace_wave<W, 8, false, false, DM>;
     }
     return nullptr;
 }
 
 template <int DM>
-WaveFn wave_dm(int W, int N, bool count)
+WaveFn wave_dm(int W, int N, bool any, bool count)
 {
     switch (W) {
-    case 2: return wave_w<2, DM>(N, count);
-    case 4: return wave_w<4, DM>(N, count);
-    case 8: return wave_w<8, DM>(N, count);
+    case 2: return wave_w<2, DM>(N, any, count);
+    case 4: return wave_w<4, DM>(N, any, count);
+    case 8: return wave_w<8, DM>(N, any, count);
     }
     return nullptr;
 }
 
-WaveFn pick_wave(int W, int N, bool count, int depth_mode)
+WaveFn pick_wave(int W, int N, bool any, bool count, int depth_mode)
 {
-    return depth_mode == 0 ? wave_dm<0>(W, N, count) : wave_dm<1>(W, N, count);
+    return depth_mode == 0 ? wave_dm<0>(W, N, any, count) : wave_dm<1>(W, N, any, count);
 }
 
 using KernelFn = void (*)(TraceArgs);
@@ -724,12 +731,14 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
     // ctrl[0] overflow count, ctrl[1] rays lost, ctrl[2..3] the persistent work counter
     a.work = reinterpret_cast<unsigned long long*>(ws.ctrl + 2);
     a.threshold = o->refill_threshold > 0 ? o->refill_threshold : kDefaultRefill;
-    // wave-shared walks: image launches of closest-hit Philox rays, not persistent
-    const bool wave_ok = a.img_w > 0 && !o->any_hit && o->rng == 0 && !o->persistent;
+    // wave-shared walks: Philox rays, not persistent; chosen automatically for
+    // image launches of closest-hit rays
+    const bool wave_ok = o->rng == 0 && !o->persistent;
     if (o->walk == 2 && !wave_ok) return SRT_ERR_UNSUPPORTED;
     WaveFn wf = nullptr;
-    if (o->walk != 1 && wave_ok) {
-        wf = pick_wave(b->W, o->n_per_traversal, counters != nullptr, o->depth_mode);
+    if (o->walk == 2 || (o->walk == 0 && wave_ok && a.img_w > 0 && !o->any_hit)) {
+        wf = pick_wave(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr,
+                       o->depth_mode);
         if (!wf) return SRT_ERR_UNSUPPORTED;
     }
     KernelFn pf = nullptr;
@@ -746,7 +755,8 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
         if (pf) {
             hipLaunchKernelGGL(pf, dim3(blocks), dim3(kPersistBlock), 0, s, a);
         } else if (wf) {
-            const int64_t tiles = tile_threads(a.img_w, rays->count / a.img_w) / 64;
+            const int64_t tiles = a.img_w > 0 ? tile_threads(a.img_w, rays->count / a.img_w) / 64
+                                              : (rays->count + 63) / 64;
             hipLaunchKernelGGL(wf, dim3((unsigned)tiles), dim3(64), 0, s, a,
                                static_cast<const void*>(b->nodes), b->recs);
         } else {
@@ -1070,7 +1080,8 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
     so.n_per_traversal = 1;
     so.sample_offset = opts->sample_offset;
     so.image_width = 0;
-    so.walk = opts->walk == 1 ? 1 : 0;  // secondary rays are not an image
+    so.walk = opts->walk == 1 ? 1 : 0;  // secondary rays are not an image: automatic
+                                        // choice gives lane walks
     for (int pass = 0; pass < 2; ++pass) {
         const SecRays& sr = pass == 0 ? w.sh : w.mr;
         srt_rays rr{};
@@ -1086,8 +1097,9 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
         so.any_hit = pass == 0 ? 1 : 0;
         // shadow rays (walks of very uneven length: many end at a neighbour of
         // their start, the unoccluded ones cross the whole scene) always run on
-        // work-stealing waves, which measured faster for them; camera and
-        // mirror rays follow the caller's choice
+        // work-stealing waves, which measured faster for them than one lane per
+        // ray and than wave-shared walks (a shared walk lasts as long as its
+        // longest ray); camera and mirror rays follow the caller's choice
         so.persistent = pass == 0 && opts->rng == 0 ? 1 : opts->persistent;
         st = launch_trace(b, &rr, &so, nullptr, pass == 0 ? w.sh_hit : w.mr_hit, nullptr, counters,
                           w.trace_ws, s);

@@ -363,19 +363,20 @@ def test_persistent_equals_plain(srt, N, spp, any_hit, thr):
 
 
 def test_persistent_pathmix_equals_plain(srt):
-    say("path-tracer mix with persistent waves")
+    say("path-tracer mix: persistent waves and wave-shared walks change nothing")
     w = si.workload(3, small=True)
     cam = w["cameras"][0]
     bvh = srt.srt_build_bvh(device_scene(w["scene"]), 4, 2)
     outs = []
-    for pers in (False, True):
+    for pers, walk in ((False, "lane"), (True, "lane"), (False, "wave"), (False, "auto")):
         res = srt.srt_trace_pathmix(bvh, cam, seed=2, spp=8, n_per_traversal=4,
                                     light=si.LIGHT_POS, plane_y=si.PLANE_Y,
-                                    tmin_secondary=si.SECONDARY_TMIN, persistent=pers)
+                                    tmin_secondary=si.SECONDARY_TMIN, persistent=pers, walk=walk)
         torch.cuda.synchronize()
         outs.append({k: to_np(v) for k, v in res.items()})
-    for k in outs[0]:
-        np.testing.assert_array_equal(outs[0][k], outs[1][k], err_msg=k)
+    for o in outs[1:]:
+        for k in outs[0]:
+            np.testing.assert_array_equal(o[k], outs[0][k], err_msg=k)
 
 
 def test_persistent_option_errors(srt):
@@ -495,16 +496,21 @@ def test_hash_rng_unsupported_combinations(srt):
                                  None, ws.data_ptr(), ws.numel(), None) == 1
 
 
-@pytest.mark.parametrize("W,L,N,spp,mode,lim", [(4, 2, 4, 8, 0, 0), (2, 1, 1, 3, 0, 0),
-                                                (8, 4, 8, 8, 0, 0), (4, 4, 2, 6, 1, 0),
-                                                (4, 2, 4, 8, 0, 5), (8, 1, 4, 4, 1, 2)])
-def test_wave_walk_equals_lane_walk(srt, W, L, N, spp, mode, lim):
-    """The 64 rays of a tile walking the BVH together reach, per ray, the same
-    candidates as the ray's own walk: outputs equal bit for bit, with ragged
-    tiles, empty rays, ignored ids and (lim > 0) tiles whose shared stack
-    overflows into the deep pass."""
+@pytest.mark.parametrize("W,L,N,spp,mode,lim,image,any_hit", [
+    (4, 2, 4, 8, 0, 0, True, False), (2, 1, 1, 3, 0, 0, True, False),
+    (8, 4, 8, 8, 0, 0, True, False), (4, 4, 2, 6, 1, 0, True, False),
+    (4, 2, 4, 8, 0, 5, True, False), (8, 1, 4, 4, 1, 2, True, False),
+    (4, 2, 4, 8, 0, 0, False, False), (4, 2, 1, 1, 0, 0, False, True),
+    (4, 2, 1, 3, 0, 3, True, True), (2, 4, 1, 2, 1, 0, False, True)])
+def test_wave_walk_equals_lane_walk(srt, W, L, N, spp, mode, lim, image, any_hit):
+    """The 64 rays of a tile (or 64 consecutive rays) walking the BVH together
+    reach, per ray, the same candidates as the ray's own walk: outputs equal
+    bit for bit, with ragged tiles, empty rays, ignored ids and (lim > 0)
+    groups whose shared stack overflows into the deep pass. Any-hit rays: the
+    same visibility; the reported id is some accepted candidate, which may
+    differ with the visiting order."""
     say(f"wave-shared walk vs lane walk: W={W} L={L} N={N} spp={spp} depth mode {mode} "
-        f"stack limit {lim}")
+        f"stack limit {lim} image {image} any-hit {any_hit}")
     sc = tiny_scene(23, 3000, (0.02, 0.08))
     cam = si.look_at((0.1, 0.3, 2.8), (0, 0, 0), 37, 29)
     o, d = si.camera_rays(cam)
@@ -516,19 +522,30 @@ def test_wave_walk_equals_lane_walk(srt, W, L, N, spp, mode, lim):
     ign = rng.integers(-1, 3000, R).astype(np.int32)
     kw = dict(seed=13, spp=spp, n_per_traversal=N, bg=(0.2, 0.1, 0.7), tmin=_cuda(tmin),
               tmax=_cuda(tmax), ignore_gid=_cuda(ign), sample_offset=3, depth_mode=mode,
-              image_width=cam.width, stack_limit=lim)
+              image_width=cam.width if image else 0, stack_limit=lim, any_hit=any_hit)
     bvh = srt.srt_build_bvh(device_scene(sc), W, L)
     lane = _trace(srt, bvh, o, d, walk="lane", **kw)
     cnt = srt.new_counters()
     wave = _trace(srt, bvh, o, d, walk="wave", counters=cnt, **kw)
-    for k in ("hit_gid", "hit_t", "rgb"):
-        np.testing.assert_array_equal(wave[k], lane[k], err_msg=k)
+    if any_hit:
+        np.testing.assert_array_equal(wave["rgb"], lane["rgb"])
+        np.testing.assert_array_equal(wave["hit_gid"] >= 0, lane["hit_gid"] >= 0)
+        hit = wave["hit_gid"] >= 0
+        t = wave["hit_t"]
+        assert np.all(hit == np.isfinite(t))
+        lo = np.repeat(tmin[:, None], spp, 1)
+        hi = np.repeat(tmax[:, None], spp, 1)
+        assert np.all((t[hit] > lo[hit]) & (t[hit] < hi[hit]))
+        assert np.all(wave["hit_gid"][hit] != np.repeat(ign[:, None], spp, 1)[hit])
+    else:
+        for k in ("hit_gid", "hit_t", "rgb"):
+            np.testing.assert_array_equal(wave[k], lane[k], err_msg=k)
     c = srt.counters_dict(cnt)
     assert c["lost"] == 0
     assert c["ray_samples"] == int((tmax > tmin).sum()) * spp
     if lim:
         assert c["deep"] > 0
-    if (W, L, N, mode, lim) == (4, 2, 4, 0, 0):
+    if (W, L, N, mode, lim, image) == (4, 2, 4, 0, 0, True):
         rays = oracle.Rays(o, d, tmin, tmax, ign, sample_base=np.full(R, 3, np.uint32))
         ora = oracle.trace(oracle.Records(sc), rays, spp=spp, seed=13)
         compare_ids(wave["hit_gid"], ora["hit_gid"], ora["flags"])
@@ -562,7 +579,7 @@ def test_walk_option_errors(srt):
     bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
     o = torch.zeros((16, 3), device="cuda")
     d = torch.tensor([[0.0, 0.0, 1.0]] * 16, device="cuda")
-    for kw in (dict(), dict(image_width=4, any_hit=True), dict(image_width=4, persistent=True),
+    for kw in (dict(image_width=4, persistent=True), dict(persistent=True),
                dict(image_width=4, rng="hash")):
         with pytest.raises(srt.SrtError) as e:
             srt.srt_trace_forward(bvh, o, d, walk="wave", **kw)
