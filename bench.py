@@ -228,7 +228,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.width, args.leaf),
-            "kernel": f"k_trace<W={args.width},N={N}> camera rays",
+            "kernel": f"k_trace_wave<W={args.width},N={N}> camera rays (8x8 tiles, wave-shared walks)",
             "kernel_ms": round(avg_ms, 3),
             "bytes_per_launch": int(bytes_per_launch),
             "per_ray_sample": {"nodes": round(kc["nodes"] / kc["ray_samples"] * N, 2),
@@ -356,7 +356,7 @@ def measured_traffic(width, leaf, root=ROOT):
     counters read on a copy of known size); None when the kernel's sources or
     the tree shape differ from those that were measured."""
     import hashlib
-    path = os.path.join(root, "profiles", "k_trace_camera_1M_pmc.json")
+    path = os.path.join(root, "profiles", "k_trace_wave_camera_1M_pmc.json")
     try:
         rec = json.load(open(path))
         h = hashlib.sha1()

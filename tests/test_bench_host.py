@@ -13,7 +13,7 @@ def _setup(tmp_path, width=4, leaf=2):
     (tmp_path / "profiles").mkdir()
     rec = {"sources": ["k.hip"], "sources_sha1": hashlib.sha1(b"kernel v1").hexdigest(),
            "width": width, "leaf_size": leaf, "hbm_bytes_per_launch": 1234}
-    (tmp_path / "profiles" / "k_trace_camera_1M_pmc.json").write_text(json.dumps(rec))
+    (tmp_path / "profiles" / "k_trace_wave_camera_1M_pmc.json").write_text(json.dumps(rec))
     return src
 
 
@@ -31,5 +31,5 @@ def test_traffic_null_after_a_source_change(tmp_path):
 def test_traffic_null_for_another_tree_shape_or_no_record(tmp_path):
     _setup(tmp_path)
     assert bench.measured_traffic(4, 4, root=str(tmp_path)) is None
-    os.remove(tmp_path / "profiles" / "k_trace_camera_1M_pmc.json")
+    os.remove(tmp_path / "profiles" / "k_trace_wave_camera_1M_pmc.json")
     assert bench.measured_traffic(4, 2, root=str(tmp_path)) is None
