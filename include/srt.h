@@ -370,9 +370,10 @@ size_t srt_pathmix_workspace_size(const srt_bvh* bvh, const srt_camera* cam, int
  * 0 occluded, 255 no shadow ray) [H*W,spp], mirror_gid (-2 no mirror ray,
  * -1 miss) [H*W,spp]: device or null. counters as srt_trace_forward; its
  * SRT_CNT_RAY_SAMPLES entry counts camera samples plus secondary rays.
- * opts->any_hit must be 0. Camera rays are traced as an image (8x8 tiles);
- * the any-hit shadow rays always run on work-stealing waves (see
- * srt_trace_opts.persistent); camera and mirror rays follow opts->persistent.
+ * opts->any_hit must be 0. Camera rays are traced as an image (8x8 tiles,
+ * wave-shared walks unless opts->walk is 1); the any-hit shadow rays always
+ * run on work-stealing waves (see srt_trace_opts.persistent); camera and
+ * mirror rays follow opts->persistent.
  * Errors: INVALID_ARG, WORKSPACE, HIP. */
 srt_status srt_trace_pathmix(const srt_bvh* bvh, const srt_camera* cam, uint32_t ray_id_base,
                              const srt_trace_opts* opts, const srt_pathmix_opts* pm,
@@ -400,7 +401,12 @@ typedef struct {
 /* Launch shape. persistent = 1: the work-stealing kernel (a grid of
  * waves_per_cu one-wave workgroups per compute unit; a wave claims new items
  * once at least refill_threshold of its 64 lanes are idle); persistent = 0:
- * the plain kernel, one lane per ray. */
+ * the plain kernel, one lane per ray. With opts->walk != 1 the views' pixels
+ * use wave-shared walks of 8x8 tiles instead: persistent, a wave first
+ * refills its lanes with extra rays while any are left, then claims one
+ * (tile, pass) group of 64 items per atomic; plain, one wave per tile. The extra rays
+ * always walk one lane per ray. Results do not depend on the choice (colours
+ * up to the order of the persistent kernel's FP32 atomic additions). */
 typedef struct {
     int32_t persistent;
     int32_t refill_threshold;  /* 1..64 */

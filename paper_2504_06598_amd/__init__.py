@@ -404,7 +404,10 @@ def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_d
                           extra_spp=1, ray_id_base=0, seed=0, n_per_traversal=4,
                           sample_offset=0, bg=(0.0, 0.0, 0.0), stack_limit=0, persistent=True,
                           refill_threshold=16, waves_per_cu=8, depth_mode=0,
-                          depth_axis=(0.0, 0.0, 0.0), rng="philox") -> BatchPlan:
+                          depth_axis=(0.0, 0.0, 0.0), rng="philox", walk="auto") -> BatchPlan:
+    """Plan of the batched forward (views with their spp, plus extra rays).
+    walk: "auto"/"wave" trace the views' 8x8 tiles as wave-shared walks,
+    "lane" one lane per pixel; extra rays always walk one lane per ray."""
     lib = _lib.load()
     nv = len(cameras)
     cams = (_lib.SrtCamera * max(nv, 1))(*[_camera(c) for c in cameras])
@@ -415,7 +418,7 @@ def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_d
     batch = _lib.SrtBatch(nv, C.cast(cams, C.c_void_p), C.cast(spp_arr, C.c_void_p), extra,
                           int(extra_spp) if n_extra else 0, int(ray_id_base))
     opts = _opts(seed, 1, n_per_traversal, sample_offset, bg, False, stack_limit, depth_mode,
-                 depth_axis, rng=rng)
+                 depth_axis, rng=rng, walk=walk)
     tun = _lib.SrtTuning(1 if persistent else 0, int(refill_threshold), int(waves_per_cu))
     h = C.c_void_p()
     _lib.check("srt_batch_plan_create", lib.srt_batch_plan_create(

@@ -16,7 +16,12 @@
 //    out), so lanes whose rays finish early are refilled instead of idling
 //    until the longest ray of the wave is done. Colour accumulates into the
 //    image with FP32 atomics (each item adds its samples' colours / spp).
-// Both queue items whose on-chip stack overflows; a deep pass with a
+// With wave-shared walks (srt_trace_opts.walk != 1) the camera pixels go to
+// tile kernels instead: plain, one wave per 8x8 tile looping over its
+// passes; persistent, each wave first joins the lane refilling for the extra
+// rays, then claims one (tile, pass) group of 64 items per atomic on a second
+// counter and walks it with its 64 rays together (walk_wave).
+// All queue items whose on-chip stack overflows; a deep pass with a
 // global-memory stack reruns them (an item contributes only once complete).
 #include <algorithm>
 #include <climits>
@@ -47,6 +52,9 @@ struct Segment {
 };
 
 struct BatchArgs {
+    int64_t first;        // plain: enumerated index of lane 0 of the grid
+    int64_t n_cam;        // camera items (persistent) or camera lanes (plain), a multiple of 64
+    unsigned long long* groups;  // persistent wave kernel: next (tile, pass) group
     const void* nodes;
     const Record* recs;
     const float* sh;
@@ -134,6 +142,10 @@ __device__ __forceinline__ BRay seg_ray(const BatchArgs& a, const Segment& S, in
 {
     BRay b;
     b.spp = S.spp;
+    for (int i = 0; i < 3; ++i) {
+        b.o[i] = 0.0f;
+        b.d[i] = 0.0f;
+    }
     if (S.width > 0) {
         // 8x8 tiles, row-major tiles; pixels outside the image are not rays
         const int64_t tile = r / (kTile * kTile);
@@ -151,16 +163,18 @@ __device__ __forceinline__ BRay seg_ray(const BatchArgs& a, const Segment& S, in
         if (b.valid) cam_ray(S.cam, x, y, b.o, b.d);
     } else {
         b.valid = r < S.rays;
+        const int64_t rr = b.valid ? r : 0;
         b.row = S.ray_begin + r;
         b.sample0 = S.sample_begin + r * S.spp;
-        b.rid = a.erid ? a.erid[r] : S.ray_id_base + (uint32_t)r;
+        b.rid = a.erid ? a.erid[rr] : S.ray_id_base + (uint32_t)r;
         b.purpose = a.epurpose;
-        b.tmin = a.etmin ? a.etmin[r] : 0.0f;
-        b.tmax = a.etmax ? a.etmax[r] : INFINITY;
-        for (int i = 0; i < 3; ++i) {
-            b.o[i] = a.eo[3 * r + i];
-            b.d[i] = a.ed[3 * r + i];
-        }
+        b.tmin = a.etmin ? a.etmin[rr] : 0.0f;
+        b.tmax = a.etmax ? a.etmax[rr] : INFINITY;
+        if (b.valid)
+            for (int i = 0; i < 3; ++i) {
+                b.o[i] = a.eo[3 * r + i];
+                b.d[i] = a.ed[3 * r + i];
+            }
     }
     return b;
 }
@@ -227,6 +241,63 @@ __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int 
     return true;
 }
 
+// run_pass over a walk shared by the wave's 64 rays (all lanes call it, with
+// the same pass; lanes whose ray is not valid take part without samples).
+// Returns false (wave-uniform) on a stack overflow; nothing was written then.
+template <int W, int N, int DM>
+__device__ __forceinline__ bool wave_pass(const BatchArgs& a, const WideNode<W>* __restrict__ nodes,
+                                          const Record* __restrict__ recs, const BRay& b, int pass,
+                                          WaveStack& stk, LaneCounts& cnt, bool atomic,
+                                          float acc[3])
+{
+    const bool live = b.valid && b.tmax > b.tmin;
+    const int n_act = live ? min(N, b.spp - pass * N) : 0;
+    const Ray ray = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
+    const ForwardCtx fc{recs, b.purpose, a.k0, a.k1};
+    const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, ray, a.r_max);
+    float bt[N];
+    int32_t bg[N];
+    uint32_t n_nodes = 0, n_prims = 0;
+    const int res = resolve_samples_wave<W, N, DM>(
+        nodes, recs, fc, dc, ray, live, (double)b.tmin, (double)b.tmax, -1, b.rid,
+        a.soff + (uint32_t)(pass * N), n_act, stk, a.max_steps, bt, bg, n_nodes, n_prims,
+        cnt.cands, cnt.philox);
+    if (live) {
+        ++cnt.trav;
+        cnt.nodes += n_nodes;
+        cnt.prims += n_prims;
+    }
+    if (res == kWalkOverflow) return false;
+    if (!b.valid) return true;
+    float Y[16];
+    const float n = sqrtf(b.d[0] * b.d[0] + b.d[1] * b.d[1] + b.d[2] * b.d[2]);
+    sh_eval(a.deg, b.d[0] / n, b.d[1] / n, b.d[2] / n, Y);
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    const int n_out = min(N, b.spp - pass * N);  // an empty ray's samples are misses
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if (k >= n_out) continue;
+        const bool hit = k < n_act && bg[k] != 0x7FFFFFFF;
+        if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? bg[k] : -1;
+        if (hit) {
+            const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, bg[k], Y));
+            c0 += c.x; c1 += c.y; c2 += c.z;
+        } else {
+            c0 += a.bg[0]; c1 += a.bg[1]; c2 += a.bg[2];
+        }
+    }
+    const float w = 1.0f / (float)b.spp;
+    if (atomic) {
+        cnt.samples += (uint32_t)n_out;
+        atomicAdd(a.rgb + 3 * b.row, c0 * w);
+        atomicAdd(a.rgb + 3 * b.row + 1, c1 * w);
+        atomicAdd(a.rgb + 3 * b.row + 2, c2 * w);
+    } else {
+        acc[0] += c0; acc[1] += c1; acc[2] += c2;
+    }
+    return true;
+}
+
 template <bool COUNT>
 __device__ __forceinline__ void flush_counts(const BatchArgs& a, const LaneCounts& c, uint32_t deep,
                                              uint32_t lost)
@@ -249,7 +320,7 @@ template <int W, int N, bool COUNT, int DM>
 __global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
 {
     __shared__ int32_t lds[32 * kPlainBlock];
-    const int64_t r = blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
+    const int64_t r = a.first + blockIdx.x * (int64_t)kPlainBlock + threadIdx.x;
     FlatStack stk{lds + threadIdx.x, kPlainBlock, min(32, a.stack_cap)};
     LaneCounts cnt;
     if (r < a.n_items) {
@@ -329,14 +400,14 @@ __device__ __forceinline__ void decode_item(const BatchArgs& a, int64_t item, in
     }
 }
 
+// The lane-refilling loop over items numbered from the work counter's
+// starting value up to n_items; lds holds 32 stack entries per lane.
 template <int W, int N, bool COUNT, int DM>
-__global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
+__device__ __forceinline__ void persist_lanes(const BatchArgs& a, int32_t* lds, LaneCounts& cnt)
 {
-    __shared__ int32_t lds[32 * kPersistBlock];
     const int lane = threadIdx.x;
     const int cap = min(32, a.stack_cap);
     const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
-    LaneCounts cnt;
 
     // lane state
     bool active = false;
@@ -472,6 +543,93 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
             active = false;
         }
     }
+}
+
+template <int W, int N, bool COUNT, int DM>
+__global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
+{
+    __shared__ int32_t lds[32 * kPersistBlock];
+    LaneCounts cnt;
+    persist_lanes<W, N, COUNT, DM>(a, lds, cnt);
+    flush_counts<COUNT>(a, cnt, 0, 0);
+}
+
+// Wave-uniform copy of a value every lane holds.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr int kWaveCap = 48;  // wave-shared stack entries (12 KB of LDS per wave)
+
+// Persistent with wave-shared walks: first the lane refilling over the extra
+// rays (whose counter the host starts at n_cam; their walks are long and
+// uneven, so they start first and the camera groups fill in around them),
+// then camera (tile, pass) groups, one per atomic. The LDS holds the lane
+// stacks, then the wave stack.
+template <int W, int N, bool COUNT, int DM>
+__global__ __launch_bounds__(kPersistBlock) void k_persistent_wave(BatchArgs a,
+                                                                   const void* __restrict__ nodes_v,
+                                                                   const Record* __restrict__ recs)
+{
+    __shared__ float lds[kWaveCap * 64];
+    static_assert(kWaveCap * 64 >= 32 * kPersistBlock, "lane stacks fit the same LDS");
+    const WideNode<W>* __restrict__ nodes = static_cast<const WideNode<W>*>(nodes_v);
+    const int lane = threadIdx.x;
+    LaneCounts cnt;
+    persist_lanes<W, N, COUNT, DM>(a, reinterpret_cast<int32_t*>(lds), cnt);
+    WaveStack stk{lds, kWaveCap, nullptr, 0, min(kWaveCap, a.stack_cap)};
+    for (;;) {
+        unsigned long long g = 0;
+        if (lane == 0) g = atomicAdd(a.groups, 1ull);
+        g = uniform_u64(__shfl(g, 0, 64));
+        const int64_t it0 = (int64_t)g * 64;
+        if (it0 >= a.n_cam) break;
+        const int64_t item = it0 + lane;
+        int32_t seg, pass;
+        int64_t ray;
+        decode_item(a, item, seg, ray, pass);
+        const BRay b = seg_ray(a, a.segs[seg], ray);
+        if (!wave_pass<W, N, DM>(a, nodes, recs, b, pass, stk, cnt, true, nullptr) && b.valid) {
+            const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+            a.ovf_list[slot] = (uint64_t)item;
+        }
+    }
+    flush_counts<COUNT>(a, cnt, 0, 0);
+}
+
+// Plain with wave-shared walks: one wave per 8x8 tile of a view, over all
+// passes of its pixels (the camera lanes [0, n_cam) of the plain numbering).
+template <int W, int N, bool COUNT, int DM>
+__global__ __launch_bounds__(64) void k_plain_wave(BatchArgs a, const void* __restrict__ nodes_v,
+                                                   const Record* __restrict__ recs)
+{
+    __shared__ float lds[kWaveCap * 64];
+    const WideNode<W>* __restrict__ nodes = static_cast<const WideNode<W>*>(nodes_v);
+    const int64_t r = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 64 + threadIdx.x;
+    const Segment& S = a.segs[find_seg(a, r, false)];
+    const BRay b = seg_ray(a, S, r - S.enum_begin);
+    WaveStack stk{lds, kWaveCap, nullptr, 0, min(kWaveCap, a.stack_cap)};
+    LaneCounts cnt;
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    bool ok = true;
+    const int passes = __builtin_amdgcn_readfirstlane(S.passes);  // one view per tile
+    for (int pass = 0; pass < passes && ok; ++pass)
+        ok = wave_pass<W, N, DM>(a, nodes, recs, b, pass, stk, cnt, false, acc);
+    if (b.valid) {
+        if (ok) {
+            cnt.samples += (uint32_t)b.spp;
+            const float w = 1.0f / (float)b.spp;
+            a.rgb[3 * b.row] = acc[0] * w;
+            a.rgb[3 * b.row + 1] = acc[1] * w;
+            a.rgb[3 * b.row + 2] = acc[2] * w;
+        } else {
+            const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+            a.ovf_list[slot] = (uint64_t)r;
+        }
+    }
     flush_counts<COUNT>(a, cnt, 0, 0);
 }
 
@@ -505,40 +663,51 @@ __global__ void k_zero_f32(float* p, int64_t n)
         p[i] = 0.0f;
 }
 
-__global__ void k_reset(unsigned long long* work, uint32_t* ctrl)
+// work[0]: next item of the lane refilling (from `start`); work[1]: next
+// camera group of the persistent wave kernel.
+__global__ void k_reset(unsigned long long* work, uint32_t* ctrl, unsigned long long start)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *work = 0ull;
+        work[0] = start;
+        work[1] = 0ull;
         ctrl[0] = 0u;
         ctrl[1] = 0u;
     }
 }
 
 using BatchFn = void (*)(BatchArgs);
+using WaveBatchFn = void (*)(BatchArgs, const void*, const Record*);
+
+struct Kernels {
+    BatchFn plain, plain_deep, persistent, persistent_deep;
+    WaveBatchFn plain_wave, persistent_wave;
+};
 
 template <int W, int N, bool C, int DM>
-void pick4(BatchFn k[4])
+void pick_all(Kernels& k)
 {
-    k[0] = k_plain<W, N, C, DM>;
-    k[1] = k_plain_deep<W, N, C, DM>;
-    k[2] = k_persistent<W, N, C, DM>;
-    k[3] = k_persistent_deep<W, N, C, DM>;
+    k.plain = k_plain<W, N, C, DM>;
+    k.plain_deep = k_plain_deep<W, N, C, DM>;
+    k.persistent = k_persistent<W, N, C, DM>;
+    k.persistent_deep = k_persistent_deep<W, N, C, DM>;
+    k.plain_wave = k_plain_wave<W, N, C, DM>;
+    k.persistent_wave = k_persistent_wave<W, N, C, DM>;
 }
 
 template <int W, bool C, int DM>
-bool pick_w(int N, BatchFn k[4])
+bool pick_w(int N, Kernels& k)
 {
     switch (N) {
-    case 1: pick4<W, 1, C, DM>(k); return true;
-    case 2: pick4<W, 2, C, DM>(k); return true;
-    case 4: pick4<W, 4, C, DM>(k); return true;
-    case 8: pick4<W, 8, C, DM>(k); return true;
+    case 1: pick_all<W, 1, C, DM>(k); return true;
+    case 2: pick_all<W, 2, C, DM>(k); return true;
+    case 4: pick_all<W, 4, C, DM>(k); return true;
+    case 8: pick_all<W, 8, C, DM>(k); return true;
     }
     return false;
 }
 
 template <int DM>
-bool pick_dm(int W, int N, bool count, BatchFn k[4])
+bool pick_dm(int W, int N, bool count, Kernels& k)
 {
     switch (W) {
     case 2: return count ? pick_w<2, true, DM>(N, k) : pick_w<2, false, DM>(N, k);
@@ -549,7 +718,7 @@ bool pick_dm(int W, int N, bool count, BatchFn k[4])
 }
 
 // kernels with the depth mode fixed at compile time (fewer registers)
-bool pick(int W, int N, bool count, int depth_mode, BatchFn k[4])
+bool pick(int W, int N, bool count, int depth_mode, Kernels& k)
 {
     return depth_mode == 0 ? pick_dm<0>(W, N, count, k) : pick_dm<1>(W, N, count, k);
 }
@@ -563,6 +732,7 @@ struct srt_batch_plan {
     std::vector<Segment> segs;
     Segment* d_segs = nullptr;
     int64_t n_items = 0, n_rays = 0, n_samples = 0, rows = 0;
+    int64_t n_cam_items = 0, n_cam_rays = 0;  // camera part (multiples of 64)
     srt_rays extra{};
     unsigned long long* work = nullptr;
     uint32_t* ctrl = nullptr;
@@ -597,9 +767,10 @@ void plan_free(srt_batch_plan* p)
 srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* counters, hipStream_t s)
 {
     const srt_bvh* b = p->bvh;
-    BatchFn k[4];
+    Kernels k{};
     if (!pick(b->W, p->opts.n_per_traversal, counters != nullptr, p->opts.depth_mode, k))
         return SRT_ERR_UNSUPPORTED;
+    const bool wave = p->opts.walk != 1 && p->n_cam_rays > 0;
     BatchArgs a{};
     a.nodes = b->nodes;
     a.recs = b->recs;
@@ -632,26 +803,44 @@ srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* count
     a.depth_mode = p->opts.depth_mode;
     for (int i = 0; i < 3; ++i) a.depth_axis[i] = p->opts.depth_axis[i];
     a.r_max = b->r_max;
-    k_reset<<<1, 64, 0, s>>>(p->work, p->ctrl);
-    SRT_HIP_TRY(hipGetLastError());
+    a.groups = p->work + 1;
     const bool persistent = p->tuning.persistent != 0;
+    a.n_cam = wave ? (persistent ? p->n_cam_items : p->n_cam_rays) : 0;
+    k_reset<<<1, 64, 0, s>>>(p->work, p->ctrl, (unsigned long long)a.n_cam);
+    SRT_HIP_TRY(hipGetLastError());
+    const void* nodes = b->nodes;
+    const Record* recs = b->recs;
     if (persistent) {
         k_zero_f32<<<1024, 256, 0, s>>>(rgb, 3 * p->rows);
         SRT_HIP_TRY(hipGetLastError());
         a.n_items = p->n_items;
         const int wpc = std::max(1, p->tuning.waves_per_cu);
-        hipLaunchKernelGGL(k[2], dim3((unsigned)(p->n_cu * wpc)), dim3(kPersistBlock), 0, s, a);
+        if (wave)
+            hipLaunchKernelGGL(k.persistent_wave, dim3((unsigned)(p->n_cu * wpc)),
+                               dim3(kPersistBlock), 0, s, a, nodes, recs);
+        else
+            hipLaunchKernelGGL(k.persistent, dim3((unsigned)(p->n_cu * wpc)), dim3(kPersistBlock),
+                               0, s, a);
         SRT_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k[3], dim3(kDeepThreads / kPlainBlock), dim3(kPlainBlock), 0, s, a);
+        hipLaunchKernelGGL(k.persistent_deep, dim3(kDeepThreads / kPlainBlock), dim3(kPlainBlock),
+                           0, s, a);
         SRT_HIP_TRY(hipGetLastError());
     } else {
         a.n_items = p->n_rays;
-        if (p->n_rays > 0) {
-            hipLaunchKernelGGL(k[0], dim3((unsigned)((p->n_rays + kPlainBlock - 1) / kPlainBlock)),
+        if (wave) {
+            hipLaunchKernelGGL(k.plain_wave, dim3((unsigned)(p->n_cam_rays / 64)), dim3(64), 0, s,
+                               a, nodes, recs);
+            SRT_HIP_TRY(hipGetLastError());
+        }
+        a.first = a.n_cam;
+        const int64_t lanes = p->n_rays - a.first;
+        if (lanes > 0) {
+            hipLaunchKernelGGL(k.plain, dim3((unsigned)((lanes + kPlainBlock - 1) / kPlainBlock)),
                                dim3(kPlainBlock), 0, s, a);
             SRT_HIP_TRY(hipGetLastError());
         }
-        hipLaunchKernelGGL(k[1], dim3(kDeepThreads / kPlainBlock), dim3(kPlainBlock), 0, s, a);
+        hipLaunchKernelGGL(k.plain_deep, dim3(kDeepThreads / kPlainBlock), dim3(kPlainBlock), 0, s,
+                           a);
         SRT_HIP_TRY(hipGetLastError());
     }
     return SRT_OK;
@@ -673,6 +862,7 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
     if (opts->depth_mode != 0 && opts->depth_mode != 1) return SRT_ERR_INVALID_ARG;
     if (opts->rng != 0 && opts->rng != 1) return SRT_ERR_INVALID_ARG;
     if (opts->rng == 1) return SRT_ERR_UNSUPPORTED;  // batched plans draw Philox numbers
+    if (opts->walk < 0 || opts->walk > 2) return SRT_ERR_INVALID_ARG;
     if (batch->num_views < 0 || (batch->num_views > 0 && (!batch->cameras || !batch->spp)))
         return SRT_ERR_INVALID_ARG;
     if (batch->extra.count < 0 || batch->extra_spp < 0) return SRT_ERR_INVALID_ARG;
@@ -714,6 +904,8 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
         rays += en;
         p->segs.push_back(S);
     }
+    p->n_cam_items = items;
+    p->n_cam_rays = rays;
     if (batch->extra.count > 0) {
         Segment S{};
         S.width = 0;
@@ -746,7 +938,7 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
     p->n_cu = prop.multiProcessorCount;
     p->ovf_cap = std::max<int64_t>(items, rays) + 1;
     if (hipMalloc(&p->d_segs, sizeof(Segment) * std::max<size_t>(1, p->segs.size())) != hipSuccess ||
-        hipMalloc(&p->work, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&p->work, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&p->ctrl, 4 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&p->ovf, sizeof(uint64_t) * (size_t)p->ovf_cap) != hipSuccess ||
         hipMalloc(&p->deep_stack, sizeof(int32_t) * (size_t)kDeepThreads * (size_t)deep_stack_cap(b)) !=

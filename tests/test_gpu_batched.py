@@ -73,14 +73,16 @@ def _reference(srt, s):
     return np.concatenate(rgbs), np.concatenate(hits)
 
 
-def test_plain_and_persistent_match_trace_forward(srt, setup):
+@pytest.mark.parametrize("walk", ["wave", "lane"])
+def test_plain_and_persistent_match_trace_forward(srt, setup, walk):
     s = setup
-    say("batched: plain vs persistent vs srt_trace_forward")
+    say(f"batched: plain vs persistent vs srt_trace_forward, {walk} walks for the views")
     ref_rgb, ref_hits = _reference(srt, s)
     for persistent, thr, wpc in [(False, 16, 8), (True, 16, 8), (True, 1, 2), (True, 64, 16),
                                  (True, 40, 5)]:
         say(f"  persistent={persistent} threshold={thr} waves/CU={wpc}")
-        plan = _plan(srt, s, persistent=persistent, refill_threshold=thr, waves_per_cu=wpc)
+        plan = _plan(srt, s, persistent=persistent, refill_threshold=thr, waves_per_cu=wpc,
+                     walk=walk)
         rgb, hits, cnt = _run(plan)
         assert np.array_equal(hits, ref_hits)
         np.testing.assert_allclose(rgb, ref_rgb, atol=2e-6, rtol=1e-5)
@@ -147,11 +149,12 @@ def test_deep_stack_and_widths(srt, setup):
     _, ref_hits, _ = _run(base)
     for lim in (1, 3):
         for persistent in (False, True):
-            plan = _plan(srt, s, persistent=persistent, stack_limit=lim)
-            _, hits, cnt = _run(plan)
-            assert np.array_equal(hits, ref_hits)
-            assert cnt[5] > 0 and cnt[7] == 0
-            assert cnt[6] == plan.samples  # rerun rays and items are counted once
+            for walk in ("wave", "lane"):
+                plan = _plan(srt, s, persistent=persistent, stack_limit=lim, walk=walk)
+                _, hits, cnt = _run(plan)
+                assert np.array_equal(hits, ref_hits)
+                assert cnt[5] > 0 and cnt[7] == 0
+                assert cnt[6] == plan.samples  # rerun rays and items are counted once
     for W, L in [(2, 1), (8, 8), (8, 2)]:
         bvh = srt.srt_build_bvh(s["dsc"], W, L)
         plan = _plan(srt, s, bvh=bvh, persistent=True)
