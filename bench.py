@@ -2,9 +2,9 @@
 
 A step is one pass of the hot path over one batch of synthetic input:
   1. canonical records + BVH build of a 1M-Gaussian scene (four shells),
-  2. forward: the path-tracer mix at 1920x1080, 16 spp, N = 4 samples per
-     traversal: camera rays, one any-hit shadow ray per shading point and a
-     mirror ray per ground-plane point, all through the same traversal kernel;
+  2. forward: the path-tracer mix at 1920x1080, 16 spp, N = 8 samples per
+     traversal (two passes per pixel): camera rays, one any-hit shadow ray per
+     shading point and a mirror ray per ground-plane point;
   3. forward + backward of an L2 loss on 8 views of 800x800 at 4 spp on a
      ring of radius 3 against targets rendered (once, before timing) from the
      scene with perturbed means and opacity logits.
@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--width", type=int, default=4)
     p.add_argument("--leaf", type=int, default=2)
-    p.add_argument("--n-per-traversal", type=int, default=4)
+    p.add_argument("--n-per-traversal", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--overlap", action=argparse.BooleanOptionalAction, default=True,
                    help="run the ring views' forward + backward on a second stream")
@@ -228,7 +228,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.width, args.leaf),
-            "kernel": f"k_trace_wave<W={args.width},N={N}> camera rays (8x8 tiles, wave-shared walks)",
+            "kernel": f"k_trace_wave<W={args.width},N={N}> camera rays (wave-shared walks of image tiles)",
             "kernel_ms": round(avg_ms, 3),
             "bytes_per_launch": int(bytes_per_launch),
             "per_ray_sample": {"nodes": round(kc["nodes"] / kc["ray_samples"] * N, 2),

@@ -3,7 +3,8 @@
 // One lane per ray. For an image launch of closest-hit rays the 64 rays of
 // an 8x8 pixel tile walk the BVH together (k_trace_wave: one shared stack,
 // node and record fetches once per wave, each lane acting only on the nodes
-// and Gaussians its own walk would reach). Otherwise each lane walks the
+// and Gaussians its own walk would reach); when a pixel needs 2 or 4 passes,
+// each pass gets its own lane and a wave covers 8x4 or 4x4 pixels. Otherwise each lane walks the
 // W-wide BVH with a per-lane stack in LDS (stride = block size, so the 64
 // lanes of a wave hit 64 distinct banks whatever their depths), visiting hit
 // children near to far. Each Gaussian of
@@ -67,6 +68,7 @@ struct TraceArgs {
     int32_t img_w;  // > 0: rays are a row-major image of this width, traced in tiles
     unsigned long long* work;  // persistent launch: next ray (item) to hand out
     int32_t threshold;         // persistent launch: idle lanes that trigger a refill
+    int32_t phases;            // wave-shared image launch: lanes per pixel (1, 2 or 4)
 };
 
 struct Counts {
@@ -429,14 +431,54 @@ __global__ __launch_bounds__(kPersistBlock) void k_trace_persist(TraceArgs a)
 // passes of its rays.
 constexpr int kWaveCap = 48;
 
-template <int W, int N, bool ANY, bool COUNT, int DM>
+// Image launches whose rays need Q = 2 or 4 passes give each pixel Q lanes,
+// lane q running pass q, so a wave covers 64 / Q pixels (8x4 or 4x4): fewer
+// distinct rays share each walk. Thread t -> pixel of a w x h image (or -1)
+// and its phase q.
+__host__ __device__ __forceinline__ void wave_tile_dims(int32_t Q, int32_t& tw, int32_t& th)
+{
+    tw = Q == 4 ? 4 : 8;
+    th = 64 / Q / tw;
+}
+
+__host__ __device__ __forceinline__ int64_t wave_tiles(int32_t w, int64_t h, int32_t Q)
+{
+    int32_t tw, th;
+    wave_tile_dims(Q, tw, th);
+    return (int64_t)((w + tw - 1) / tw) * ((h + th - 1) / th);
+}
+
+__device__ __forceinline__ int64_t wave_pixel(int64_t t, int32_t w, int64_t h, int32_t Q,
+                                              int32_t& phase)
+{
+    int32_t tw, th;
+    wave_tile_dims(Q, tw, th);
+    const int32_t per = 64 / Q;
+    const int32_t lane = (int32_t)(t & 63);
+    phase = lane / per;
+    const int32_t j = lane % per;
+    const int64_t tiles_x = (w + tw - 1) / tw;
+    const int64_t tile = t >> 6;
+    const int64_t x = (tile % tiles_x) * tw + j % tw;
+    const int64_t y = (tile / tiles_x) * th + j / tw;
+    return (x < w && y < h) ? y * w + x : -1;
+}
+
+// PH: the pixels of an image launch get a.phases (2 or 4) lanes, one per
+// pass; otherwise one lane per ray (no registers for the colour hand-over).
+template <int W, int N, bool ANY, bool COUNT, int DM, bool PH>
 __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __restrict__ nodes_v,
                                                    const Record* __restrict__ recs)
 {
     __shared__ float lds_t[kWaveCap * 64];
     const WideNode<W>* __restrict__ nodes = static_cast<const WideNode<W>*>(nodes_v);
     const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 64 + threadIdx.x;
-    const int64_t ray = a.img_w > 0 ? tile_pixel(t, a.img_w, a.R / a.img_w) : (t < a.R ? t : -1);
+    const int32_t Q = PH ? a.phases : 1;  // lanes per pixel; phase q runs passes q, q + Q, ...
+    int32_t phase = 0;
+    const int64_t ray =
+        a.img_w > 0 ? (PH ? wave_pixel(t, a.img_w, a.R / a.img_w, Q, phase)
+                          : tile_pixel(t, a.img_w, a.R / a.img_w))
+                    : (t < a.R ? t : -1);
     const bool valid = ray >= 0;
     const int64_t rr = valid ? ray : 0;
     const float ox = a.o[3 * rr], oy = a.o[3 * rr + 1], oz = a.o[3 * rr + 2];
@@ -458,9 +500,15 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
     Counts cnt;
     uint32_t samples = 0;
     float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+    float col[PH ? N : 1][3];  // PH: this lane's sample colours (of its one pass)
+    int my_n = 0;
     bool overflow = false;
-    for (int pass = 0; pass * N < a.spp; ++pass) {
-        const int n_act = min(N, a.spp - pass * N);
+    const int P = (a.spp + N - 1) / N;
+    for (int it = 0; it * Q < P; ++it) {  // uniform
+        const int pass = it * Q + phase;
+        const bool has = pass < P;
+        const int n_act = has ? min(N, a.spp - pass * N) : 0;
+        const bool lv = live && has;
         const uint32_t s0 = sbase + (uint32_t)(pass * N);
         FwdSamples<N> st;
         st.reset(n_act, tmax_f);
@@ -472,9 +520,9 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
         };
         uint32_t n_nodes = 0, n_prims = 0;
         WaveStack stk{lds_t, kWaveCap, nullptr, 0, cap};
-        const int res = walk_wave<W, ANY>(nodes, rd, live, st.tcut, slack, stk, a.max_steps,
+        const int res = walk_wave<W, ANY>(nodes, rd, lv, st.tcut, slack, stk, a.max_steps,
                                           n_nodes, n_prims, visit);
-        if (live) {
+        if (lv) {
             ++cnt.trav;
             cnt.nodes += n_nodes;
             cnt.prims += n_prims;
@@ -485,8 +533,9 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
             overflow = true;
             break;
         }
-        if (!valid) continue;
+        if (!valid || !has) continue;
         samples += live ? (uint32_t)n_act : 0u;
+        my_n = n_act;
         float Y[16];
         if (shade) {
             const float ex = opaque(dx), ey = opaque(dy), ez = opaque(dz);
@@ -500,26 +549,52 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
             const int64_t o = ray * a.spp + pass * N + k;
             if (a.hit_gid) a.hit_gid[o] = hit ? st.bg[k] : -1;
             if (a.hit_t) a.hit_t[o] = hit ? st.bt[k] : INFINITY;
+            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
             if (ANY) {
-                const float v = hit ? 0.0f : 1.0f;
-                acc0 += v; acc1 += v; acc2 += v;
+                c0 = c1 = c2 = hit ? 0.0f : 1.0f;
             } else if (shade) {
                 if (hit) {
                     const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, st.bg[k], Y));
-                    acc0 += c.x; acc1 += c.y; acc2 += c.z;
+                    c0 = c.x; c1 = c.y; c2 = c.z;
                 } else {
-                    acc0 += a.bg[0]; acc1 += a.bg[1]; acc2 += a.bg[2];
+                    c0 = a.bg[0]; c1 = a.bg[1]; c2 = a.bg[2];
                 }
+            }
+            if constexpr (PH) {
+                col[k][0] = c0; col[k][1] = c1; col[k][2] = c2;
+            } else {
+                acc0 += c0; acc1 += c1; acc2 += c2;
+            }
+        }
+    }
+    if (PH && !overflow) {
+        // the pixel's colour sums its samples in sample order, as one lane
+        // would: phase 0's samples, then phase 1's, ...; the running sum moves
+        // to the pixel's lane of the next phase
+        const int per = 64 / Q;
+        for (int q = 0; q < Q; ++q) {  // uniform
+            if (phase == q) {
+#pragma unroll
+                for (int k = 0; k < (PH ? N : 1); ++k) {
+                    if (k >= my_n) continue;
+                    acc0 += col[k][0]; acc1 += col[k][1]; acc2 += col[k][2];
+                }
+            }
+            const float u0 = __shfl_up(acc0, per, 64);
+            const float u1 = __shfl_up(acc1, per, 64);
+            const float u2 = __shfl_up(acc2, per, 64);
+            if (phase == q + 1) {
+                acc0 = u0; acc1 = u1; acc2 = u2;
             }
         }
     }
     if (overflow) {
-        if (valid) {
+        if (valid && phase == 0) {  // once per pixel
             const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
             a.ovf_list[slot] = (uint32_t)ray;
         }
     } else if (valid) {
-        if (a.rgb) {
+        if (a.rgb && phase == Q - 1) {
             const float inv = 1.0f / (float)a.spp;
             a.rgb[3 * ray] = acc0 * inv;
             a.rgb[3 * ray + 1] = acc1 * inv;
@@ -539,36 +614,39 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
 
 using WaveFn = void (*)(TraceArgs, const void*, const Record*);
 
-template <int W, int DM>
-WaveFn wave_w(int N, bool any, bool count)
+template <int W, int N, bool ANY, int DM, bool PH>
+WaveFn wave_c(bool count)
 {
-    if (any) {
-        if (N != 1) return nullptr;
-        return count ? k_trace_wave<W, 1, true, true, DM> : k_trace_wave<W, 1, true, false, DM>;
-    }
+    return count ? k_trace_wave<W, N, ANY, true, DM, PH> : k_trace_wave<W, N, ANY, false, DM, PH>;
+}
+
+template <int W, int DM>
+WaveFn wave_w(int N, bool any, bool count, bool ph)
+{
+    if (any) return N == 1 && !ph ? wave_c<W, 1, true, DM, false>(count) : nullptr;
     switch (N) {
-    case 1: return count ? k_trace_wave<W, 1, false, true, DM> : k_trace_wave<W, 1, false, false, DM>;
-    case 2: return count ? k_trace_wave<W, 2, false, true, DM> : k_trace_wave<W, 2, false, false, DM>;
-    case 4: return count ? k_trace_wave<W, 4, false, true, DM> : k_trace_wave<W, 4, false, false, DM>;
-    case 8: return count ? k_trace_wave<W, 8, false, true, DM> : k_trace_wave<W, 8, false, false, DM>;
+    case 1: return ph ? wave_c<W, 1, false, DM, true>(count) : wave_c<W, 1, false, DM, false>(count);
+    case 2: return ph ? wave_c<W, 2, false, DM, true>(count) : wave_c<W, 2, false, DM, false>(count);
+    case 4: return ph ? wave_c<W, 4, false, DM, true>(count) : wave_c<W, 4, false, DM, false>(count);
+    case 8: return ph ? wave_c<W, 8, false, DM, true>(count) : wave_c<W, 8, false, DM, false>(count);
     }
     return nullptr;
 }
 
 template <int DM>
-WaveFn wave_dm(int W, int N, bool any, bool count)
+WaveFn wave_dm(int W, int N, bool any, bool count, bool ph)
 {
     switch (W) {
-    case 2: return wave_w<2, DM>(N, any, count);
-    case 4: return wave_w<4, DM>(N, any, count);
-    case 8: return wave_w<8, DM>(N, any, count);
+    case 2: return wave_w<2, DM>(N, any, count, ph);
+    case 4: return wave_w<4, DM>(N, any, count, ph);
+    case 8: return wave_w<8, DM>(N, any, count, ph);
     }
     return nullptr;
 }
 
-WaveFn pick_wave(int W, int N, bool any, bool count, int depth_mode)
+WaveFn pick_wave(int W, int N, bool any, bool count, int depth_mode, bool ph)
 {
-    return depth_mode == 0 ? wave_dm<0>(W, N, any, count) : wave_dm<1>(W, N, any, count);
+    return depth_mode == 0 ? wave_dm<0>(W, N, any, count, ph) : wave_dm<1>(W, N, any, count, ph);
 }
 
 using KernelFn = void (*)(TraceArgs);
@@ -736,9 +814,13 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
     const bool wave_ok = o->rng == 0 && !o->persistent;
     if (o->walk == 2 && !wave_ok) return SRT_ERR_UNSUPPORTED;
     WaveFn wf = nullptr;
+    a.phases = 1;
     if (o->walk == 2 || (o->walk == 0 && wave_ok && a.img_w > 0 && !o->any_hit)) {
+        // 2 or 4 passes per pixel: one lane per pass (see wave_pixel)
+        const int passes = (o->spp + o->n_per_traversal - 1) / o->n_per_traversal;
+        if (a.img_w > 0 && !o->any_hit && (passes == 2 || passes == 4)) a.phases = passes;
         wf = pick_wave(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr,
-                       o->depth_mode);
+                       o->depth_mode, a.phases > 1);
         if (!wf) return SRT_ERR_UNSUPPORTED;
     }
     KernelFn pf = nullptr;
@@ -755,7 +837,7 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
         if (pf) {
             hipLaunchKernelGGL(pf, dim3(blocks), dim3(kPersistBlock), 0, s, a);
         } else if (wf) {
-            const int64_t tiles = a.img_w > 0 ? tile_threads(a.img_w, rays->count / a.img_w) / 64
+            const int64_t tiles = a.img_w > 0 ? wave_tiles(a.img_w, rays->count / a.img_w, a.phases)
                                               : (rays->count + 63) / 64;
             hipLaunchKernelGGL(wf, dim3((unsigned)tiles), dim3(64), 0, s, a,
                                static_cast<const void*>(b->nodes), b->recs);

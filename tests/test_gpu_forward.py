@@ -501,14 +501,19 @@ def test_hash_rng_unsupported_combinations(srt):
     (8, 4, 8, 8, 0, 0, True, False), (4, 4, 2, 6, 1, 0, True, False),
     (4, 2, 4, 8, 0, 5, True, False), (8, 1, 4, 4, 1, 2, True, False),
     (4, 2, 4, 8, 0, 0, False, False), (4, 2, 1, 1, 0, 0, False, True),
-    (4, 2, 1, 3, 0, 3, True, True), (2, 4, 1, 2, 1, 0, False, True)])
+    (4, 2, 1, 3, 0, 3, True, True), (2, 4, 1, 2, 1, 0, False, True),
+    (4, 2, 4, 16, 0, 0, True, False), (4, 2, 4, 13, 1, 0, True, False),
+    (2, 4, 4, 7, 0, 3, True, False), (8, 2, 2, 8, 0, 0, True, False)])
 def test_wave_walk_equals_lane_walk(srt, W, L, N, spp, mode, lim, image, any_hit):
     """The 64 rays of a tile (or 64 consecutive rays) walking the BVH together
     reach, per ray, the same candidates as the ray's own walk: outputs equal
     bit for bit, with ragged tiles, empty rays, ignored ids and (lim > 0)
-    groups whose shared stack overflows into the deep pass. Any-hit rays: the
-    same visibility; the reported id is some accepted candidate, which may
-    differ with the visiting order."""
+    groups whose shared stack overflows into the deep pass. Images whose rays
+    need 2 or 4 passes put each pass of a pixel on its own lane (8x4 or 4x4
+    pixels per wave; colours summed in sample order across the lanes), also
+    with a partial last pass. Any-hit rays: the same visibility; the reported
+    id is some accepted candidate, which may differ with the visiting
+    order."""
     say(f"wave-shared walk vs lane walk: W={W} L={L} N={N} spp={spp} depth mode {mode} "
         f"stack limit {lim} image {image} any-hit {any_hit}")
     sc = tiny_scene(23, 3000, (0.02, 0.08))
