@@ -178,3 +178,28 @@ def test_autotuner_guards_and_picks(srt, setup, tmp_path):
                      leaves=(1, 4), thresholds=(16, 48), waves=(4, 8), reps=1,
                      cache_path=str(tmp_path / "tune.json"))
     assert again == json.loads(json.dumps(res))
+
+
+@pytest.mark.parametrize("N,mode", [(2, 1), (8, 0), (1, 0)])
+def test_wave_and_lane_walks_agree(srt, setup, N, mode):
+    """The views' tiles on wave-shared walks (plain: one wave per tile;
+    persistent: (tile, pass) groups after the extra rays) give the same hit
+    ids as lane walks, for other N and the centre depth mode, and colours up
+    to the order of the FP32 sums."""
+    s = setup
+    say(f"batched wave vs lane walks, N={N}, depth mode {mode}")
+    out = {}
+    for persistent in (False, True):
+        for walk in ("lane", "wave"):
+            plan = srt.srt_batch_plan_create(s["bvh"], s["cams"], s["spp"],
+                                             extra_origins=s["eoc"], extra_dirs=s["edc"],
+                                             extra_spp=2, seed=5, n_per_traversal=N,
+                                             depth_mode=mode, persistent=persistent, walk=walk)
+            rgb, hits, cnt = _run(plan)
+            assert cnt[6] == plan.samples and cnt[7] == 0
+            out[(persistent, walk)] = (rgb, hits)
+            del plan
+    ref_rgb, ref_hits = out[(False, "lane")]
+    for k, (rgb, hits) in out.items():
+        assert np.array_equal(hits, ref_hits), k
+        np.testing.assert_allclose(rgb, ref_rgb, atol=2e-6, rtol=1e-5, err_msg=str(k))
