@@ -196,8 +196,10 @@ typedef struct {
  * image_width     0: rays are independent (lane i traces ray i). > 0: the
  *                 rays are the pixels of a row-major image of this width
  *                 (count must be a multiple of it, else SRT_ERR_INVALID_ARG)
- *                 and each wave traces one 8x8 pixel tile, which keeps its
- *                 lanes on neighbouring rays. Results do not depend on it.
+ *                 and each wave traces one 8x8 pixel tile (with wave-shared
+ *                 walks and 2 or 4 passes per pixel: 8x4 or 4x4 pixels, one
+ *                 lane per pass), which keeps its lanes on neighbouring
+ *                 rays. Results do not depend on it.
  * persistent      0: one lane per ray. 1: work-stealing waves (one wave per
  *                 workgroup, as many as fit on the GPU) loop over the rays; a
  *                 lane runs all passes of its ray, and once refill_threshold
