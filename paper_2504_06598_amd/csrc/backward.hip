@@ -297,7 +297,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_backward(BwdArgs a, const void* _
                 n_trav += work ? 1u : 0u;
                 float tcut = fminf(cut_after(wt), tmax_f);
                 const uint32_t s0 = sbase + (uint32_t)(pass * N);
-                auto visit_rec = [&](const Record& r) -> bool {
+                // the ten sums' terms of record r for this lane's samples; false
+                // when r is no valid candidate in front of them
+                auto front_terms = [&](const Record& r, float (&v)[kAccVals]) -> bool {
                     if (depth_mode_of<DM>(dc) == 0 ? sphere_reject(r, rr, tmin_f, tcut)
                                                    : sphere_reject(r, rr, -INFINITY, INFINITY))
                         return false;
@@ -371,26 +373,50 @@ __global__ __launch_bounds__(kBlock, 3) void k_backward(BwdArgs a, const void* _
                                              : ((float)nf * gc - xs) * inv_spp / (1.0f - alpha);
                     const float sa = s_alpha * alpha;
                     const float p0 = (float)p[0], p1 = (float)p[1], p2 = (float)p[2];
-                    const float v[kAccVals] = {sa,           sa * p0,      sa * p1,
-                                               sa * p2,      sa * p0 * p0, sa * p1 * p1,
-                                               sa * p2 * p2, sa * p0 * p1, sa * p0 * p2,
-                                               sa * p1 * p2};
-                    table_add(table, a.acc, r.gid, v);
-                    return false;
+                    v[0] = sa;
+                    v[1] = sa * p0;
+                    v[2] = sa * p1;
+                    v[3] = sa * p2;
+                    v[4] = sa * p0 * p0;
+                    v[5] = sa * p1 * p1;
+                    v[6] = sa * p2 * p2;
+                    v[7] = sa * p0 * p1;
+                    v[8] = sa * p0 * p2;
+                    v[9] = sa * p1 * p2;
+                    return true;
                 };
                 const float slack = DM == 0 ? 0.0f : dc.node_slack;
                 int res;
                 if constexpr (WV) {
+                    // every lane of the walk handles the same record: the lanes' terms
+                    // are summed across the wave and one lane adds them to the table
+                    // (instead of up to 64 atomics on one LDS slot)
                     auto visit = [&](uint32_t ri, bool on) -> bool {
                         const Record r = load_record(recs_r, ri);
-                        if (on) visit_rec(r);
+                        float v[kAccVals] = {};
+                        const bool c = on && front_terms(r, v);
+                        const uint64_t m = __ballot(c);
+                        if (m != 0) {
+#pragma unroll
+                            for (int j = 0; j < kAccVals; ++j) {
+                                float x = c ? v[j] : 0.0f;
+#pragma unroll
+                                for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+                                v[j] = x;
+                            }
+                            if ((int)__lane_id() == __builtin_ctzll(m))
+                                table_add(table, a.acc, r.gid, v);
+                        }
                         return false;
                     };
                     res = walk_wave<W>(wnodes, rr, work, tcut, slack, wstk, a.max_steps, n_nodes,
                                        n_prims, visit);
                 } else {
                     auto visit = [&](uint32_t ri) -> bool {
-                        return visit_rec(load_record(a.recs, ri));
+                        const Record r = load_record(a.recs, ri);
+                        float v[kAccVals];
+                        if (front_terms(r, v)) table_add(table, a.acc, r.gid, v);
+                        return false;
                     };
                     res = walk<W>(nodes, rr, tcut, slack, stk, a.max_steps, n_nodes, n_prims, visit);
                 }
