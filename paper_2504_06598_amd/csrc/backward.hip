@@ -136,7 +136,8 @@ __device__ __forceinline__ void table_add(Table& t, float* acc, int32_t gid, con
 // waves per SIMD (a few spill to scratch; measured faster than 2 waves).
 template <int W, int N, bool COUNT, bool RB, int DM, bool WV>
 __global__ __launch_bounds__(kBlock, 3) void k_backward(BwdArgs a, const void* __restrict__ nodes_v,
-                                                     const Record* __restrict__ recs_r)
+                                                     const Record* __restrict__ recs_r,
+                                                     const float* __restrict__ sh_r)
 {
     __shared__ int32_t lds[kLdsEntries * kBlock];
     __shared__ int32_t tkeys[kTableSlots];
@@ -364,7 +365,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_backward(BwdArgs a, const void* _
                     ++n_front;
                     // alpha only weights FP32 sums here: FP32 precision suffices
                     const float alpha = r.opacity * expf(-0.5f * (float)q);
-                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, r.gid, Y));
+                    // WV: r.gid is the same on every lane, so its SH row is fetched once
+                    const float3 c = clamp0(sh_colour_pre(WV ? sh_r : a.sh, a.deg, r.gid, Y));
                     const float gc = g0 * c.x + g1 * c.y + g2 * c.z;
                     // plain: <g, c_k - X> / (1 - alpha_k) per front sample; RB: the
                     // same without the division, and <g, c_a> for a sample's first
@@ -590,7 +592,7 @@ __global__ void k_chain(int64_t G, const float* __restrict__ acc, const float* _
     g_logits[g] += (float)((1.0 - o) * A);
 }
 
-using BwdFn = void (*)(BwdArgs, const void*, const Record*);
+using BwdFn = void (*)(BwdArgs, const void*, const Record*, const float*);
 
 template <int W, bool C, bool RB, int DM, bool WV>
 BwdFn pick_n(int N)
@@ -757,7 +759,7 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
     a.tile_ctr = ws.tile_ctr;
     fill_u32(ws.tile_ctr, 0u, 128, s);
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, s, a, static_cast<const void*>(b->nodes),
-                       static_cast<const Record*>(b->recs));
+                       static_cast<const Record*>(b->recs), static_cast<const float*>(b->sh));
     SRT_HIP_TRY(hipGetLastError());
     k_chain<<<(unsigned)((b->G + 255) / 256), 256, 0, s>>>(
         b->G, ws.acc, scene->log_scales, scene->quats, scene->opacity_logits, g_means, g_log_scales,
