@@ -153,8 +153,17 @@ def isect_one(rec: Records, g, o, d, tmin=0.0, tmax=np.inf):
     return bool(v), out[0], out[1], out[2]
 
 
-def candidates(rec: Records, o, d, tmin=0.0, tmax=np.inf, ignore_gid=-1, cap=1 << 16):
-    """Valid candidates of one ray, sorted by (FP32 depth, id)."""
+def _axis(depth_axis):
+    return _f64(np.asarray(depth_axis, np.float64).reshape(3))
+
+
+def candidates(rec: Records, o, d, tmin=0.0, tmax=np.inf, ignore_gid=-1, cap=1 << 16,
+               depth_mode=0, depth_axis=(0.0, 0.0, 0.0)):
+    """Valid candidates of one ray, sorted by (FP32 depth, id). depth_mode:
+    0 = the mean of the 1D Gaussian along the ray (Sec. 3.1); 1 = the centre
+    projected onto depth_axis (Sec. 4.1; a zero axis means the ray's own
+    direction). The same keyword applies to every function below that
+    collects candidates."""
     lib = _load()
     t = np.zeros(cap)
     q = np.zeros(cap)
@@ -163,7 +172,8 @@ def candidates(rec: Records, o, d, tmin=0.0, tmax=np.inf, ignore_gid=-1, cap=1 <
     g = np.zeros(cap, np.int32)
     n = lib.srto_candidates(C.c_int64(rec.G), _p(rec.mu), _p(rec.M), _p(rec.op), _p(_f32(o)),
                             _p(_f32(d)), C.c_double(tmin), C.c_double(tmax),
-                            C.c_int32(ignore_gid), C.c_int64(cap), _p(t), _p(q), _p(a),
+                            C.c_int32(ignore_gid), C.c_int(depth_mode), _p(_axis(depth_axis)),
+                            C.c_int64(cap), _p(t), _p(q), _p(a),
                             _p(t32), _p(g))
     n = min(n, cap)
     return dict(t=t[:n], q=q[:n], alpha=a[:n], t32=t32[:n], gid=g[:n])
@@ -185,28 +195,9 @@ class Rays:
         return self.o.shape[0]
 
 
-def set_depth_mode(mode=0, axis=(0.0, 0.0, 0.0)):
-    """Depth used for ordering and the range test: 0 = mean of the 1D Gaussian
-    along the ray (Sec. 3.1); 1 = centre projected onto `axis` (Sec. 4.1;
-    zero axis = each ray's direction). Applies to every later call."""
-    _load().srto_set_depth_mode(C.c_int(mode), _p(_f64(axis)))
-
-
-class depth_mode:
-    """Context manager selecting the oracle's depth mode."""
-
-    def __init__(self, mode, axis=(0.0, 0.0, 0.0)):
-        self.mode, self.axis = mode, axis
-
-    def __enter__(self):
-        set_depth_mode(self.mode, self.axis)
-
-    def __exit__(self, *exc):
-        set_depth_mode(0)
-
-
 def trace(rec: Records, rays: Rays, spp=1, seed=0, purpose=0, any_hit=False,
-          bg=(0.0, 0.0, 0.0), u_override=None, threads=None):
+          bg=(0.0, 0.0, 0.0), u_override=None, threads=None, depth_mode=0,
+          depth_axis=(0.0, 0.0, 0.0)):
     """Nearest accepted hit per sample (brute force, FP64)."""
     lib = _load()
     R = rays.count
@@ -221,12 +212,14 @@ def trace(rec: Records, rays: Rays, spp=1, seed=0, purpose=0, any_hit=False,
                    _p(rec._sh), C.c_int64(R), _p(rays.o), _p(rays.d), _p(rays.tmin),
                    _p(rays.tmax), _p(rays.ignore_gid), _p(rays.ray_id), _p(rays.sample_base),
                    C.c_int32(spp), C.c_uint64(seed), C.c_uint32(purpose),
-                   C.c_int(1 if any_hit else 0), _p(bg), _p(uo), _p(rgb), _p(gid), _p(t),
+                   C.c_int(1 if any_hit else 0), _p(bg), _p(uo), C.c_int(depth_mode),
+                   _p(_axis(depth_axis)), _p(rgb), _p(gid), _p(t),
                    _p(flags), _p(margin), C.c_int(threads or default_threads()))
     return dict(rgb=rgb, hit_gid=gid, hit_t=t, flags=flags, margin=margin)
 
 
-def composite(rec: Records, rays: Rays, bg=(0.0, 0.0, 0.0), threads=None):
+def composite(rec: Records, rays: Rays, bg=(0.0, 0.0, 0.0), threads=None, depth_mode=0,
+              depth_axis=(0.0, 0.0, 0.0)):
     """Exact sorted front-to-back composite L [R,3], single-sample variance,
     final transmittance and candidate count."""
     lib = _load()
@@ -237,7 +230,8 @@ def composite(rec: Records, rays: Rays, bg=(0.0, 0.0, 0.0), threads=None):
     n = np.zeros(R, np.int32)
     lib.srto_composite(C.c_int64(rec.G), _p(rec.mu), _p(rec.M), _p(rec.op), C.c_int(rec.deg),
                        _p(rec._sh), C.c_int64(R), _p(rays.o), _p(rays.d), _p(rays.tmin),
-                       _p(rays.tmax), _p(rays.ignore_gid), _p(_f64(bg)), _p(L), _p(var),
+                       _p(rays.tmax), _p(rays.ignore_gid), _p(_f64(bg)), C.c_int(depth_mode),
+                       _p(_axis(depth_axis)), _p(L), _p(var),
                        _p(T), _p(n), C.c_int(threads or default_threads()))
     return dict(L=L, var=var, T_end=T, n_cand=n)
 
@@ -250,7 +244,8 @@ def _grad_bufs(rec):
                 sh=np.zeros((G, K, 3)))
 
 
-def composite_grad(rec: Records, rays: Rays, dL, bg=(0.0, 0.0, 0.0), threads=None):
+def composite_grad(rec: Records, rays: Rays, dL, bg=(0.0, 0.0, 0.0), threads=None,
+                   depth_mode=0, depth_axis=(0.0, 0.0, 0.0)):
     """Gradient of sum_i <dL_i, L_i> (exact composite) w.r.t. raw parameters."""
     lib = _load()
     g = _grad_bufs(rec)
@@ -258,6 +253,7 @@ def composite_grad(rec: Records, rays: Rays, dL, bg=(0.0, 0.0, 0.0), threads=Non
                             C.c_int(rec.deg), _p(rec._sh), _p(rec._ls), _p(rec._q),
                             _p(rec._lg), C.c_int64(rays.count), _p(rays.o), _p(rays.d),
                             _p(rays.tmin), _p(rays.tmax), _p(rays.ignore_gid), _p(_f64(bg)),
+                            C.c_int(depth_mode), _p(_axis(depth_axis)),
                             _p(_f64(dL)), _p(g["means"]), _p(g["log_scales"]),
                             _p(g["quats"]), _p(g["opacity_logits"]), _p(g["sh"]),
                             C.c_int(threads or default_threads()))
@@ -265,7 +261,8 @@ def composite_grad(rec: Records, rays: Rays, dL, bg=(0.0, 0.0, 0.0), threads=Non
 
 
 def estimator_grad(rec: Records, rays: Rays, dL, spp=1, seed=0, purpose=0,
-                   bg=(0.0, 0.0, 0.0), threads=None, estimator="plain"):
+                   bg=(0.0, 0.0, 0.0), threads=None, estimator="plain", depth_mode=0,
+                   depth_axis=(0.0, 0.0, 0.0)):
     """The stochastic gradient estimator on the realisation ``trace`` draws;
     estimator="rb" averages each candidate's term over its own acceptance
     number (see srto_estimator_grad_rb)."""
@@ -280,6 +277,7 @@ def estimator_grad(rec: Records, rays: Rays, dL, spp=1, seed=0, purpose=0,
                             _p(rays.tmin), _p(rays.tmax), _p(rays.ignore_gid),
                             _p(rays.ray_id), _p(rays.sample_base), C.c_int32(spp),
                             C.c_uint64(seed), C.c_uint32(purpose), _p(_f64(bg)),
+                            C.c_int(depth_mode), _p(_axis(depth_axis)),
                             _p(_f64(dL)), _p(g["means"]), _p(g["log_scales"]),
                             _p(g["quats"]), _p(g["opacity_logits"]), _p(g["sh"]),
                             C.c_int(threads or default_threads()))
@@ -287,8 +285,10 @@ def estimator_grad(rec: Records, rays: Rays, dL, spp=1, seed=0, purpose=0,
 
 
 def pathmix(rec: Records, o, d, ray_id=None, spp=1, seed=0, light=(5.0, 5.0, 5.0),
-            plane_y=-2.5, bg=(0.0, 0.0, 0.0), threads=None):
-    """Camera rays with shadow and mirror secondaries (see srt_oracle.c)."""
+            plane_y=-2.5, bg=(0.0, 0.0, 0.0), threads=None, u_override=None):
+    """Camera rays with shadow and mirror secondaries (see srt_oracle.c).
+    u_override [G]: replaces every acceptance number of Gaussian g by
+    u_override[g] (tests inject binary outcomes)."""
     lib = _load()
     o = _f32(o)
     d = _f32(d)
@@ -302,7 +302,8 @@ def pathmix(rec: Records, o, d, ray_id=None, spp=1, seed=0, light=(5.0, 5.0, 5.0
     lib.srto_pathmix(C.c_int64(rec.G), _p(rec.mu), _p(rec.M), _p(rec.op), C.c_int(rec.deg),
                      _p(rec._sh), C.c_int64(R), _p(o), _p(d), _p(_u32(ray_id)),
                      C.c_int32(spp), C.c_uint64(seed), _p(_f32(light)),
-                     C.c_float(plane_y), _p(_f64(bg)), _p(rgb), _p(cg), _p(ct), _p(vis),
+                     C.c_float(plane_y), _p(_f64(bg)), _p(_f64(u_override)), _p(rgb), _p(cg),
+                     _p(ct), _p(vis),
                      _p(mg), _p(fl), C.c_int(threads or default_threads()))
     return dict(rgb=rgb, cam_gid=cg, cam_t=ct, shadow_vis=vis, mirror_gid=mg, flags=fl)
 

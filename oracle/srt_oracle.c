@@ -300,20 +300,26 @@ static int near_rel(double a, double b)
  * of the 1D Gaussian along the ray. Mode 1 ("center"): the Gaussian centre
  * projected onto a viewing axis a, expressed as the ray parameter with the
  * same depth along a: t = ((mu - o) . a) / (d . a); a = (0,0,0) means the
- * ray's own direction. Opacity stays at the 1D peak in both modes. */
-static int g_depth_mode = 0;
-static double g_axis[3] = {0.0, 0.0, 0.0};
+ * ray's own direction. Opacity stays at the 1D peak in both modes. The mode
+ * is an argument of every call that collects candidates (no global state). */
+typedef struct {
+    int mode;
+    double axis[3];
+} depth_t;
 
-void srto_set_depth_mode(int mode, const double* axis)
+static depth_t depth_of(int mode, const double* axis)
 {
-    g_depth_mode = mode;
-    for (int i = 0; i < 3; ++i) g_axis[i] = axis ? axis[i] : 0.0;
+    depth_t dm;
+    dm.mode = mode;
+    for (int i = 0; i < 3; ++i) dm.axis[i] = (mode != 0 && axis) ? axis[i] : 0.0;
+    return dm;
 }
 
-static double depth_key(const isect_t* r, const double* mu, const float* o, const float* d)
+static double depth_key(const depth_t* dm, const isect_t* r, const double* mu, const float* o,
+                        const float* d)
 {
-    if (g_depth_mode == 0) return r->t;
-    double a[3] = {g_axis[0], g_axis[1], g_axis[2]};
+    if (dm->mode == 0) return r->t;
+    double a[3] = {dm->axis[0], dm->axis[1], dm->axis[2]};
     if (a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0) {
         a[0] = d[0];
         a[1] = d[1];
@@ -330,8 +336,8 @@ static double depth_key(const isect_t* r, const double* mu, const float* o, cons
 /* Brute-force candidate collection for one ray: every Gaussian whose depth
  * is in the open ray range and whose 1D mean is inside the ellipsoid, plus
  * borderline ones (kept for flagging, never selected). */
-static void collect(int64_t G, const double* mu, const double* M, const double* op,
-                    const float* o, const float* d, double tmin, double tmax,
+static void collect(const depth_t* dm, int64_t G, const double* mu, const double* M,
+                    const double* op, const float* o, const float* d, double tmin, double tmax,
                     int32_t ignore_gid, clist_t* out)
 {
     out->n = 0;
@@ -339,7 +345,7 @@ static void collect(int64_t G, const double* mu, const double* M, const double* 
         if ((int32_t)g == ignore_gid) continue;
         isect_t r;
         isect(mu + 3 * g, M + 9 * g, o, d, &r);
-        const double t = depth_key(&r, mu + 3 * g, o, d);
+        const double t = depth_key(dm, &r, mu + 3 * g, o, d);
         int valid = (t > tmin && t < tmax && r.q <= SRTO_S2);
         int border = near_rel(r.q, SRTO_S2) || near_rel(t, tmin) ||
                      (isfinite(tmax) && near_rel(t, tmax));
@@ -440,10 +446,12 @@ void srto_trace(int64_t G, const double* mu, const double* M, const double* op, 
                 const float* sh, int64_t R, const float* o, const float* d, const float* tmin,
                 const float* tmax, const int32_t* ignore_gid, const uint32_t* ray_id,
                 const uint32_t* sample_base, int32_t spp, uint64_t seed, uint32_t purpose,
-                int any_hit, const double* bg, const double* u_override, double* rgb,
-                int32_t* hit_gid, float* hit_t, uint8_t* flags, double* margin, int threads)
+                int any_hit, const double* bg, const double* u_override, int depth_mode,
+                const double* depth_axis, double* rgb, int32_t* hit_gid, float* hit_t,
+                uint8_t* flags, double* margin, int threads)
 {
     rays_t RR = {R, o, d, tmin, tmax, ignore_gid, ray_id, sample_base};
+    const depth_t dm = depth_of(depth_mode, depth_axis);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #endif
@@ -456,7 +464,7 @@ void srto_trace(int64_t G, const double* mu, const double* M, const double* op, 
             int32_t ign;
             uint32_t rid, sb;
             ray_get(&RR, i, &t0, &t1, &ign, &rid, &sb);
-            collect(G, mu, M, op, o + 3 * i, d + 3 * i, t0, t1, ign, &cl);
+            collect(&dm, G, mu, M, op, o + 3 * i, d + 3 * i, t0, t1, ign, &cl);
             double Y[16], dir[3] = {d[3 * i], d[3 * i + 1], d[3 * i + 2]};
             srto_sh_basis(deg, dir, Y);
             double acc[3] = {0, 0, 0};
@@ -492,11 +500,13 @@ void srto_trace(int64_t G, const double* mu, const double* M, const double* op, 
  * the number written (at most cap). */
 int64_t srto_candidates(int64_t G, const double* mu, const double* M, const double* op,
                         const float* o, const float* d, double tmin, double tmax,
-                        int32_t ignore_gid, int64_t cap, double* t, double* q, double* alpha,
-                        float* t32, int32_t* gid)
+                        int32_t ignore_gid, int depth_mode, const double* depth_axis,
+                        int64_t cap, double* t, double* q, double* alpha, float* t32,
+                        int32_t* gid)
 {
     clist_t cl = {0, 0, 0};
-    collect(G, mu, M, op, o, d, tmin, tmax, ignore_gid, &cl);
+    const depth_t dm = depth_of(depth_mode, depth_axis);
+    collect(&dm, G, mu, M, op, o, d, tmin, tmax, ignore_gid, &cl);
     int64_t n = 0;
     for (int64_t i = 0; i < cl.n; ++i)
         if (cl.v[i].valid) cl.v[n++] = cl.v[i];
@@ -524,11 +534,12 @@ typedef struct {
     double* pre; /* [n,3] unclamped */
 } sorted_t;
 
-static void sorted_build(sorted_t* S, int64_t G, const double* mu, const double* M,
-                         const double* op, int deg, const float* sh, const float* o,
-                         const float* d, double tmin, double tmax, int32_t ign, const double* Y)
+static void sorted_build(sorted_t* S, const depth_t* dm, int64_t G, const double* mu,
+                         const double* M, const double* op, int deg, const float* sh,
+                         const float* o, const float* d, double tmin, double tmax, int32_t ign,
+                         const double* Y)
 {
-    collect(G, mu, M, op, o, d, tmin, tmax, ign, &S->cl);
+    collect(dm, G, mu, M, op, o, d, tmin, tmax, ign, &S->cl);
     int64_t n = 0;
     for (int64_t i = 0; i < S->cl.n; ++i)
         if (S->cl.v[i].valid) S->cl.v[n++] = S->cl.v[i];
@@ -545,10 +556,11 @@ static void sorted_build(sorted_t* S, int64_t G, const double* mu, const double*
 void srto_composite(int64_t G, const double* mu, const double* M, const double* op, int deg,
                     const float* sh, int64_t R, const float* o, const float* d,
                     const float* tmin, const float* tmax, const int32_t* ignore_gid,
-                    const double* bg, double* L, double* var, double* T_end, int32_t* n_cand,
-                    int threads)
+                    const double* bg, int depth_mode, const double* depth_axis, double* L,
+                    double* var, double* T_end, int32_t* n_cand, int threads)
 {
     rays_t RR = {R, o, d, tmin, tmax, ignore_gid, 0, 0};
+    const depth_t dm = depth_of(depth_mode, depth_axis);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #endif
@@ -563,7 +575,7 @@ void srto_composite(int64_t G, const double* mu, const double* M, const double* 
             ray_get(&RR, i, &t0, &t1, &ign, &rid, &sb);
             double Y[16], dir[3] = {d[3 * i], d[3 * i + 1], d[3 * i + 2]};
             srto_sh_basis(deg, dir, Y);
-            sorted_build(&S, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
+            sorted_build(&S, &dm, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
             double T = 1.0, l[3] = {0, 0, 0}, l2[3] = {0, 0, 0};
             for (int64_t k = 0; k < S.cl.n; ++k) {
                 double a = S.cl.v[k].alpha;
@@ -687,11 +699,13 @@ void srto_composite_grad(int64_t G, const double* mu, const double* M, const dou
                          int deg, const float* sh, const float* log_scales,
                          const float* quats, const float* logits, int64_t R, const float* o,
                          const float* d, const float* tmin, const float* tmax,
-                         const int32_t* ignore_gid, const double* bg, const double* dL,
-                         double* g_means, double* g_ls, double* g_quats, double* g_logits,
-                         double* g_sh, int threads)
+                         const int32_t* ignore_gid, const double* bg, int depth_mode,
+                         const double* depth_axis, const double* dL, double* g_means,
+                         double* g_ls, double* g_quats, double* g_logits, double* g_sh,
+                         int threads)
 {
     rays_t RR = {R, o, d, tmin, tmax, ignore_gid, 0, 0};
+    const depth_t dm = depth_of(depth_mode, depth_axis);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #endif
@@ -708,7 +722,7 @@ void srto_composite_grad(int64_t G, const double* mu, const double* M, const dou
             ray_get(&RR, i, &t0, &t1, &ign, &rid, &sb);
             double Y[16], dir[3] = {d[3 * i], d[3 * i + 1], d[3 * i + 2]};
             srto_sh_basis(deg, dir, Y);
-            sorted_build(&S, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
+            sorted_build(&S, &dm, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
             int64_t n = S.cl.n;
             if (n == 0) continue;
             if (Bcap < n) {
@@ -757,11 +771,13 @@ void srto_estimator_grad(int64_t G, const double* mu, const double* M, const dou
                          const float* d, const float* tmin, const float* tmax,
                          const int32_t* ignore_gid, const uint32_t* ray_id,
                          const uint32_t* sample_base, int32_t spp, uint64_t seed,
-                         uint32_t purpose, const double* bg, const double* dL,
-                         double* g_means, double* g_ls, double* g_quats, double* g_logits,
-                         double* g_sh, int threads)
+                         uint32_t purpose, const double* bg, int depth_mode,
+                         const double* depth_axis, const double* dL, double* g_means,
+                         double* g_ls, double* g_quats, double* g_logits, double* g_sh,
+                         int threads)
 {
     rays_t RR = {R, o, d, tmin, tmax, ignore_gid, ray_id, sample_base};
+    const depth_t dm = depth_of(depth_mode, depth_axis);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #endif
@@ -778,7 +794,7 @@ void srto_estimator_grad(int64_t G, const double* mu, const double* M, const dou
             ray_get(&RR, i, &t0, &t1, &ign, &rid, &sb);
             double Y[16], dir[3] = {d[3 * i], d[3 * i + 1], d[3 * i + 2]};
             srto_sh_basis(deg, dir, Y);
-            sorted_build(&S, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
+            sorted_build(&S, &dm, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
             int64_t n = S.cl.n;
             if (n == 0) continue;
             if (cap < n) {
@@ -846,10 +862,12 @@ void srto_estimator_grad_rb(int64_t G, const double* mu, const double* M, const 
                             const float* tmax, const int32_t* ignore_gid,
                             const uint32_t* ray_id, const uint32_t* sample_base, int32_t spp,
                             uint64_t seed, uint32_t purpose, const double* bg,
-                            const double* dL, double* g_means, double* g_ls, double* g_quats,
-                            double* g_logits, double* g_sh, int threads)
+                            int depth_mode, const double* depth_axis, const double* dL,
+                            double* g_means, double* g_ls, double* g_quats, double* g_logits,
+                            double* g_sh, int threads)
 {
     rays_t RR = {R, o, d, tmin, tmax, ignore_gid, ray_id, sample_base};
+    const depth_t dm = depth_of(depth_mode, depth_axis);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #endif
@@ -866,7 +884,7 @@ void srto_estimator_grad_rb(int64_t G, const double* mu, const double* M, const 
             ray_get(&RR, i, &t0, &t1, &ign, &rid, &sb);
             double Y[16], dir[3] = {d[3 * i], d[3 * i + 1], d[3 * i + 2]};
             srto_sh_basis(deg, dir, Y);
-            sorted_build(&S, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
+            sorted_build(&S, &dm, G, mu, M, op, deg, sh, o + 3 * i, d + 3 * i, t0, t1, ign, Y);
             int64_t n = S.cl.n;
             if (n == 0) continue;
             if (cap < n) {
@@ -940,14 +958,18 @@ void srto_estimator_grad_rb(int64_t G, const double* mu, const double* M, const 
 /* Colour: Gaussian c * (0.3 + 0.7 V); plane 0.5 V max(0, l_y) + 0.5 Lm,     */
 /* Lm the mirror ray's Gaussian colour (bg on a miss); a miss of both: bg.   */
 /* Secondary rays reuse the camera sample's ray id and sample index with     */
-/* Philox purposes 2 (shadow) and 3 (mirror).                                */
+/* Philox purposes 2 (shadow) and 3 (mirror). `u_override`, when non-null,   */
+/* replaces every acceptance number of Gaussian g (any ray, any purpose) by  */
+/* u_override[g] (tests inject binary outcomes this way).                    */
 /* ------------------------------------------------------------------------ */
 void srto_pathmix(int64_t G, const double* mu, const double* M, const double* op, int deg,
                   const float* sh, int64_t R, const float* o, const float* d,
                   const uint32_t* ray_id, int32_t spp, uint64_t seed, const float* light,
-                  float plane_y, const double* bg, double* rgb, int32_t* cam_gid, float* cam_t,
-                  uint8_t* shadow_vis, int32_t* mirror_gid, uint8_t* flags, int threads)
+                  float plane_y, const double* bg, const double* u_override, double* rgb,
+                  int32_t* cam_gid, float* cam_t, uint8_t* shadow_vis, int32_t* mirror_gid,
+                  uint8_t* flags, int threads)
 {
+    const depth_t dm = depth_of(0, 0);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #endif
@@ -960,7 +982,7 @@ void srto_pathmix(int64_t G, const double* mu, const double* M, const double* op
             const float* oi = o + 3 * i;
             const float* di = d + 3 * i;
             uint32_t rid = ray_id ? ray_id[i] : (uint32_t)i;
-            collect(G, mu, M, op, oi, di, 0.0, INFINITY, -1, &cam);
+            collect(&dm, G, mu, M, op, oi, di, 0.0, INFINITY, -1, &cam);
             double Y[16], dir[3] = {di[0], di[1], di[2]};
             srto_sh_basis(deg, dir, Y);
             float tp = INFINITY;
@@ -974,7 +996,7 @@ void srto_pathmix(int64_t G, const double* mu, const double* M, const double* op
                 int64_t k = i * spp + s;
                 uint8_t f = 0, f2 = 0;
                 double m;
-                int64_t b = resolve(&cam, seed, rid, (uint32_t)s, 0u, 0, 0, &f, &m);
+                int64_t b = resolve(&cam, seed, rid, (uint32_t)s, 0u, 0, u_override, &f, &m);
                 float tg = b >= 0 ? cam.v[b].t32 : INFINITY;
                 int32_t gg = b >= 0 ? cam.v[b].gid : -1;
                 if (cam_gid) cam_gid[k] = gg;
@@ -999,9 +1021,9 @@ void srto_pathmix(int64_t G, const double* mu, const double* M, const double* op
                     float len = sqrtf(len2);
                     float l[3] = {v[0] / len, v[1] / len, v[2] / len};
                     /* shadow ray: (P, l, tmin_sec, len, gg), any hit */
-                    collect(G, mu, M, op, P, l, (double)tmin_sec, (double)len,
+                    collect(&dm, G, mu, M, op, P, l, (double)tmin_sec, (double)len,
                             on_gauss ? gg : -1, &sec);
-                    int64_t sb = resolve(&sec, seed, rid, (uint32_t)s, 2u, 1, 0, &f2, &m);
+                    int64_t sb = resolve(&sec, seed, rid, (uint32_t)s, 2u, 1, u_override, &f2, &m);
                     f |= f2;
                     vis = sb >= 0 ? 0 : 1;
                     double V = (double)vis;
@@ -1011,8 +1033,8 @@ void srto_pathmix(int64_t G, const double* mu, const double* M, const double* op
                         for (int ch = 0; ch < 3; ++ch) col[ch] = c[ch] * (0.3 + 0.7 * V);
                     } else {
                         float md[3] = {di[0], -di[1], di[2]};
-                        collect(G, mu, M, op, P, md, (double)tmin_sec, INFINITY, -1, &sec);
-                        int64_t mb = resolve(&sec, seed, rid, (uint32_t)s, 3u, 0, 0, &f2, &m);
+                        collect(&dm, G, mu, M, op, P, md, (double)tmin_sec, INFINITY, -1, &sec);
+                        int64_t mb = resolve(&sec, seed, rid, (uint32_t)s, 3u, 0, u_override, &f2, &m);
                         f |= f2;
                         double Lm[3];
                         if (mb >= 0) {

@@ -196,12 +196,11 @@ def test_backward_center_depth_matches_oracle(srt):
     o, d = si.camera_rays(cam)
     ax = tuple(float(x) for x in cam.forward)
     rec = oracle.Records(sc)
-    with oracle.depth_mode(1, np.asarray(ax, np.float64)):
-        ora_f = oracle.trace(rec, oracle.Rays(o, d), spp=4, seed=5)
-        dL = np.random.default_rng(8).normal(0, 1, (len(o), 3))
-        dL[(ora_f["flags"] != 0).any(1)] = 0.0
-        ora = oracle.estimator_grad(rec, oracle.Rays(o, d), dL.astype(np.float32).astype(np.float64),
-                                    spp=4, seed=5)
+    ora_f = oracle.trace(rec, oracle.Rays(o, d), spp=4, seed=5, depth_mode=1, depth_axis=ax)
+    dL = np.random.default_rng(8).normal(0, 1, (len(o), 3))
+    dL[(ora_f["flags"] != 0).any(1)] = 0.0
+    ora = oracle.estimator_grad(rec, oracle.Rays(o, d), dL.astype(np.float32).astype(np.float64),
+                                spp=4, seed=5, depth_mode=1, depth_axis=ax)
     bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
     oc, dc = _cu(o), _cu(d)
     fw = srt.srt_trace_forward(bvh, oc, dc, seed=5, spp=4, n_per_traversal=4, depth_mode=1,

@@ -286,8 +286,8 @@ def test_center_depth_matches_oracle(srt, axis):
     ax = tuple(float(x) for x in cam.forward) if axis == "camera" else (0.0, 0.0, 0.0)
     bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
     g = _trace(srt, bvh, o, d, seed=8, spp=8, n_per_traversal=4, depth_mode=1, depth_axis=ax)
-    with oracle.depth_mode(1, np.asarray(ax, np.float64)):
-        ora = oracle.trace(oracle.Records(sc), oracle.Rays(o, d), spp=8, seed=8)
+    ora = oracle.trace(oracle.Records(sc), oracle.Rays(o, d), spp=8, seed=8, depth_mode=1,
+                       depth_axis=ax)
     compare_ids(g["hit_gid"], ora["hit_gid"], ora["flags"])
     compare_rgb(g["rgb"], ora["rgb"], ora["flags"])
     same = (g["hit_gid"] == ora["hit_gid"]) & (ora["hit_gid"] >= 0)

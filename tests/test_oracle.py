@@ -319,6 +319,69 @@ def test_flags_mark_threshold_flips():
     assert r["flags"][0, 0] == 0
 
 
+def _offsets_near_q8():
+    """FP32 ray offsets (bx, by) with q = bx^2 + by^2 (FP64) just inside and
+    just outside the ellipsoid boundary q = 8 (within 1e-9 relative), and one
+    clearly inside. With M = I and the ray (bx, by, -3) + t (0, 0, 1) the 1D
+    mean is t* = 3 and q = bx^2 + by^2 exactly as the oracle evaluates it."""
+    bx = (F32(1.9) + F32(2.0 ** -23) * np.arange(400000, dtype=np.float64)).astype(F32)
+    by0 = np.sqrt(8.0 - bx.astype(np.float64) ** 2).astype(F32)
+    found = {}
+    for by in (by0, np.nextafter(by0, F32(3)), np.nextafter(by0, F32(0))):
+        q = bx.astype(np.float64) * bx + by.astype(np.float64) * by
+        for name, sel in (("in", (q < 8) & (q > 8 - 4e-9)), ("out", (q > 8) & (q < 8 + 4e-9)),
+                          ("far_in", (q < 8 - 1e-6) & (q > 8 - 1e-5))):
+            if name not in found and sel.any():
+                i = int(np.argmax(sel))
+                found[name] = (bx[i], by[i], q[i])
+    return found
+
+
+def test_flags_mark_the_ellipsoid_boundary():
+    """A candidate whose q lies within 1e-9 (relative) of s^2 = 8 (eqn
+    "cuboid") may be valid on one side and not on the other once the GPU
+    rounds differently: an accepted one is flagged FLAG_GEO (2) on either
+    side; a clearly inside one and a rejected borderline one are not."""
+    sc = _scene([[0.0, 0.0, 0.0]], [[0.0, 0.0, 0.0]], [[1, 0, 0, 0]], [_logit(0.9)])
+    rec = oracle.Records(sc)
+    assert np.array_equal(rec.M[0], np.eye(3).ravel()) and np.all(rec.mu[0] == 0)
+    off = _offsets_near_q8()
+    d = [[0.0, 0.0, 1.0]]
+    for name, (bx, by, q) in off.items():
+        rays = oracle.Rays([[bx, by, -3.0]], d)
+        valid, t, qq, a = oracle.isect_one(rec, 0, [bx, by, -3.0], d[0])
+        assert qq == q and t == 3.0 and valid == (q <= 8.0), (name, qq, q)
+        r = oracle.trace(rec, rays, u_override=np.array([0.0]))
+        assert r["hit_gid"][0, 0] == (0 if q <= 8.0 else -1), name
+        assert bool(r["flags"][0, 0] & 2) == (name != "far_in"), (name, r["flags"])
+        # rejected (u >= alpha): nothing to flip
+        r = oracle.trace(rec, rays, u_override=np.array([0.999]))
+        assert r["hit_gid"][0, 0] == -1 and r["flags"][0, 0] == 0, name
+
+
+def test_flags_mark_keys_one_ulp_apart():
+    """Two accepted candidates whose FP32 depth keys are adjacent floats may
+    swap order under another FP64 evaluation order of t*: flagged FLAG_GEO.
+    Two ulps apart, equal keys (ties go by id, exactly) or a rejected
+    neighbour: not flagged. With M = I and the ray along the z axis through
+    the centres, t* = mu_z exactly."""
+    z0 = F32(2.0)
+    cases = {"one_ulp": np.nextafter(z0, F32(3)), "two_ulps": np.nextafter(
+        np.nextafter(z0, F32(3)), F32(3)), "equal": z0}
+    rays = oracle.Rays([[0, 0, 0]], [[0, 0, 1]])
+    for name, z1 in cases.items():
+        sc = _scene([[0, 0, z0], [0, 0, z1]], np.zeros((2, 3)), [[1, 0, 0, 0]] * 2,
+                    [_logit(0.5)] * 2)
+        rec = oracle.Records(sc)
+        c = oracle.candidates(rec, [0, 0, 0], [0, 0, 1])
+        assert c["t32"].tolist() == [z0, z1] and c["t"].tolist() == [float(z0), float(z1)]
+        r = oracle.trace(rec, rays, u_override=np.array([0.0, 0.0]))
+        assert r["hit_gid"][0, 0] == 0
+        assert bool(r["flags"][0, 0] & 2) == (name == "one_ulp"), (name, r["flags"])
+        r = oracle.trace(rec, rays, u_override=np.array([0.0, 0.999]))
+        assert r["hit_gid"][0, 0] == 0 and r["flags"][0, 0] == 0, name
+
+
 # --------------------------------------------------------------------------
 # Exact compositing (eqn "accumulated") and convergence of the estimator
 # --------------------------------------------------------------------------
@@ -630,6 +693,92 @@ def test_pathmix_shadow_occlusion_probability():
     assert binomtest(occl, n, float(cand["alpha"][0])).pvalue > 1e-4
 
 
+def _sh_colour_scipy(coef, direction):
+    """max(0, 0.5 + sum_lm k_lm Y_lm(d)) per channel with scipy's harmonics."""
+    dv = np.asarray(direction, np.float64)
+    dv = dv / np.linalg.norm(dv)
+    K = coef.shape[0]
+    deg = int(round(math.sqrt(K))) - 1
+    Y = np.array([_real_sh_scipy(l, m, dv) for l in range(deg + 1) for m in range(-l, l + 1)])
+    return np.maximum(0.0, 0.5 + Y @ coef.astype(np.float64))
+
+
+def _fp32_shading_point(o, d, t):
+    """P = o + (t * d), per component in FP32 (the secondary-ray construction)."""
+    return np.array([F32(F32(o[i]) + F32(F32(t) * F32(d[i]))) for i in range(3)], F32)
+
+
+def _fp32_light_dir(P, light=(5.0, 5.0, 5.0)):
+    v = (np.asarray(light, F32) - P).astype(F32)
+    ln = np.sqrt(F32(F32(F32(v[0] * v[0]) + F32(v[1] * v[1])) + F32(v[2] * v[2])))
+    return (v / ln).astype(F32), F32(ln)
+
+
+def test_pathmix_gaussian_hit_colour_and_self_shadow():
+    """A camera sample that accepts Gaussian A is shaded c_A (0.3 + 0.7 V),
+    c_A its SH colour along the camera ray and V the visibility of the light
+    (Sec. 1 / Sec. 5 secondary rays). The shadow ray starts inside A, where
+    A is a valid candidate of it, yet it must never report A (its spawning
+    Gaussian): with the occluder B switched off, V = 1. With B accepted,
+    V = 0."""
+    rng = np.random.default_rng(17)
+    sh = rng.normal(0, 0.4, (3, 16, 3)).astype(F32)
+    o = np.array([-0.05, 0.0, 4.0], F32)
+    d = np.array([0.0, 0.0, -1.0], F32)
+    # A near the camera ray at depth 2; B straddles the shadow ray 1.0 further on
+    P_est = np.array([-0.05, 0.0, 2.0])
+    l_est = np.array([5.0, 5.0, 5.0]) - P_est
+    l_est /= np.linalg.norm(l_est)
+    B = P_est + 1.0 * l_est
+    C = [5.0, -40.0, 5.0]  # far away, never a candidate
+    sc = _scene([[0.0, 0.0, 2.0], B, C], np.log(np.full((3, 3), 0.1)), [[1, 0, 0, 0]] * 3,
+                [_logit(0.8)] * 3, sh, deg=3)
+    rec = oracle.Records(sc)
+    for V, uB in ((1, 1.0), (0, 0.0)):
+        u = np.array([0.0, uB, 1.0])
+        r = oracle.pathmix(rec, o[None], d[None], spp=1, u_override=u)
+        assert r["cam_gid"][0, 0] == 0 and r["mirror_gid"][0, 0] == -2
+        assert r["shadow_vis"][0, 0] == V
+        cA = _sh_colour_scipy(sh[0], d)
+        np.testing.assert_allclose(r["rgb"][0], cA * (0.3 + 0.7 * V), rtol=1e-12, atol=1e-12)
+    # the precondition that makes the check bite: A is a valid candidate of
+    # the shadow ray it spawns, and B lies on it
+    P = _fp32_shading_point(o, d, r["cam_t"][0, 0])
+    l, ln = _fp32_light_dir(P)
+    cand = oracle.candidates(rec, P, l, tmin=float(F32(1e-4)), tmax=float(ln))
+    assert set(cand["gid"].tolist()) == {0, 1}, cand
+
+
+def test_pathmix_mirror_hit_colour():
+    """A camera ray that reaches the ground plane y = -2.5 spawns a mirror ray
+    along (dx, -dy, dz); the plane point is shaded 0.5 V max(0, l_y) + 0.5 c,
+    c the SH colour of the mirror ray's accepted Gaussian seen along the
+    reflected direction (not the camera's)."""
+    rng = np.random.default_rng(18)
+    sh = rng.normal(0, 0.4, (2, 16, 3)).astype(F32)
+    o = np.array([0.0, 0.0, 4.0], F32)
+    d = (np.array([0.0, -1.0, -0.5]) / math.sqrt(1.25)).astype(F32)
+    tp = F32(F32(F32(-2.5) - o[1]) / d[1])
+    P = _fp32_shading_point(o, d, tp)
+    P[1] = F32(-2.5)
+    md = np.array([d[0], -d[1], d[2]], F32)
+    Cg = P.astype(np.float64) + 2.0 * md
+    sc = _scene([Cg, [5.0, -40.0, 5.0]], np.log(np.full((2, 3), 0.1)), [[1, 0, 0, 0]] * 2,
+                [_logit(0.8)] * 2, sh, deg=3)
+    rec = oracle.Records(sc)
+    bg = np.array([0.05, 0.1, 0.2])
+    for uC, hit in ((0.0, True), (1.0, False)):
+        r = oracle.pathmix(rec, o[None], d[None], spp=1, bg=bg, u_override=np.array([uC, 1.0]))
+        assert r["cam_gid"][0, 0] == -1 and r["shadow_vis"][0, 0] == 1
+        assert r["mirror_gid"][0, 0] == (0 if hit else -1)
+        l, _ = _fp32_light_dir(P)
+        Lm = _sh_colour_scipy(sh[0], md) if hit else bg
+        expect = 0.5 * max(0.0, float(l[1])) + 0.5 * Lm
+        np.testing.assert_allclose(r["rgb"][0], expect, rtol=1e-12, atol=1e-12)
+    # the reflected direction matters: the camera direction would give another colour
+    assert np.abs(_sh_colour_scipy(sh[0], md) - _sh_colour_scipy(sh[0], d)).max() > 0.05
+
+
 # --------------------------------------------------------------------------
 # Centre depth (Sec. 4.1)
 # --------------------------------------------------------------------------
@@ -645,8 +794,7 @@ def test_center_depth_orders_by_projected_centre():
     o, d = [0, 0, 0], [0, 0, 1]
     c_mean = oracle.candidates(rec, o, d)
     assert list(c_mean["gid"]) == [1, 0], c_mean
-    with oracle.depth_mode(1):
-        c_ctr = oracle.candidates(rec, o, d)
+    c_ctr = oracle.candidates(rec, o, d, depth_mode=1)
     assert list(c_ctr["gid"]) == [0, 1]
     np.testing.assert_allclose(c_ctr["t"], [np.float32(1.9), 2.0], rtol=1e-7)
     # alpha stays at the 1D peak: identical in both modes
@@ -655,8 +803,7 @@ def test_center_depth_orders_by_projected_centre():
     # to the ray parameter
     axis = np.array([0.0, 0.6, 0.8])
     d2 = np.array([0.0, 0.05, 1.0], np.float32)
-    with oracle.depth_mode(1, axis):
-        c_ax = oracle.candidates(rec, o, d2)
+    c_ax = oracle.candidates(rec, o, d2, depth_mode=1, depth_axis=axis)
     for g, t in zip(c_ax["gid"], c_ax["t"]):
         mu = rec.mu[g]
         assert abs(t - (mu @ axis) / (d2.astype(np.float64) @ axis)) < 1e-12
