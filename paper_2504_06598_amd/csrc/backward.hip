@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_backward(BwdArgs a, const void* _
             const int32_t ign = a.ign ? a.ign[rq] : -1;
             const uint32_t rid = a.rid ? a.rid[rq] : (uint32_t)rq;
             const uint32_t sbase = (a.sid ? a.sid[rq] : 0u) + a.soff;
-            const Ray rr = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
+            Ray rr = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
             const double tmin = tmin_f, tmax = tmax_f;
             const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rr, a.r_max);
             float Y[16];

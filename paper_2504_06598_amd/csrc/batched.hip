@@ -201,7 +201,7 @@ __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int 
                                          LaneCounts& cnt, bool atomic, float acc[3])
 {
     const int n_act = min(N, b.spp - pass * N);
-    const Ray ray = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
+    Ray ray = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
     const ForwardCtx fc{a.recs, b.purpose, a.k0, a.k1};
     const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, ray, a.r_max);
     float bt[N];
@@ -252,7 +252,7 @@ __device__ __forceinline__ bool wave_pass(const BatchArgs& a, const WideNode<W>*
 {
     const bool live = b.valid && b.tmax > b.tmin;
     const int n_act = live ? min(N, b.spp - pass * N) : 0;
-    const Ray ray = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
+    Ray ray = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
     const ForwardCtx fc{recs, b.purpose, a.k0, a.k1};
     const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, ray, a.r_max);
     float bt[N];

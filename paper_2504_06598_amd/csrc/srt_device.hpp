@@ -229,7 +229,8 @@ struct Ray {
     float ox, oy, oz;
     float dx, dy, dz;
     float ix, iy, iz;  // 1 / d, with |d_i| clamped away from 0
-    float tmin;
+    float tmin;        // boxes exiting before it are culled: the ray's tmin,
+                       // lowered by the depth slack in centre-depth mode
     float inv_dd;      // 1 / |d|^2
     float inv_len;     // 1 / |d|
 };

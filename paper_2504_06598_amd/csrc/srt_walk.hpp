@@ -225,7 +225,9 @@ __device__ __forceinline__ float cut_after(float t)
 // (a = the ray's direction when none is given); the opacity stays at the 1D
 // peak. Because x(t*) lies in the bounding sphere of radius r about mu,
 // |t - t*| <= r / (d . a_hat), so boxes are culled against the cut plus that
-// slack (r = the largest radius in the scene).
+// slack (r = the largest radius in the scene), and a box is kept when it
+// exits after tmin minus that slack: a Gaussian whose centre depth is past
+// tmin can be crossed before tmin.
 struct DepthCtx {
     int mode;         // uniform
     bool own_axis;    // uniform: the axis is each ray's direction
@@ -234,7 +236,8 @@ struct DepthCtx {
     float node_slack; // per ray
 };
 
-__device__ __forceinline__ DepthCtx make_depth(int mode, const float axis[3], const Ray& ray,
+// In mode 1 also lowers ray.tmin (the box-exit bound) by the slack.
+__device__ __forceinline__ DepthCtx make_depth(int mode, const float axis[3], Ray& ray,
                                                float r_max)
 {
     DepthCtx c;
@@ -258,6 +261,7 @@ __device__ __forceinline__ DepthCtx make_depth(int mode, const float axis[3], co
         const double cosd = den / alen;  // d . a_hat
         c.node_slack = cosd > 0.0 ? (float)((double)r_max * (1.0 + 0x1p-12) / cosd) * 1.0001f
                                   : INFINITY;
+        ray.tmin = ray.tmin - c.node_slack;
     }
     return c;
 }

@@ -90,7 +90,7 @@ __device__ __forceinline__ bool trace_ray(const TraceArgs& a, int64_t ray, int32
     const uint32_t sbase = (a.sid ? a.sid[ray] : 0u) + a.soff;
     const bool live = tmax_f > tmin_f;
 
-    const Ray rd = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
+    Ray rd = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
     const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
     const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rd, a.r_max);
     const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __re
     const uint32_t sbase = (a.sid ? a.sid[rr] : 0u) + a.soff;
     const bool live = valid && tmax_f > tmin_f;
 
-    const Ray rd = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
+    Ray rd = make_ray(ox, oy, oz, dx, dy, dz, tmin_f);
     const ForwardCtx fc{recs, a.purpose, a.k0, a.k1};
     const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rd, a.r_max);
     const float slack = DM == 0 ? 0.0f : dc.node_slack;

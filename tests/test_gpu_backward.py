@@ -189,25 +189,40 @@ def test_estimator_is_unbiased_for_the_exact_gradient(srt):
         assert checked >= 1, n
 
 
-def test_backward_center_depth_matches_oracle(srt):
-    say("backward with centre depth vs oracle estimator")
-    sc = tiny_scene(51, 800, (0.03, 0.1), deg=1)
-    cam = si.look_at((0.1, 0.2, 3), (0, 0, 0), 32, 32)
+@pytest.mark.parametrize("inside,walk", [(False, "lane"), (True, "lane"), (True, "wave")])
+def test_backward_center_depth_matches_oracle(srt, inside, walk):
+    """Centre depth (Sec. 4.1) in the backward; inside: a camera in the middle
+    of the cloud with rays starting at random tmin, so Gaussians whose centre
+    depth lies past tmin are crossed before it (their boxes must still be
+    re-traversed)."""
+    say(f"backward with centre depth vs oracle estimator, camera inside {inside}, {walk} walks")
+    sc = tiny_scene(51, 800 if not inside else 2000, (0.03, 0.1), deg=1)
+    if inside:
+        cam = si.look_at((0.05, -0.1, 0.0), (0.3, 0.2, -1.0), 32, 32, vfov_deg=80.0)
+    else:
+        cam = si.look_at((0.1, 0.2, 3), (0, 0, 0), 32, 32)
     o, d = si.camera_rays(cam)
+    tmin = None
+    if inside:
+        tmin = np.random.default_rng(52).uniform(0.0, 1.5, len(o)).astype(np.float32)
+        tmin[::3] = 0.0
     ax = tuple(float(x) for x in cam.forward)
     rec = oracle.Records(sc)
-    ora_f = oracle.trace(rec, oracle.Rays(o, d), spp=4, seed=5, depth_mode=1, depth_axis=ax)
+    rays = oracle.Rays(o, d, tmin)
+    ora_f = oracle.trace(rec, rays, spp=4, seed=5, depth_mode=1, depth_axis=ax)
     dL = np.random.default_rng(8).normal(0, 1, (len(o), 3))
     dL[(ora_f["flags"] != 0).any(1)] = 0.0
-    ora = oracle.estimator_grad(rec, oracle.Rays(o, d), dL.astype(np.float32).astype(np.float64),
+    ora = oracle.estimator_grad(rec, rays, dL.astype(np.float32).astype(np.float64),
                                 spp=4, seed=5, depth_mode=1, depth_axis=ax)
     bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
     oc, dc = _cu(o), _cu(d)
+    tc = None if tmin is None else _cu(tmin)
     fw = srt.srt_trace_forward(bvh, oc, dc, seed=5, spp=4, n_per_traversal=4, depth_mode=1,
-                               depth_axis=ax)
+                               depth_axis=ax, tmin=tc)
     g = srt.srt_trace_backward(bvh, oc, dc, _cu(dL.astype(np.float32)), hit_gid=fw["hit_gid"],
                                hit_t=fw["hit_t"], seed=5, spp=4, n_per_traversal=4,
-                               depth_mode=1, depth_axis=ax)
+                               depth_mode=1, depth_axis=ax, tmin=tc, walk=walk,
+                               image_width=cam.width)
     torch.cuda.synchronize()
     for name in NAMES:
         _close(to_np(g[name]).reshape(ora[name].shape), ora[name], name)

@@ -297,6 +297,55 @@ def test_center_depth_matches_oracle(srt, axis):
     assert (g0["hit_gid"] != g["hit_gid"]).mean() > 0.01
 
 
+@pytest.mark.parametrize("axis,inside,walk", [("camera", False, "lane"),
+                                               ("camera", False, "wave"),
+                                               ("ray", False, "wave"),
+                                               ("camera", True, "lane"),
+                                               ("camera", True, "wave"),
+                                               ("ray", True, "lane")])
+def test_center_depth_with_tmin_matches_oracle(srt, axis, inside, walk):
+    """Centre depth with tmin > 0: a Gaussian whose centre depth lies past
+    tmin but which the ray crosses before tmin is still a candidate, so boxes
+    that the ray leaves before tmin (but not before tmin minus the depth
+    slack) must be walked. Rays start at random tmin in [0, 1.5], and (inside)
+    from a camera in the middle of the cloud."""
+    say(f"centre depth with tmin: axis {axis}, camera inside {inside}, {walk} walks")
+    sc = tiny_scene(43, 3000, (0.02, 0.12), deg=1)
+    if inside:
+        cam = si.look_at((0.05, -0.1, 0.0), (0.3, 0.2, -1.0), 40, 32, vfov_deg=80.0)
+    else:
+        cam = si.look_at((0.3, 0.2, 2.2), (0, 0, 0), 40, 32, vfov_deg=75.0)
+    o, d = si.camera_rays(cam)
+    R = len(o)
+    rng = np.random.default_rng(44)
+    tmin = rng.uniform(0.0, 1.5 if inside else 3.0, R).astype(np.float32)
+    if inside:
+        tmin[::3] = 0.0
+    ax = tuple(float(x) for x in cam.forward) if axis == "camera" else (0.0, 0.0, 0.0)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2)
+    g = _trace(srt, bvh, o, d, seed=9, spp=8, n_per_traversal=4, depth_mode=1, depth_axis=ax,
+               tmin=_cuda(tmin), image_width=cam.width, walk=walk)
+    rays = oracle.Rays(o, d, tmin, None, None)
+    ora = oracle.trace(oracle.Records(sc), rays, spp=8, seed=9, depth_mode=1, depth_axis=ax)
+    compare_ids(g["hit_gid"], ora["hit_gid"], ora["flags"])
+    compare_rgb(g["rgb"], ora["rgb"], ora["flags"])
+    hit = ora["hit_gid"] >= 0
+    assert hit.mean() > 0.2
+    if axis == "camera":
+        # the case the test is about occurs: accepted Gaussians whose exact
+        # k-sigma box the ray leaves before tmin
+        rec = oracle.Records(sc)
+        Minv = np.linalg.inv(rec.M.reshape(-1, 3, 3))
+        h = np.sqrt(8.0 * (Minv ** 2).sum(2))
+        r_idx, s_idx = np.nonzero(hit)
+        gg = ora["hit_gid"][r_idx, s_idx]
+        inv = 1.0 / d[r_idx].astype(np.float64)
+        a = (rec.mu[gg] - h[gg] - o[r_idx]) * inv
+        b = (rec.mu[gg] + h[gg] - o[r_idx]) * inv
+        t_exit = np.maximum(a, b).min(1)
+        assert (t_exit < tmin[r_idx]).sum() > 0
+
+
 @pytest.mark.parametrize("w,h", [(13, 9), (40, 24), (1, 5), (8, 8)])
 def test_image_tiles_change_nothing(srt, w, h):
     say(f"tiled image launch {w}x{h}")
@@ -503,7 +552,9 @@ def test_hash_rng_unsupported_combinations(srt):
     (4, 2, 4, 8, 0, 0, False, False), (4, 2, 1, 1, 0, 0, False, True),
     (4, 2, 1, 3, 0, 3, True, True), (2, 4, 1, 2, 1, 0, False, True),
     (4, 2, 4, 16, 0, 0, True, False), (4, 2, 4, 13, 1, 0, True, False),
-    (2, 4, 4, 7, 0, 3, True, False), (8, 2, 2, 8, 0, 0, True, False)])
+    (2, 4, 4, 7, 0, 3, True, False), (8, 2, 2, 8, 0, 0, True, False),
+    (4, 2, 8, 16, 0, 0, True, False), (4, 2, 8, 16, 1, 0, True, False),
+    (4, 2, 8, 13, 0, 0, True, False)])
 def test_wave_walk_equals_lane_walk(srt, W, L, N, spp, mode, lim, image, any_hit):
     """The 64 rays of a tile (or 64 consecutive rays) walking the BVH together
     reach, per ray, the same candidates as the ray's own walk: outputs equal
@@ -550,10 +601,12 @@ def test_wave_walk_equals_lane_walk(srt, W, L, N, spp, mode, lim, image, any_hit
     assert c["ray_samples"] == int((tmax > tmin).sum()) * spp
     if lim:
         assert c["deep"] > 0
-    if (W, L, N, mode, lim, image) == (4, 2, 4, 0, 0, True):
+    if not any_hit and not lim and (W, L) == (4, 2):
         rays = oracle.Rays(o, d, tmin, tmax, ign, sample_base=np.full(R, 3, np.uint32))
-        ora = oracle.trace(oracle.Records(sc), rays, spp=spp, seed=13)
+        ora = oracle.trace(oracle.Records(sc), rays, spp=spp, seed=13, bg=(0.2, 0.1, 0.7),
+                           depth_mode=mode)
         compare_ids(wave["hit_gid"], ora["hit_gid"], ora["flags"])
+        compare_rgb(wave["rgb"], ora["rgb"], ora["flags"])
 
 
 def test_wave_walk_on_the_four_shell_scene(srt):
