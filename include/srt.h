@@ -287,6 +287,27 @@ srt_status srt_trace_forward(const srt_bvh* bvh, const srt_rays* rays,
                              float* hit_t, uint64_t* counters, void* workspace,
                              size_t workspace_bytes, void* stream);
 
+/* Bytes of the per-device scratch array behind srt_trace_forward_noalloc. */
+#define SRT_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* srt_trace_forward without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and results, with the
+ * scratch taken from a static device array of SRT_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) that each GPU holds until the process ends. Nothing is allocated
+ * or freed by this call. The array's address on a device is looked up once,
+ * at the first call whose stream runs on that device.
+ * Limit: srt_trace_workspace_size(bvh, rays->count) must not exceed
+ * SRT_NOALLOC_SCRATCH_BYTES (about 15M rays on a 1M-Gaussian BVH), else
+ * SRT_ERR_WORKSPACE and nothing is enqueued. Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (different streams, or
+ * threads without ordering) race and give undefined results; calls ordered
+ * on one stream are safe. What must start at zero is cleared by each call.
+ * Arguments and other errors as srt_trace_forward. */
+srt_status srt_trace_forward_noalloc(const srt_bvh* bvh, const srt_rays* rays,
+                                     const srt_trace_opts* opts, float* rgb, int32_t* hit_gid,
+                                     float* hit_t, uint64_t* counters, void* stream);
+
 /* ------------------------------------------------------------------------
  * Backward: gradients of the expected colour (the exact composite of eqn
  * "accumulated") with respect to the raw parameters. The paper names

@@ -216,6 +216,28 @@ def srt_trace_forward(bvh: Bvh, origins, dirs, *, tmin=None, tmax=None, ignore_g
     return res
 
 
+def srt_trace_forward_noalloc(bvh: Bvh, origins, dirs, out, *, tmin=None, tmax=None,
+                              ignore_gid=None, ray_ids=None, sample_ids=None, purpose=0, seed=0,
+                              spp=1, n_per_traversal=1, sample_offset=0, bg=(0.0, 0.0, 0.0),
+                              any_hit=False, stack_limit=0, depth_mode=0,
+                              depth_axis=(0.0, 0.0, 0.0), image_width=0, persistent=False,
+                              refill_threshold=0, walk="auto", counters=None):
+    """srt_trace_forward with the library's static per-device scratch: no
+    workspace and no allocation (the caller passes the outputs in `out`:
+    rgb [R,3] and/or hit_gid, hit_t [R,spp]). Calls that overlap on one GPU
+    race on its scratch."""
+    lib = _lib.load()
+    R = int(origins.shape[0])
+    rays = _lib.SrtRays(R, _ptr(origins), _ptr(dirs), _ptr(tmin), _ptr(tmax), _ptr(ignore_gid),
+                        _ptr(ray_ids), _ptr(sample_ids), int(purpose))
+    opts = _opts(seed, spp, n_per_traversal, sample_offset, bg, any_hit, stack_limit, depth_mode,
+                 depth_axis, image_width, persistent, refill_threshold, walk=walk)
+    _lib.check("srt_trace_forward_noalloc", lib.srt_trace_forward_noalloc(
+        bvh.handle, C.byref(rays), C.byref(opts), _ptr(out.get("rgb")), _ptr(out.get("hit_gid")),
+        _ptr(out.get("hit_t")), _ptr(counters), _stream()))
+    return out
+
+
 def srt_trace_backward(bvh: Bvh, origins, dirs, grad_rgb, *, hit_gid=None, hit_t=None,
                        tmin=None, tmax=None, ignore_gid=None, ray_ids=None, sample_ids=None,
                        purpose=0, seed=0, spp=1, n_per_traversal=1, sample_offset=0,

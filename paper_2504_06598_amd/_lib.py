@@ -10,6 +10,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SRT_LIB_PATH") or os.path.join(_PKG, "libsrt.so")
 
 SRT_NUM_COUNTERS = 8
+NOALLOC_SCRATCH_BYTES = 64 << 20  # SRT_NOALLOC_SCRATCH_BYTES in include/srt.h
 COUNTER_NAMES = ["traversals", "nodes", "prims", "candidates", "philox", "deep", "ray_samples",
                  "lost"]
 
@@ -82,6 +83,9 @@ PROTOTYPES = {
     "srt_trace_forward": (C.c_int, [C.c_void_p, C.POINTER(SrtRays), C.POINTER(SrtTraceOpts),
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_size_t, C.c_void_p]),
+    "srt_trace_forward_noalloc": (C.c_int, [C.c_void_p, C.POINTER(SrtRays),
+                                            C.POINTER(SrtTraceOpts), C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p]),
     "srt_backward_workspace_size": (C.c_size_t, [C.c_void_p, C.c_int64]),
     "srt_trace_backward": (C.c_int, [C.c_void_p, C.POINTER(SrtScene), C.POINTER(SrtRays),
                                      C.POINTER(SrtTraceOpts), C.c_void_p, C.c_void_p,

@@ -18,6 +18,7 @@
 // memory sized by the tree depth.
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "srt_internal.hpp"
 #include "srt_walk.hpp"
@@ -1070,6 +1071,48 @@ PathmixWs pathmix_ws(const srt_bvh* b, int64_t R, int32_t spp, void* base)
     return w;
 }
 
+// Scratch of srt_trace_forward_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends. Host code never uses the array's name
+// as an address; each device's address comes from hipGetSymbolAddress, taken
+// once per device at that device's first call, with the device current.
+}  // namespace
+
+constexpr size_t kStaticScratchBytes = (size_t)SRT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that runs work on `s`.
+srt_status static_scratch(hipStream_t s, void** out)
+{
+    int dev = -1;
+    if (s) {
+        hipDevice_t d = -1;
+        SRT_HIP_TRY(hipStreamGetDevice(s, &d));
+        dev = (int)d;
+    } else {
+        SRT_HIP_TRY(hipGetDevice(&dev));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return SRT_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        SRT_HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) SRT_HIP_TRY(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) SRT_HIP_TRY(hipSetDevice(cur));
+        if (e != hipSuccess || !p) return SRT_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SRT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1093,6 +1136,23 @@ srt_status srt_trace_forward(const srt_bvh* b, const srt_rays* rays, const srt_t
         return SRT_ERR_WORKSPACE;
     return launch_trace(b, rays, opts, rgb, hit_gid, hit_t, counters, workspace,
                         static_cast<hipStream_t>(stream));
+}
+
+srt_status srt_trace_forward_noalloc(const srt_bvh* b, const srt_rays* rays,
+                                     const srt_trace_opts* opts, float* rgb, int32_t* hit_gid,
+                                     float* hit_t, uint64_t* counters, void* stream)
+{
+    if (!b || !rays) return SRT_ERR_INVALID_ARG;
+    const srt_status vs = validate_opts(opts);
+    if (vs != SRT_OK) return vs;
+    if (rays->count < 0 || rays->count > (int64_t)UINT32_MAX) return SRT_ERR_INVALID_ARG;
+    if (rays->count > 0 && (!rays->origins || !rays->dirs)) return SRT_ERR_INVALID_ARG;
+    if (srt_trace_workspace_size(b, rays->count) > kStaticScratchBytes) return SRT_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    const srt_status ss = static_scratch(s, &ws);
+    if (ss != SRT_OK) return ss;
+    return launch_trace(b, rays, opts, rgb, hit_gid, hit_t, counters, ws, s);
 }
 
 srt_status srt_camera_rays(const srt_camera* cam, float* origins, float* dirs, void* stream)

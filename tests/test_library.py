@@ -60,6 +60,14 @@ def test_validation_happens_before_any_device_work(lib):
     lib.srt_destroy_bvh(None)
     cam = _lib.SrtCamera()
     assert lib.srt_camera_rays(C.byref(cam), None, None, None) == 1
+    assert lib.srt_trace_forward_noalloc(None, None, None, None, None, None, None, None) == 1
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    src = open(os.path.join(ROOT, "include", "srt.h")).read()
+    m = re.search(r"#define SRT_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", src)
+    from paper_2504_06598_amd import _lib
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
 
 
 def test_camera_generator_geometry():
