@@ -384,11 +384,29 @@ typedef struct {
     float light[3];
     float plane_y;
     float tmin_secondary;
+    int32_t stages;  /* 0: the whole mix; else the stages to run, a mask of
+                        SRT_PATHMIX_* below. Stages hand their results on
+                        through the workspace: running each stage alone, in
+                        order, with the same arguments and workspace gives
+                        the whole mix's outputs (to time or overlap them). */
 } srt_pathmix_opts;
+
+enum {
+    SRT_PATHMIX_CAMERA = 1,  /* camera rays, their trace, secondary-ray spawning */
+    SRT_PATHMIX_SHADOW = 2,  /* the any-hit shadow rays */
+    SRT_PATHMIX_MIRROR = 4,  /* the mirror rays */
+    SRT_PATHMIX_COMPOSE = 8  /* shading and the outputs */
+};
 
 size_t srt_pathmix_workspace_size(const srt_bvh* bvh, const srt_camera* cam, int32_t spp);
 
 /* Render one camera's path-tracer mix. Camera ray ids are ray_id_base + pixel.
+ * The shadow rays of one pixel whose shading points coincide (the samples
+ * that accepted the same Gaussian, or that all reached the plane) are
+ * identical but for their sample index; with Philox numbers and spp <= 64
+ * each such group is resolved by one walk (a sample is occluded iff one of
+ * the walk's candidates accepts its own number), which gives every sample
+ * the visibility of its own any-hit walk.
  * rgb [H*W,3] device; cam_gid/cam_t [H*W,spp], shadow_vis (uint8: 1 lit,
  * 0 occluded, 255 no shadow ray) [H*W,spp], mirror_gid (-2 no mirror ray,
  * -1 miss) [H*W,spp]: device or null. counters as srt_trace_forward; its
@@ -397,7 +415,7 @@ size_t srt_pathmix_workspace_size(const srt_bvh* bvh, const srt_camera* cam, int
  * wave-shared walks unless opts->walk is 1); the any-hit shadow rays always
  * run on work-stealing waves (see srt_trace_opts.persistent); camera and
  * mirror rays follow opts->persistent.
- * Errors: INVALID_ARG, WORKSPACE, HIP. */
+ * Errors: INVALID_ARG (also pm->stages outside 0..15), WORKSPACE, HIP. */
 srt_status srt_trace_pathmix(const srt_bvh* bvh, const srt_camera* cam, uint32_t ray_id_base,
                              const srt_trace_opts* opts, const srt_pathmix_opts* pm,
                              float* rgb, int32_t* cam_gid, float* cam_t, uint8_t* shadow_vis,

@@ -355,9 +355,11 @@ def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_trav
                       sample_offset=0, bg=(0.0, 0.0, 0.0), light=(5.0, 5.0, 5.0), plane_y=-2.5,
                       tmin_secondary=1e-4, stack_limit=0, persistent=False, refill_threshold=0,
                       rng="philox", walk="auto", want_hits=True, counters=None, workspace=None,
-                      out=None):
+                      out=None, stages=0):
     """Path-tracer mix of one camera; returns dict(rgb [, cam_gid, cam_t,
-    shadow_vis, mirror_gid]). walk applies to the camera rays."""
+    shadow_vis, mirror_gid]). walk applies to the camera rays. stages: 0 for
+    the whole mix, else a mask of PATHMIX_CAMERA/SHADOW/MIRROR/COMPOSE (run
+    in order on the same workspace, they give the whole mix)."""
     lib = _lib.load()
     dev = bvh.scene.means.device
     R = int(cam.width) * int(cam.height)
@@ -369,6 +371,7 @@ def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_trav
         pm.light[i] = float(light[i])
     pm.plane_y = float(plane_y)
     pm.tmin_secondary = float(tmin_secondary)
+    pm.stages = int(stages)
     res = dict(out or {})
     if "rgb" not in res:
         res["rgb"] = torch.empty((R, 3), dtype=torch.float32, device=dev)
@@ -385,6 +388,9 @@ def srt_trace_pathmix(bvh: Bvh, cam, *, ray_id_base=0, seed=0, spp=1, n_per_trav
         _ptr(res.get("cam_gid")), _ptr(res.get("cam_t")), _ptr(res.get("shadow_vis")),
         _ptr(res.get("mirror_gid")), _ptr(counters), _ptr(workspace), need, _stream()))
     return res
+
+
+PATHMIX_CAMERA, PATHMIX_SHADOW, PATHMIX_MIRROR, PATHMIX_COMPOSE = 1, 2, 4, 8
 
 
 class BatchPlan:

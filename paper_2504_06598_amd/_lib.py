@@ -54,7 +54,8 @@ class SrtCamera(C.Structure):
 
 
 class SrtPathmixOpts(C.Structure):
-    _fields_ = [("light", C.c_float * 3), ("plane_y", C.c_float), ("tmin_secondary", C.c_float)]
+    _fields_ = [("light", C.c_float * 3), ("plane_y", C.c_float), ("tmin_secondary", C.c_float),
+                ("stages", C.c_int32)]
 
 
 class SrtBatch(C.Structure):

@@ -30,6 +30,11 @@ struct srt_bvh {
     int32_t* level_nodes = nullptr;
     std::vector<uint32_t> level_off, level_cnt;
     uint32_t* bounds = nullptr;      // [8]
+    // start_node[gid]: the node start_levels levels above the leaf that holds
+    // Gaussian gid (the root when the leaf is shallower); null when absent.
+    // A ray that starts inside that Gaussian can walk this subtree first.
+    int32_t* start_node = nullptr;
+    int32_t start_levels = 0;
     std::vector<std::pair<void*, size_t>> blocks;  // device buffers owned (pointer, bytes)
 };
 

@@ -395,6 +395,47 @@ __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, co
     return false;
 }
 
+// Offer record r to a group of identical any-hit rays that differ only in
+// their sample indices (bit j of `pending`: sample s0 + j still unoccluded).
+// The validity test is fwd_offer's for an any-hit ray with cut tmax; each
+// pending sample then draws its own Philox number (one block per four
+// consecutive samples) and is occluded iff u < alpha. Returns the samples r
+// occludes.
+template <int DM>
+__device__ __forceinline__ uint64_t group_offer(const Record& r, const Ray& ray,
+                                                const DepthCtx& dc, double tmin, double tmax,
+                                                float tcut, int32_t ign, uint32_t rid,
+                                                uint32_t s0, uint64_t pending,
+                                                const ForwardCtx& fc, FwdCounts& cnt)
+{
+    if (depth_mode_of<DM>(dc) == 0) {
+        if (sphere_reject(r, ray, ray.tmin, tcut)) return 0;
+    } else if (sphere_reject(r, ray, -INFINITY, INFINITY)) {
+        return 0;
+    }
+    double tm, q;
+    isect_tq(r, ray, tm, q);
+    const double t = depth_of<DM>(dc, r, ray, tm);
+    if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return 0;
+    ++cnt.cands;
+    const AlphaTest at(r.opacity, q);
+    uint64_t occ = 0, m = pending;
+    uint4 w = make_uint4(0, 0, 0, 0);
+    uint32_t grp = 0xFFFFFFFFu;
+    while (m) {
+        const int j = __builtin_ctzll(m);
+        m &= m - 1;
+        const uint32_t s = s0 + (uint32_t)j;
+        if ((s >> 2) != grp) {
+            grp = s >> 2;
+            w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, fc.purpose), fc.k0, fc.k1);
+            ++cnt.philox;
+        }
+        if (at.accepts(word_of(w, s & 3u))) occ |= 1ull << j;
+    }
+    return occ;
+}
+
 template <int W, int N, bool ANY, class Stack, bool HASH = false, int DM = -1>
 __device__ __forceinline__ int resolve_samples(const WideNode<W>* __restrict__ nodes,
                                                const ForwardCtx& fc, const DepthCtx& dc,

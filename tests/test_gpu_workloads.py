@@ -92,20 +92,27 @@ def test_path_tracer_full_size_sampled(srt):
     assert c["ray_samples"] > R * 16
 
 
-def test_pathmix_many_samples_per_pixel(srt):
-    say("path-tracer mix: 80 spp, N=8, 24x14")
+@pytest.mark.parametrize("spp,N", [(80, 8), (64, 8), (12, 4), (5, 1)])
+def test_pathmix_many_samples_per_pixel(srt, spp, N):
+    """Shadow rays of a pixel are resolved per group of identical rays: with
+    spp dividing 64 (groups found by lane shuffles), with other spp up to 64
+    (one thread per pixel), and per sample above 64."""
+    say(f"path-tracer mix: {spp} spp, N={N}, 24x14")
     w = si.workload(3, small=True)
     cam = si.look_at((0, 0, 4), (0, 0, 0), 24, 14)
-    _pathmix_check(srt, w["scene"], cam, 80, 8, np.arange(24 * 14))
+    _pathmix_check(srt, w["scene"], cam, spp, N, np.arange(24 * 14))
 
 
-def test_pathmix_deep_stack_is_exact(srt):
-    say("path-tracer mix through the deep-stack pass (stack limit 1)")
+@pytest.mark.parametrize("limit", [1, 3])
+def test_pathmix_deep_stack_is_exact(srt, limit):
+    """A shadow-ray group whose stack overflows reruns each of its samples in
+    the deep pass (limit 3: some groups finish on chip, others overflow)."""
+    say(f"path-tracer mix through the deep-stack pass (stack limit {limit})")
     w = si.workload(3, small=True)
     cam = si.look_at((0.3, -0.2, 4), (0, 0, 0), 48, 27)
     bvh = srt.srt_build_bvh(device_scene(w["scene"]), 4, 2)
     out = []
-    for lim in (0, 1):
+    for lim in (0, limit):
         cnt = srt.new_counters()
         res = srt.srt_trace_pathmix(bvh, cam, seed=3, spp=8, n_per_traversal=4, sample_offset=5,
                                     light=si.LIGHT_POS, plane_y=si.PLANE_Y,
@@ -117,3 +124,33 @@ def test_pathmix_deep_stack_is_exact(srt):
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
     assert cb["deep"] > 0 and cb["lost"] == 0 and ca["deep"] == 0
+
+
+def test_pathmix_stages_run_alone_equal_the_whole_mix(srt):
+    """The mix's stages (camera, shadow, mirror, compose) run as separate
+    calls on one workspace give the whole mix's outputs bit for bit."""
+    say("path-tracer mix stage by stage")
+    w = si.workload(3, small=True)
+    cam = si.look_at((0.2, -0.1, 4), (0, 0, 0), 40, 24)
+    bvh = srt.srt_build_bvh(device_scene(w["scene"]), 4, 2)
+    kw = dict(seed=6, spp=16, n_per_traversal=8, light=si.LIGHT_POS, plane_y=si.PLANE_Y,
+              tmin_secondary=si.SECONDARY_TMIN)
+    whole = srt.srt_trace_pathmix(bvh, cam, **kw)
+    import ctypes as C
+    lib = srt._lib.load()
+    ws = torch.empty(lib.srt_pathmix_workspace_size(bvh.handle, C.byref(srt._camera(cam)), 16),
+                     dtype=torch.uint8, device="cuda")
+    R = cam.width * cam.height
+    out = dict(rgb=torch.full((R, 3), -1.0, device="cuda"),
+               cam_gid=torch.full((R, 16), -9, dtype=torch.int32, device="cuda"),
+               cam_t=torch.zeros((R, 16), device="cuda"),
+               shadow_vis=torch.zeros((R, 16), dtype=torch.uint8, device="cuda"),
+               mirror_gid=torch.full((R, 16), -9, dtype=torch.int32, device="cuda"))
+    for st in (srt.PATHMIX_CAMERA, srt.PATHMIX_SHADOW, srt.PATHMIX_MIRROR, srt.PATHMIX_COMPOSE):
+        srt.srt_trace_pathmix(bvh, cam, out=out, workspace=ws, stages=st, **kw)
+    torch.cuda.synchronize()
+    for k in whole:
+        np.testing.assert_array_equal(to_np(out[k]), to_np(whole[k]), err_msg=k)
+    with pytest.raises(srt.SrtError) as e:
+        srt.srt_trace_pathmix(bvh, cam, out=out, workspace=ws, stages=16, **kw)
+    assert e.value.code == 1
