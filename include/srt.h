@@ -119,6 +119,19 @@ typedef struct {
 srt_status srt_build_bvh(const srt_scene* scene, const srt_build_opts* opts, void* stream,
                          srt_bvh** out);
 
+/* Cap the device memory the library holds in use for BVH handles and build
+ * temporaries (bytes; 0 removes the cap). An allocation that would exceed
+ * it fails with SRT_ERR_OOM before anything is enqueued, as a failed
+ * hipMalloc does; memory already held is not freed. Blocks the library
+ * keeps for reuse (up to 8 GiB, per device and size class) do not count.
+ * Batch plans and caller workspaces are not covered. Process-wide.
+ * Errors: INVALID_ARG (bytes < 0). */
+srt_status srt_set_memory_limit(int64_t bytes);
+
+/* Bytes the library holds in use (handles and running builds) and keeps
+ * for reuse; either pointer may be null, not both (INVALID_ARG). */
+srt_status srt_memory_stats(int64_t* in_use, int64_t* cached);
+
 /* Refit a handle to new parameters of the same Gaussians (an optimisation
  * step, Sec. 7's differentiable-rendering use): the records and Gaussian
  * boxes are recomputed from `scene` exactly as srt_build_bvh computes them,

@@ -35,7 +35,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (IEEE FP64, no contraction, OpenMP)."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.tmp{os.getpid()}"  # concurrent test workers each write their own
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
                                "-ffp-contract=off", "-fno-fast-math", "-Wall",
                                "-o", tmp, _SRC, "-lm"])
@@ -43,12 +43,26 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(path: str) -> str:
+    """The oracle compiled with AddressSanitizer and UndefinedBehaviorSanitizer
+    (abort on the first report), for running its tests with gcc's libasan
+    preloaded and SRT_ORACLE_LIB pointing here."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                           "-ffp-contract=off", "-fno-fast-math", "-Wall",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", "-o", path, _SRC, "-lm"])
+    return path
+
+
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        _lib = C.CDLL(_LIB)
+        path = os.environ.get("SRT_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        _lib = C.CDLL(path)
         _lib.srto_accept_u.restype = C.c_double
         _lib.srto_candidates.restype = C.c_int64
         _lib.srto_isect_one.restype = C.c_int

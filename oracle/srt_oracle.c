@@ -510,7 +510,7 @@ int64_t srto_candidates(int64_t G, const double* mu, const double* M, const doub
     int64_t n = 0;
     for (int64_t i = 0; i < cl.n; ++i)
         if (cl.v[i].valid) cl.v[n++] = cl.v[i];
-    qsort(cl.v, (size_t)n, sizeof(cand_t), cmp_cand);
+    if (n > 1) qsort(cl.v, (size_t)n, sizeof(cand_t), cmp_cand); /* v may be null when n = 0 */
     int64_t m = n < cap ? n : cap;
     for (int64_t i = 0; i < m; ++i) {
         t[i] = cl.v[i].t;
@@ -544,7 +544,7 @@ static void sorted_build(sorted_t* S, const depth_t* dm, int64_t G, const double
     for (int64_t i = 0; i < S->cl.n; ++i)
         if (S->cl.v[i].valid) S->cl.v[n++] = S->cl.v[i];
     S->cl.n = n;
-    qsort(S->cl.v, (size_t)n, sizeof(cand_t), cmp_cand);
+    if (n > 1) qsort(S->cl.v, (size_t)n, sizeof(cand_t), cmp_cand); /* v may be null when n = 0 */
     S->c = (double*)realloc(S->c, (size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
     S->pre = (double*)realloc(S->pre, (size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
     for (int64_t k = 0; k < n; ++k)

@@ -118,6 +118,19 @@ class Bvh:
 DEFAULT_SIZE_SPLIT = 0
 
 
+def srt_set_memory_limit(nbytes: int) -> None:
+    """Cap the device bytes the library holds for BVH handles and build
+    temporaries (0: no cap); a build beyond it raises SrtError (OOM)."""
+    _lib.check("srt_set_memory_limit", _lib.load().srt_set_memory_limit(int(nbytes)))
+
+
+def srt_memory_stats() -> dict:
+    """Device bytes the library holds in use and keeps for reuse."""
+    a, b = C.c_int64(), C.c_int64()
+    _lib.check("srt_memory_stats", _lib.load().srt_memory_stats(C.byref(a), C.byref(b)))
+    return {"in_use": a.value, "cached": b.value}
+
+
 def srt_build_bvh(scene: DeviceScene, width: int = 4, leaf_size: int = 4,
                   size_split: int = DEFAULT_SIZE_SPLIT) -> Bvh:
     lib = _lib.load()

@@ -75,6 +75,8 @@ PROTOTYPES = {
     "srt_build_bvh": (C.c_int, [C.POINTER(SrtScene), C.POINTER(SrtBuildOpts), C.c_void_p,
                                 C.POINTER(C.c_void_p)]),
     "srt_destroy_bvh": (None, [C.c_void_p]),
+    "srt_set_memory_limit": (C.c_int, [C.c_int64]),
+    "srt_memory_stats": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "srt_refit_bvh": (C.c_int, [C.c_void_p, C.POINTER(SrtScene), C.c_void_p]),
     "srt_bvh_get_info": (C.c_int, [C.c_void_p, C.POINTER(SrtBvhInfo)]),
     "srt_bvh_records": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

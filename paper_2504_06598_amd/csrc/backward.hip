@@ -679,6 +679,7 @@ srt_status srt_trace_backward(const srt_bvh* b, const srt_scene* scene, const sr
                               float* g_sh, uint64_t* counters, void* workspace,
                               size_t workspace_bytes, void* stream)
 {
+    const srt::Range range_("srt_trace_backward");
     if (!b || !rays || !opts || !scene) return SRT_ERR_INVALID_ARG;
     if (opts->spp < 1 || opts->any_hit) return SRT_ERR_INVALID_ARG;
     if (opts->depth_mode != 0 && opts->depth_mode != 1) return SRT_ERR_INVALID_ARG;

@@ -854,6 +854,7 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
                                  const srt_trace_opts* opts, const srt_tuning* tuning, void* stream,
                                  srt_batch_plan** out)
 {
+    const srt::Range range_("srt_batch_plan_create");
     if (!b || !batch || !opts || !tuning || !out) return SRT_ERR_INVALID_ARG;
     *out = nullptr;
     const int N = opts->n_per_traversal;
@@ -976,6 +977,7 @@ srt_status srt_batch_plan_info(const srt_batch_plan* p, int64_t* rows, int64_t* 
 srt_status srt_batch_plan_execute(srt_batch_plan* p, float* rgb, int32_t* hit_gid,
                                   uint64_t* counters, void* stream)
 {
+    const srt::Range range_("srt_batch_plan_execute");
     if (!p || (!rgb && p->rows > 0)) return SRT_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!p->exec || p->g_rgb != rgb || p->g_hits != hit_gid || p->g_counters != counters) {

@@ -504,11 +504,14 @@ __global__ void k_unpermute_records(int64_t G, const Record* __restrict__ recs, 
 // build has synchronised its stream, a handle's buffers at destroy (whose
 // contract says no work on the handle is pending). Blocks are kept per
 // device and size class (64 KiB granules) up to 8 GiB in total; more is
-// freed at once.
+// freed at once. An optional limit caps the bytes in use (handed out and not
+// returned); a request beyond it fails as out of memory.
 struct BlockCache {
     std::mutex mu;
     std::map<std::pair<int, size_t>, std::vector<void*>> free_blocks;
     size_t kept = 0;
+    size_t in_use = 0;
+    size_t limit = 0;  // 0: none
     static constexpr size_t kGranule = size_t(1) << 16;
     static constexpr size_t kMaxKept = size_t(8) << 30;
 
@@ -522,6 +525,8 @@ struct BlockCache {
         if (e != hipSuccess) return e;
         {
             std::lock_guard<std::mutex> lock(mu);
+            if (limit > 0 && in_use + sz > limit) return hipErrorOutOfMemory;
+            in_use += sz;  // reserved before the allocation
             auto it = free_blocks.find({dev, sz});
             if (it != free_blocks.end() && !it->second.empty()) {
                 *p = it->second.back();
@@ -530,13 +535,22 @@ struct BlockCache {
                 return hipSuccess;
             }
         }
-        return hipMalloc(p, sz);
+        e = hipMalloc(p, sz);
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lock(mu);
+            in_use -= sz;
+        }
+        return e;
     }
 
     void put(void* p, size_t bytes)
     {
         if (!p) return;
         const size_t sz = round(bytes);
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            in_use -= std::min(in_use, sz);
+        }
         int dev = 0;
         if (hipGetDevice(&dev) == hipSuccess) {
             std::lock_guard<std::mutex> lock(mu);
@@ -865,9 +879,29 @@ const char* srt_status_str(srt_status s)
 
 int32_t srt_version(void) { return 10000; }
 
+srt_status srt_set_memory_limit(int64_t bytes)
+{
+    if (bytes < 0) return SRT_ERR_INVALID_ARG;
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    c.limit = (size_t)bytes;
+    return SRT_OK;
+}
+
+srt_status srt_memory_stats(int64_t* in_use, int64_t* cached)
+{
+    if (!in_use && !cached) return SRT_ERR_INVALID_ARG;
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (in_use) *in_use = (int64_t)c.in_use;
+    if (cached) *cached = (int64_t)c.kept;
+    return SRT_OK;
+}
+
 srt_status srt_build_bvh(const srt_scene* sc, const srt_build_opts* opts, void* stream,
                          srt_bvh** out)
 {
+    const srt::Range range_("srt_build_bvh");
     if (!sc || !opts || !out) return SRT_ERR_INVALID_ARG;
     *out = nullptr;
     const int64_t G = sc->num_gaussians;
@@ -909,6 +943,7 @@ void srt_destroy_bvh(srt_bvh* b)
 
 srt_status srt_refit_bvh(srt_bvh* b, const srt_scene* sc, void* stream)
 {
+    const srt::Range range_("srt_refit_bvh");
     if (!b || !sc) return SRT_ERR_INVALID_ARG;
     if (sc->num_gaussians != b->G || sc->sh_degree != b->deg) return SRT_ERR_INVALID_ARG;
     if (b->G > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))

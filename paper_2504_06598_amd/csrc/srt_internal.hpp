@@ -8,6 +8,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "srt.h"
 #include "srt_device.hpp"
 
@@ -39,6 +41,15 @@ struct srt_bvh {
 };
 
 namespace srt {
+
+// A roctx range over a host call (it covers the enqueueing, shown on the CPU
+// timeline of `rocprofv3 --marker-trace`); free when no tool listens.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 #define SRT_HIP_TRY(expr)                              \
     do {                                               \

@@ -1480,6 +1480,7 @@ srt_status srt_trace_forward(const srt_bvh* b, const srt_rays* rays, const srt_t
                              float* rgb, int32_t* hit_gid, float* hit_t, uint64_t* counters,
                              void* workspace, size_t workspace_bytes, void* stream)
 {
+    const srt::Range range_("srt_trace_forward");
     if (!b || !rays) return SRT_ERR_INVALID_ARG;
     const srt_status vs = validate_opts(opts);
     if (vs != SRT_OK) return vs;
@@ -1495,6 +1496,7 @@ srt_status srt_trace_forward_noalloc(const srt_bvh* b, const srt_rays* rays,
                                      const srt_trace_opts* opts, float* rgb, int32_t* hit_gid,
                                      float* hit_t, uint64_t* counters, void* stream)
 {
+    const srt::Range range_("srt_trace_forward_noalloc");
     if (!b || !rays) return SRT_ERR_INVALID_ARG;
     const srt_status vs = validate_opts(opts);
     if (vs != SRT_OK) return vs;
@@ -1530,6 +1532,7 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
                              int32_t* mirror_gid, uint64_t* counters, void* workspace,
                              size_t workspace_bytes, void* stream)
 {
+    const srt::Range range_("srt_trace_pathmix");
     if (!b || !cam || !pm || !rgb) return SRT_ERR_INVALID_ARG;
     const srt_status vs = validate_opts(opts);
     if (vs != SRT_OK) return vs;
@@ -1551,6 +1554,7 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
     srt_status st = SRT_OK;
 
     if (stages & SRT_PATHMIX_CAMERA) {
+        const Range r("srt_trace_pathmix: camera rays");
         k_camera_rays<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(*cam, w.co, w.cd);
         SRT_HIP_TRY(hipGetLastError());
         srt_rays cr{};
@@ -1589,6 +1593,7 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
                                         // choice gives lane walks
     for (int pass = 0; pass < 2; ++pass) {
         if (!(stages & (pass == 0 ? SRT_PATHMIX_SHADOW : SRT_PATHMIX_MIRROR))) continue;
+        const Range r(pass == 0 ? "srt_trace_pathmix: shadow rays" : "srt_trace_pathmix: mirror rays");
         const SecRays& sr = pass == 0 ? w.sh : w.mr;
         srt_rays rr{};
         rr.count = n;

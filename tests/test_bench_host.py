@@ -52,10 +52,10 @@ def test_summariser_scales_counters_by_the_calibration_copy(tmp_path, capsys):
     d.mkdir()
     rows = []
     disp = 0
+    copy = "at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add<float> >"
     for name, fetch, write, hit, miss in [("void k_shadow_persist<4, false, 0>(...)", 100.0,
                                            50.0, 90.0, 10.0)] * 3 + \
-                                          [("at::elementwise_kernel<add>", 131072.0, 262144.0,
-                                            1.0, 1.0)]:
+                                          [(copy, 131072.0, 262144.0, 1.0, 1.0)]:
         disp += 1
         for cn, cv in (("FETCH_SIZE", fetch), ("WRITE_SIZE", write), ("TCC_HIT_sum", hit),
                        ("TCC_MISS_sum", miss)):

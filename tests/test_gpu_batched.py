@@ -142,6 +142,34 @@ def test_graph_replays_equal_eager(srt, setup):
         torch.cuda.synchronize()
 
 
+def test_graph_recaptured_for_new_output_pointers(srt, setup):
+    """A call with other output pointers re-captures the plan's graph: every
+    buffer it is given, in turn and back again, receives the eager result,
+    and the buffers it is no longer given stay untouched."""
+    s = setup
+    say("graph re-capture when the output pointers change")
+    plan = _plan(srt, s, persistent=True)
+    e_rgb, e_hits, _ = _run(plan, eager=True)
+    bufs = [(torch.empty((plan.rows, 3), device="cuda"),
+             torch.empty(plan.samples, dtype=torch.int32, device="cuda")) for _ in range(3)]
+    cnt = srt.new_counters()
+    for i in (0, 1, 2, 1, 0):
+        for r, h in bufs:
+            r.fill_(55.0)
+            h.fill_(-9)
+        rgb, hit = bufs[i]
+        # the counters pointer alternates too (None, then a buffer)
+        plan.execute(rgb=rgb, hit_gid=hit, counters=cnt if i % 2 else None)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(hit), e_hits), i
+        np.testing.assert_allclose(to_np(rgb), e_rgb, atol=2e-6, rtol=1e-5)
+        for j, (r, h) in enumerate(bufs):
+            if j != i:
+                assert (to_np(h) == -9).all() and (to_np(r) == 55.0).all(), (i, j)
+    c = srt.counters_dict(cnt)
+    assert c["ray_samples"] == 2 * plan.samples and c["lost"] == 0
+
+
 def test_deep_stack_and_widths(srt, setup):
     s = setup
     say("batched deep-stack fallback and BVH widths")

@@ -146,3 +146,36 @@ def test_fit_recovers_perturbed_scene(srt, estimator):
     assert np.all(np.isfinite(losses))
     assert after < 0.35 * before
     assert err1 < 0.8 * err0
+
+
+def test_memory_limit_forces_out_of_memory(srt):
+    """A cap on the library's device memory makes a build fail with
+    SRT_ERR_OOM, at its first allocation or part-way through, with everything
+    it had taken returned; without the cap the same build succeeds."""
+    import gc
+    say("memory limit: builds fail with SRT_ERR_OOM and return their blocks")
+    sc = tiny_scene(71, 3000)
+    dsc = device_scene(sc)
+    gc.collect()
+    base = srt.srt_memory_stats()["in_use"]
+    bvh = srt.srt_build_bvh(dsc, 4, 2)
+    full = srt.srt_memory_stats()["in_use"] - base
+    assert full > 0
+    del bvh
+    gc.collect()
+    assert srt.srt_memory_stats()["in_use"] == base
+    try:
+        for cap in (base + 1, base + full // 2):
+            srt.srt_set_memory_limit(cap)
+            with pytest.raises(srt.SrtError) as e:
+                srt.srt_build_bvh(dsc, 4, 2)
+            assert e.value.code == 2, cap
+            assert srt.srt_memory_stats()["in_use"] == base, cap
+    finally:
+        srt.srt_set_memory_limit(0)
+    bvh = srt.srt_build_bvh(dsc, 4, 2)
+    o = torch.tensor([[0.0, 0.0, 3.0]] * 64, device="cuda")
+    d = torch.tensor([[0.0, 0.0, -1.0]] * 64, device="cuda")
+    res = srt.srt_trace_forward(bvh, o, d, spp=2, n_per_traversal=2)
+    torch.cuda.synchronize()
+    assert res["hit_gid"].shape == (64, 2)

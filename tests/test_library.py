@@ -61,6 +61,13 @@ def test_validation_happens_before_any_device_work(lib):
     cam = _lib.SrtCamera()
     assert lib.srt_camera_rays(C.byref(cam), None, None, None) == 1
     assert lib.srt_trace_forward_noalloc(None, None, None, None, None, None, None, None) == 1
+    # the memory cap and its statistics are host state
+    assert lib.srt_set_memory_limit(-1) == 1
+    assert lib.srt_memory_stats(None, None) == 1
+    used, cached = C.c_int64(-1), C.c_int64(-1)
+    assert lib.srt_memory_stats(C.byref(used), C.byref(cached)) == 0
+    assert used.value >= 0 and cached.value >= 0
+    assert lib.srt_set_memory_limit(1 << 20) == 0 and lib.srt_set_memory_limit(0) == 0
 
 
 def test_noalloc_scratch_size_matches_the_header():
