@@ -62,9 +62,9 @@ def parse():
     p.add_argument("--kernel-launches", type=int, default=5)
     p.add_argument("--no-batched", action="store_true",
                    help="skip the persistent-vs-plain measurement on the batched workload")
-    p.add_argument("--batched-scale", type=int, default=16,
+    p.add_argument("--batched-scale", type=int, default=1,
                    help="run the batched workload at 1/k of its pixels and incoherent rays")
-    p.add_argument("--batched-reps", type=int, default=3)
+    p.add_argument("--batched-reps", type=int, default=1)
     p.add_argument("--no-multisample", action="store_true",
                    help="skip the N = 1 vs N = 4 comparison on the object-like scene")
     p.add_argument("--profile-kernels", action="store_true",
@@ -666,11 +666,17 @@ def summarize_profiles(args):
 
 
 def bench_batched(args, srt, si, torch, dev):
-    """Persistent vs plain on the batched scene (64 views of 512x512 with
-    their spp, 4M incoherent rays), at 1/k of the pixels (views of 512/sqrt(k)
-    pixels a side, the same spp per view) and 1/k of the incoherent rays with
-    --batched-scale k (1: the full workload); the autotuner picks its
-    configuration on 8 of those views and 1/8 of those rays."""
+    """Persistent vs plain on the batched scene: 64 views of 512x512 with
+    their spp and 4M incoherent rays in one graph launch (with
+    --batched-scale k: 1/k of the pixels, views of 512/sqrt(k) pixels a side
+    with the same spp, and 1/k of the incoherent rays). The autotuner sweeps
+    width {2,4,8} x leaf size {1,2,4,8} (size split 4: Gaussians more than 16x
+    apart in size in subtrees of their own, 2x faster than none on this scene)
+    x refill threshold {16,32,48} on a subsample that keeps the workload's
+    coherence and mix: every 16th view at full resolution with its spp, and
+    the incoherent rays in the same proportion to the camera samples; each
+    kind then runs the workload at its pick, one warm-up launch and
+    --batched-reps timed launches."""
     from paper_2504_06598_amd.autotune import autotune
     t0 = time.perf_counter()
     w = si.workload(5)
@@ -679,19 +685,24 @@ def bench_batched(args, srt, si, torch, dev):
     side = int(round(512 / k ** 0.5))
     cams = si.fibonacci_cameras(len(w["cameras"]), 3.0, side, side)
     spp = w["spp"]
-    n_inc = w["incoherent"][0].shape[0] // k
+    n_all = w["incoherent"][0].shape[0]
+    n_inc = n_all // k
     eo, ed = (torch.from_numpy(x[:n_inc]).to(dev) for x in w["incoherent"])
+    del w
     print(f"# batched workload: {sc.num_gaussians} Gaussians, {len(cams)} views {side}x{side}, "
           f"{n_inc} incoherent rays (generated in {time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
-    sub = slice(0, None, 8)
-    tune = autotune(sc, cams[sub], spp[sub], extra_origins=eo[: n_inc // 8],
-                    extra_dirs=ed[: n_inc // 8], extra_spp=1, seed=si.PHILOX_SEED,
-                    widths=(4, 8), leaves=(2, 4), splits=(0, 4), thresholds=(16, 32, 48),
-                    waves=(4, 8), reps=1, use_cache=False, cache_path=None,
+    sub = slice(0, None, 16)
+    tcams = si.fibonacci_cameras(len(cams), 3.0, 512, 512)[sub]
+    n_t = max(1, int(round(n_all * sum(spp[sub]) / sum(spp))))
+    t1 = time.perf_counter()
+    tune = autotune(sc, tcams, spp[sub], extra_origins=eo[:n_t], extra_dirs=ed[:n_t],
+                    extra_spp=1, seed=si.PHILOX_SEED, widths=(2, 4, 8), leaves=(1, 2, 4, 8),
+                    splits=(4,), thresholds=(16, 32, 48), waves=(8,), reps=1,
+                    use_cache=False, cache_path=None,
                     log=lambda r: print("# tune", r, file=sys.stderr, flush=True))
-    print(f"# autotuner: persistent {tune['persistent']}, plain {tune['plain']}, rejected "
-          f"{tune['rejected']}", file=sys.stderr, flush=True)
+    print(f"# autotuner ({time.perf_counter() - t1:.1f} s): persistent {tune['persistent']}, "
+          f"plain {tune['plain']}, rejected {tune['rejected']}", file=sys.stderr, flush=True)
     res = {}
     for kind in ("plain", "persistent"):
         cfg = tune[kind]
@@ -707,28 +718,28 @@ def bench_batched(args, srt, si, torch, dev):
         torch.cuda.synchronize()
         c = srt.counters_dict(cnt)
         assert c["ray_samples"] == plan.samples and c["lost"] == 0
-        start = torch.cuda.Event(enable_timing=True)
-        stop = torch.cuda.Event(enable_timing=True)
-        start.record()
-        for _ in range(args.batched_reps):
-            plan.execute(rgb=rgb, counters=cnt)
-        stop.record()
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(stop) / args.batched_reps
+        print(f"# batched {kind}: warm-up launch done", file=sys.stderr, flush=True)
+        ms = ev_time(torch, lambda: plan.execute(rgb=rgb), args.batched_reps)
+        tr = max(c["traversals"], 1)
         res[kind] = {"mrays_per_s": round(plan.samples / (ms * 1e-3) / 1e6, 2),
                      "ms_per_launch": round(ms, 3), "width": cfg["width"],
                      "leaf_size": cfg["leaf_size"], "size_split": cfg["size_split"],
                      "refill_threshold": cfg["refill_threshold"],
-                     "waves_per_cu": cfg["waves_per_cu"]}
+                     "waves_per_cu": cfg["waves_per_cu"],
+                     "per_traversal": {"nodes": round(c["nodes"] / tr, 1),
+                                       "records": round(c["prims"] / tr, 1),
+                                       "candidates": round(c["candidates"] / tr, 1),
+                                       "philox": round(c["philox"] / tr, 1)}}
         print(f"# batched {kind}: {ms:.2f} ms per launch, {res[kind]['mrays_per_s']} Mrays/s",
               file=sys.stderr, flush=True)
         res["ray_samples_per_launch"] = int(plan.samples)
-        del plan, bvh
+        del plan, bvh, rgb
     res["speedup"] = round(res["persistent"]["mrays_per_s"] / res["plain"]["mrays_per_s"], 3)
     scale = "full size" if k == 1 else f"1/{k} of the pixels and incoherent rays"
     res["workload"] = (f"3.3M Gaussians (3M object-like + 300k large diffuse); 64 views on a "
                        f"Fibonacci sphere at {side}x{side}, spp per view from {{1,...,64}}; "
                        f"{n_inc} incoherent rays; N=4; one graph launch ({scale})")
+    res["autotune_configs"] = len(tune["table"])
     return res
 
 

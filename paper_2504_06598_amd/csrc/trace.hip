@@ -1140,41 +1140,52 @@ __global__ __launch_bounds__(256) void k_shadow_groups_wave(int64_t n, SecRays s
     }
 }
 
-// Work-stealing waves over the groups (the scheme of k_trace_persist): a lane
-// walks one group's ray, one node or one leaf per iteration. `a` describes
-// the per-sample shadow rays (spp 1, any-hit); hit_gid of each occluded
-// sample receives the Gaussian that occluded it, -1 if none did. A group
-// whose stack overflows queues each of its samples for the deep pass.
-// Registers capped for 5 waves per SIMD at W <= 4 (121 -> 96 VGPRs, no
-// spills; 1.6 % faster on the 1M mix).
+// Work-stealing waves over the groups (the refill scheme of k_trace_persist),
+// with the record tests taken off the lanes' walks. A lane walks one group's
+// ray. Each iteration every walking lane hands up to two records of the leaf
+// it is at to a wave-wide queue in LDS, then takes one node step; the wave
+// then tests the queued records one per lane, reading the owner's ray from
+// the owner's registers with lane shuffles, and occludes samples of the
+// owner's group through a per-lane mask in LDS (64-bit LDS atomics). So the
+// node code and the record code do not run for different lanes of one step
+// one after the other, and a leaf's records are tested side by side.
+// `a` describes the per-sample shadow rays (spp 1, any-hit); hit_gid of each
+// occluded sample receives a Gaussian that occluded it, -1 if none did. A
+// group whose stack overflows queues each of its samples for the deep pass.
 template <int W, bool COUNT, int DM>
-__global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 5) void k_shadow_persist(TraceArgs a,
-                                                                                 ShadowGroups g)
+__global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 4) void k_shadow_queue(TraceArgs a,
+                                                                                ShadowGroups g)
 {
-    __shared__ int32_t lds[LdsStack<W>::value * kPersistBlock];
+    constexpr int kRecPerStep = 2;
+    constexpr int kStack = LdsStack<W>::value;
+    __shared__ int32_t lds[kStack * kPersistBlock];
+    __shared__ uint32_t q_rec[kPersistBlock * kRecPerStep];
+    __shared__ uint8_t q_lane[kPersistBlock * kRecPerStep];
+    __shared__ unsigned long long s_pend[kPersistBlock];
     const int lane = threadIdx.x;
-    const int cap = min(LdsStack<W>::value, a.stack_cap);
+    const int cap = min(kStack, a.stack_cap);
     const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
     const int64_t n_items = (int64_t)*g.count;
-    const int64_t spp = g.spp;
+    const uint32_t spp = (uint32_t)g.spp;
     Counts cnt;
 
-    bool active = false, exhausted = false;
-    int64_t pix = 0;
-    uint64_t all = 0, pend = 0;
+    bool active = false, walking = false, exhausted = false;
+    uint32_t pix = 0;
+    uint64_t all = 0;
     float tmin_f = 0.0f, tmax_f = 0.0f;
     int32_t ign = -1;
     uint32_t rid = 0;
-    Ray lr;
-    DepthCtx dc;
-    int32_t node = 0;
-    int32_t skip = -1;  // a subtree already walked (second phase), else -1
+    Ray lr = make_ray(0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f);
+    DepthCtx dc = make_depth(0, a.depth_axis, lr, a.r_max);
+    int32_t node = 0, skip = -1;
     bool phase2 = true;
     int sp = 0;
     int64_t steps = 0;
     const ForwardCtx fc{a.recs, a.purpose, a.k0, a.k1};
+    s_pend[lane] = 0;
 
     for (;;) {
+        // ---- refill idle lanes (wave-uniform decision) ----
         const unsigned long long idle = __ballot(!active);
         const int n_idle = __popcll(idle);
         if (n_idle == 64 && exhausted) break;
@@ -1189,8 +1200,9 @@ __global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 5) void k_shadow_persis
                 const int64_t it = (int64_t)(base + (unsigned long long)__popcll(below));
                 if (it < n_items) {
                     const int64_t ray = g.rep[it];
-                    all = pend = g.mask[it];
-                    pix = ray / spp;
+                    all = g.mask[it];
+                    s_pend[lane] = all;
+                    pix = (uint32_t)(ray / spp);
                     tmin_f = a.tmin[ray];
                     tmax_f = a.tmax[ray];
                     ign = a.ign[ray];
@@ -1205,89 +1217,160 @@ __global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 5) void k_shadow_persis
                     skip = phase2 ? -1 : node;
                     sp = 0;
                     steps = 0;
-                    active = true;
+                    active = walking = true;
                     ++cnt.trav;
                 }
             }
         }
-        if (!active) continue;
+        __syncthreads();
 
-        bool done = false, overflow = false;
-        if (++steps > a.max_steps) {
-            overflow = true;
-        } else if (node >= 0) {
-            ++cnt.nodes;
-            NodeBuf<W> nb;
-            load_node<W>(nodes, node, nb);
-            uint32_t key[W];
-            slab_keys<W>(nb, lr, tmax_f + (DM == 0 ? 0.0f : dc.node_slack), key);
-            if (phase2 && skip >= 0) {
+        // ---- one step of every walking lane: the records of the leaf it is
+        // at go to the queue (two at a time), then it takes one node step ----
+        uint32_t q_first = 0;
+        int q_n = 0;
+        if (active && walking) {
+            bool ended = false;
+            if (s_pend[lane] == 0) {
+                walking = false;  // every sample occluded
+            } else if (++steps > a.max_steps) {
+                ended = true;
+            } else {
+                if (node < 0) {
+                    const uint32_t first = leaf_first(node), count = leaf_count(node);
+                    q_first = first;
+                    q_n = (int)min(count, (uint32_t)kRecPerStep);
+                    if (count > (uint32_t)q_n) {
+                        node = make_leaf(first + (uint32_t)q_n, count - (uint32_t)q_n);
+                    } else if (sp > 0) {
+                        --sp;
+                        node = lds[sp * kPersistBlock + lane];
+                    } else if (!phase2) {
+                        phase2 = true;
+                        node = 0;
+                    } else {
+                        walking = false;
+                    }
+                }
+                if (walking && node >= 0) {
+                    ++cnt.nodes;
+                    NodeBuf<W> nb;
+                    load_node<W>(nodes, node, nb);
+                    uint32_t key[W];
+                    slab_keys<W>(nb, lr, tmax_f + (DM == 0 ? 0.0f : dc.node_slack), key);
+                    if (phase2 && skip >= 0) {
 #pragma unroll
-                for (int c = 0; c < W; ++c)
-                    if (nb.n.child[c] == skip) key[c] = 0xFFFFFFFFu;
-            }
-            sort_keys<W>(key);
-            int nh = 0;
+                        for (int c = 0; c < W; ++c)
+                            if (nb.n.child[c] == skip) key[c] = 0xFFFFFFFFu;
+                    }
+                    sort_keys<W>(key);
+                    int nh = 0;
 #pragma unroll
-            for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
-            if (nh > 0) {
-                if (sp + nh - 1 > cap) {
-                    overflow = true;
-                } else {
+                    for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
+                    if (nh > 0) {
+                        if (sp + nh - 1 > cap) {
+                            ended = true;
+                        } else {
 #pragma unroll
-                    for (int c = W - 1; c >= 1; --c)
-                        if (key[c] != 0xFFFFFFFFu) {
-                            lds[sp * kPersistBlock + lane] = child_at<W>(nb, key[c] & 7u);
-                            ++sp;
+                            for (int c = W - 1; c >= 1; --c)
+                                if (key[c] != 0xFFFFFFFFu) {
+                                    lds[sp * kPersistBlock + lane] = child_at<W>(nb, key[c] & 7u);
+                                    ++sp;
+                                }
+                            node = child_at<W>(nb, key[0] & 7u);
                         }
-                    node = child_at<W>(nb, key[0] & 7u);
+                    } else if (sp > 0) {
+                        --sp;
+                        node = lds[sp * kPersistBlock + lane];
+                    } else if (!phase2) {
+                        phase2 = true;
+                        node = 0;
+                    } else {
+                        walking = false;
+                    }
                 }
-            } else if (sp == 0) {
-                done = true;
-            } else {
-                --sp;
-                node = lds[sp * kPersistBlock + lane];
             }
-        } else {
-            const uint32_t first = leaf_first(node), count = leaf_count(node);
-            FwdCounts fcnt;
-            for (uint32_t i = 0; i < count && pend; ++i) {
+            if (ended) {
+                // stack or step bound exceeded: the deep pass reruns every
+                // sample of the group on its own (the leaf records queued in
+                // this step are dropped with the mask)
+                for (uint64_t m = all; m; m &= m - 1) {
+                    const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+                    a.ovf_list[slot] = pix * spp + (uint32_t)__builtin_ctzll(m);
+                }
+                s_pend[lane] = 0;
+                active = walking = false;
+            }
+        }
+
+        // ---- queue the records (wave prefix sum of the counts) ----
+        int incl = q_n;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, 63, 64);
+        for (int i = 0; i < q_n; ++i) {
+            q_rec[incl - q_n + i] = q_first + (uint32_t)i;
+            q_lane[incl - q_n + i] = (uint8_t)lane;
+        }
+        __syncthreads();
+
+        // ---- test the queued records, one per lane ----
+        for (int b0 = 0; b0 < total; b0 += 64) {
+            const int e = b0 + lane;
+            const bool has = e < total;
+            const int owner = has ? (int)q_lane[e] : lane;
+            const float rox = __shfl(lr.ox, owner, 64), roy = __shfl(lr.oy, owner, 64),
+                        roz = __shfl(lr.oz, owner, 64);
+            const float rdx = __shfl(lr.dx, owner, 64), rdy = __shfl(lr.dy, owner, 64),
+                        rdz = __shfl(lr.dz, owner, 64);
+            const float r_cull = __shfl(lr.tmin, owner, 64);
+            const float r_idd = __shfl(lr.inv_dd, owner, 64);
+            const float r_il = __shfl(lr.inv_len, owner, 64);
+            const float r_tmin = __shfl(tmin_f, owner, 64), r_tmax = __shfl(tmax_f, owner, 64);
+            const int32_t r_ign = __shfl(ign, owner, 64);
+            const uint32_t r_rid = (uint32_t)__shfl((int32_t)rid, owner, 64);
+            const uint32_t r_pix = (uint32_t)__shfl((int32_t)pix, owner, 64);
+            double r_den = 0.0;
+            if (DM != 0) r_den = __shfl(dc.inv_den, owner, 64);
+            if (has) {
                 ++cnt.prims;
-                const Record r = load_record(a.recs, first + i);
-                const uint64_t occ = group_offer<DM>(r, lr, dc, (double)tmin_f, (double)tmax_f,
-                                                     tmax_f, ign, rid, a.soff, pend, fc, fcnt);
-                if (occ) {
-                    pend &= ~occ;
-                    for (uint64_t m = occ; m; m &= m - 1)
-                        a.hit_gid[pix * spp + __builtin_ctzll(m)] = r.gid;
+                Ray rr;
+                rr.ox = rox; rr.oy = roy; rr.oz = roz;
+                rr.dx = rdx; rr.dy = rdy; rr.dz = rdz;
+                rr.ix = rr.iy = rr.iz = 0.0f;  // not used by the record test
+                rr.tmin = r_cull;
+                rr.inv_dd = r_idd;
+                rr.inv_len = r_il;
+                DepthCtx rdc = dc;
+                rdc.inv_den = r_den;
+                const uint64_t pend_o = s_pend[owner];
+                if (pend_o) {
+                    const Record rec = load_record(a.recs, q_rec[e]);
+                    FwdCounts fcnt;
+                    const uint64_t occ =
+                        group_offer<DM>(rec, rr, rdc, (double)r_tmin, (double)r_tmax, r_tmax,
+                                        r_ign, r_rid, a.soff, pend_o, fc, fcnt);
+                    cnt.cands += fcnt.cands;
+                    cnt.philox += fcnt.philox;
+                    if (occ) {
+                        const uint64_t old = atomicAnd(&s_pend[owner], ~occ);
+                        for (uint64_t m = old & occ; m; m &= m - 1)
+                            a.hit_gid[(int64_t)r_pix * spp + __builtin_ctzll(m)] = rec.gid;
+                    }
                 }
             }
-            cnt.cands += fcnt.cands;
-            cnt.philox += fcnt.philox;
-            if (!pend || sp == 0) {
-                done = true;
-            } else {
-                --sp;
-                node = lds[sp * kPersistBlock + lane];
-            }
         }
-        if (done && pend && !phase2) {
-            done = false;
-            phase2 = true;
-            node = 0;
-            sp = 0;
-        }
-        if (overflow) {
-            // the deep pass reruns every sample of the group on its own
-            for (uint64_t m = all; m; m &= m - 1) {
-                const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
-                a.ovf_list[slot] = (uint32_t)(pix * spp + __builtin_ctzll(m));
-            }
-            active = false;
-        } else if (done) {
-            for (uint64_t m = pend; m; m &= m - 1) a.hit_gid[pix * spp + __builtin_ctzll(m)] = -1;
+        __syncthreads();
+
+        // ---- finish lanes whose walk ended or whose samples are all occluded ----
+        if (active && (!walking || s_pend[lane] == 0)) {
+            for (uint64_t m = s_pend[lane]; m; m &= m - 1)
+                a.hit_gid[(int64_t)pix * spp + __builtin_ctzll(m)] = -1;
             cnt.samples += (uint32_t)__popcll(all);
-            active = false;
+            s_pend[lane] = 0;
+            active = walking = false;
         }
     }
     if (COUNT && a.counters) {
@@ -1305,7 +1388,7 @@ using KernelFnG = void (*)(TraceArgs, ShadowGroups);
 template <int W, int DM>
 KernelFnG shadow_fn_w(bool count)
 {
-    return count ? k_shadow_persist<W, true, DM> : k_shadow_persist<W, false, DM>;
+    return count ? k_shadow_queue<W, true, DM> : k_shadow_queue<W, false, DM>;
 }
 
 KernelFnG pick_shadow(int W, bool count, int depth_mode)

@@ -256,3 +256,49 @@ def test_differentiation_recipe_full_size(srt):
             if checked == 2:
                 break
         assert checked >= 1, n
+
+
+def test_batched_workload_full_size_sampled(srt):
+    """The batched workload at its stated size (3.3M Gaussians, 64 views of
+    512x512 with spp drawn per view, 4M incoherent rays) in one persistent
+    graph launch: ids of 96 sampled camera pixels and 96 sampled incoherent
+    rays against the oracle, every view's spp included."""
+    w = si.workload(5)
+    sc = w["scene"]
+    cams, spp = w["cameras"], w["spp"]
+    eo, ed = w["incoherent"]
+    say(f"batched workload at full size: {sc.num_gaussians} Gaussians, {len(cams)} views "
+        f"{cams[0].width}x{cams[0].height}, {len(eo)} incoherent rays")
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2, 4)
+    plan = srt.srt_batch_plan_create(bvh, cams, spp, extra_origins=_cu(eo), extra_dirs=_cu(ed),
+                                     extra_spp=1, seed=si.PHILOX_SEED, n_per_traversal=4,
+                                     persistent=True, refill_threshold=32, waves_per_cu=8)
+    hits = torch.empty(plan.samples, dtype=torch.int32, device="cuda")
+    cnt = srt.new_counters()
+    rgb = plan.execute(hit_gid=hits, counters=cnt)
+    torch.cuda.synchronize()
+    c = srt.counters_dict(cnt)
+    assert c["ray_samples"] == plan.samples and c["lost"] == 0
+    hits = to_np(hits)
+    rgb = to_np(rgb)
+    rec = oracle.Records(sc)
+    rng = np.random.default_rng(105)
+    R = cams[0].width * cams[0].height
+    row_base = np.arange(len(cams)) * R
+    hit_base = np.concatenate([[0], np.cumsum([R * s for s in spp])])
+    for v in rng.choice(len(cams), 12, replace=False):
+        px = np.sort(rng.choice(R, 8, replace=False))
+        o, d = si.camera_rays(cams[v])
+        ora = oracle.trace(rec, oracle.Rays(o[px], d[px], ray_id=row_base[v] + px),
+                           spp=spp[v], seed=si.PHILOX_SEED)
+        g = hits[hit_base[v]:hit_base[v + 1]].reshape(R, spp[v])[px]
+        compare_ids(g, ora["hit_gid"], ora["flags"], max_flag_frac=5e-3,
+                    what=f"view {v} ({spp[v]} spp)")
+        compare_rgb(rgb[row_base[v] + px], ora["rgb"], ora["flags"])
+    rows0 = len(cams) * R
+    ri = np.sort(rng.choice(len(eo), 96, replace=False))
+    ora = oracle.trace(rec, oracle.Rays(eo[ri], ed[ri], ray_id=rows0 + ri), spp=1,
+                       seed=si.PHILOX_SEED, purpose=4)
+    compare_ids(hits[hit_base[-1] + ri][:, None], ora["hit_gid"], ora["flags"],
+                max_flag_frac=5e-3, what="incoherent rays")
+    compare_rgb(rgb[rows0 + ri], ora["rgb"], ora["flags"])
