@@ -218,7 +218,8 @@ def kernel_specs(st, bvh, k=0):
                    lambda c: st.camera_trace(bvh, k, c),
                    # nodes, records; per sample its (id, depth) written; per pixel its ray
                    lambda c: graph_bytes(c) + c["ray_samples"] * 8 + R * 24),
-        "shadow": ("k_shadow_persist<" + str(W) + "> shadow-ray groups (work-stealing waves)",
+        "shadow": ("k_shadow_queue<" + str(W) + "> shadow-ray groups (work-stealing waves, "
+                   "records tested from a wave-wide queue)",
                    lambda: st.pathmix(bvh, k, None, stages=st.srt.PATHMIX_CAMERA),
                    lambda c: st.pathmix(bvh, k, c, stages=st.srt.PATHMIX_SHADOW),
                    # nodes, records; per group its entry (12 B) and ray (40 B); per
@@ -579,7 +580,7 @@ def profile_kernels(st):
 
 # kernel-name patterns of the --profile-kernels launches (the last 3 matching
 # dispatches of each are the measured ones)
-PROFILE_PATTERNS = {"camera": ("k_trace_wave<4, 8,",), "shadow": ("k_shadow_persist",),
+PROFILE_PATTERNS = {"camera": ("k_trace_wave<4, 8,",), "shadow": ("k_shadow_queue",),
                     "ring_forward": ("k_trace_wave<4, 4,",), "backward": ("k_backward",),
                     "calibration": ("CUDAFunctorOnSelf_add",)}
 
@@ -665,6 +666,12 @@ def summarize_profiles(args):
             json.dump(full, fh, indent=1)
 
 
+# samples per traversal in the batched launch: in this scene's fog of large
+# Gaussians a traversal tests ~10k records whatever its N, so N = 8 halves the
+# traversals of views with 8 or more spp (camera items 3.5 -> 2.1 s at full size)
+BATCH_N = 8
+
+
 def bench_batched(args, srt, si, torch, dev):
     """Persistent vs plain on the batched scene: 64 views of 512x512 with
     their spp and 4M incoherent rays in one graph launch (with
@@ -697,7 +704,8 @@ def bench_batched(args, srt, si, torch, dev):
     n_t = max(1, int(round(n_all * sum(spp[sub]) / sum(spp))))
     t1 = time.perf_counter()
     tune = autotune(sc, tcams, spp[sub], extra_origins=eo[:n_t], extra_dirs=ed[:n_t],
-                    extra_spp=1, seed=si.PHILOX_SEED, widths=(2, 4, 8), leaves=(1, 2, 4, 8),
+                    extra_spp=1, seed=si.PHILOX_SEED, n_per_traversal=BATCH_N,
+                    widths=(2, 4, 8), leaves=(1, 2, 4, 8),
                     splits=(4,), thresholds=(16, 32, 48), waves=(8,), reps=1,
                     use_cache=False, cache_path=None,
                     log=lambda r: print("# tune", r, file=sys.stderr, flush=True))
@@ -708,7 +716,8 @@ def bench_batched(args, srt, si, torch, dev):
         cfg = tune[kind]
         bvh = srt.srt_build_bvh(sc, cfg["width"], cfg["leaf_size"], cfg["size_split"])
         plan = srt.srt_batch_plan_create(bvh, cams, spp, extra_origins=eo, extra_dirs=ed,
-                                         extra_spp=1, seed=si.PHILOX_SEED, n_per_traversal=4,
+                                         extra_spp=1, seed=si.PHILOX_SEED,
+                                         n_per_traversal=BATCH_N,
                                          persistent=cfg["persistent"],
                                          refill_threshold=cfg["refill_threshold"],
                                          waves_per_cu=cfg["waves_per_cu"])
@@ -738,7 +747,7 @@ def bench_batched(args, srt, si, torch, dev):
     scale = "full size" if k == 1 else f"1/{k} of the pixels and incoherent rays"
     res["workload"] = (f"3.3M Gaussians (3M object-like + 300k large diffuse); 64 views on a "
                        f"Fibonacci sphere at {side}x{side}, spp per view from {{1,...,64}}; "
-                       f"{n_inc} incoherent rays; N=4; one graph launch ({scale})")
+                       f"{n_inc} incoherent rays; N={BATCH_N}; one graph launch ({scale})")
     res["autotune_configs"] = len(tune["table"])
     return res
 

@@ -53,7 +53,7 @@ def test_summariser_scales_counters_by_the_calibration_copy(tmp_path, capsys):
     rows = []
     disp = 0
     copy = "at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add<float> >"
-    for name, fetch, write, hit, miss in [("void k_shadow_persist<4, false, 0>(...)", 100.0,
+    for name, fetch, write, hit, miss in [("void k_shadow_queue<4, false, 0>(...)", 100.0,
                                            50.0, 90.0, 10.0)] * 3 + \
                                           [(copy, 131072.0, 262144.0, 1.0, 1.0)]:
         disp += 1
@@ -62,7 +62,7 @@ def test_summariser_scales_counters_by_the_calibration_copy(tmp_path, capsys):
             rows.append({"Dispatch_Id": disp, "Kernel_Name": name, "Counter_Name": cn,
                          "Counter_Value": cv})
     _write_csv(d / "run_counter_collection.csv", rows)
-    trace = [{"Kernel_Name": "void k_shadow_persist<4, false, 0>(...)", "Start_Timestamp": 0,
+    trace = [{"Kernel_Name": "void k_shadow_queue<4, false, 0>(...)", "Start_Timestamp": 0,
               "End_Timestamp": 2_000_000}]
     _write_csv(d / "run_kernel_trace.csv", trace)
     out = tmp_path / "rec.json"
