@@ -1003,6 +1003,10 @@ __global__ void k_compose(int64_t R, int32_t spp, int32_t deg, const float* __re
     sh_eval(deg, dx / n, dy / n, dz / n, Yc);
     sh_eval(deg, dx / n, -dy / n, dz / n, Ym);
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    // a pixel's samples often shade the same Gaussian: the last colour of
+    // each kind is kept (the same inputs give the same bits)
+    int32_t last_g = -1, last_m = -1;
+    float3 col_g = make_float3(0.0f, 0.0f, 0.0f), col_m = col_g;
     for (int32_t s = 0; s < spp; ++s) {
         const int64_t i = p * spp + s;
         const bool has_shadow = shr.tmax[i] > shr.tmin[i];
@@ -1014,13 +1018,24 @@ __global__ void k_compose(int64_t R, int32_t spp, int32_t deg, const float* __re
             const float V = sh_hit[i] < 0 ? 1.0f : 0.0f;
             vis = sh_hit[i] < 0 ? 1 : 0;
             if (!has_mirror) {
-                const float3 c = clamp0(sh_colour_pre(sh, deg, cam_gid[i], Yc));
+                const int32_t g = cam_gid[i];
+                if (g != last_g) {
+                    col_g = clamp0(sh_colour_pre(sh, deg, g, Yc));
+                    last_g = g;
+                }
+                const float3 c = col_g;
                 const float f = 0.3f + 0.7f * V;
                 c0 = c.x * f; c1 = c.y * f; c2 = c.z * f;
             } else {
                 float3 Lm = make_float3(bg0, bg1, bg2);
                 mg = mr_hit[i];
-                if (mg >= 0) Lm = clamp0(sh_colour_pre(sh, deg, mg, Ym));
+                if (mg >= 0) {
+                    if (mg != last_m) {
+                        col_m = clamp0(sh_colour_pre(sh, deg, mg, Ym));
+                        last_m = mg;
+                    }
+                    Lm = col_m;
+                }
                 const float nl = fmaxf(shr.d[3 * i + 1], 0.0f);
                 const float lit = 0.5f * V * nl;
                 c0 = lit + 0.5f * Lm.x; c1 = lit + 0.5f * Lm.y; c2 = lit + 0.5f * Lm.z;
@@ -1103,11 +1118,16 @@ __global__ __launch_bounds__(256) void k_shadow_groups(int64_t R, SecRays sh, Sh
 
 // The same groups when spp divides 64: one thread per sample, a pixel's
 // samples in consecutive lanes of one wave, keys compared by lane shuffles;
-// the first sample of each group stores it. A block's groups are stored
-// contiguously (pixel order) at an offset taken with one atomic per block.
-__global__ __launch_bounds__(256) void k_shadow_groups_wave(int64_t n, SecRays sh, ShadowGroups g)
+// the first sample of each group stores it. A block's groups (1024 samples)
+// are stored contiguously (pixel order) at an offset taken with one atomic
+// per block.
+constexpr int kGroupBlock = 1024;
+
+__global__ __launch_bounds__(kGroupBlock) void k_shadow_groups_wave(int64_t n, SecRays sh,
+                                                                   ShadowGroups g)
 {
-    __shared__ uint32_t wave_n[4], wave_base[4];
+    constexpr int kWaves = kGroupBlock / 64;
+    __shared__ uint32_t wave_n[kWaves], wave_base[kWaves];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int spp = g.spp;
@@ -1125,12 +1145,12 @@ __global__ __launch_bounds__(256) void k_shadow_groups_wave(int64_t n, SecRays s
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kWaves; ++k) {
             wave_base[k] = tot;
             tot += wave_n[k];
         }
         const uint32_t b0 = tot ? atomicAdd(g.count, tot) : 0u;
-        for (int k = 0; k < 4; ++k) wave_base[k] += b0;
+        for (int k = 0; k < kWaves; ++k) wave_base[k] += b0;
     }
     __syncthreads();
     if (leader) {
@@ -1471,7 +1491,8 @@ srt_status build_shadow_groups(int64_t R, int32_t spp, const PathmixWs& w, hipSt
     const ShadowGroups g{w.grp_rep, w.grp_mask, w.grp_count, spp};
     if (64 % spp == 0) {
         const int64_t n = R * spp;
-        k_shadow_groups_wave<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, w.sh, g);
+        k_shadow_groups_wave<<<(unsigned)((n + kGroupBlock - 1) / kGroupBlock), kGroupBlock, 0,
+                               s>>>(n, w.sh, g);
     } else {
         k_shadow_groups<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(R, w.sh, g);
     }
