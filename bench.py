@@ -268,7 +268,8 @@ def measure_kernels(st, bvh, launches, profiles):
             e["hbm_bytes"] = int(p["hbm_bytes_per_launch"])
             e["hbm_gbs"] = round(p["hbm_bytes_per_launch"] / (ms * 1e-3) / 1e9, 2)
             e["hbm_frac"] = round(e["hbm_gbs"] / HBM_PEAK_GBS, 5)
-            for k in ("l2_hit_rate", "valu_insts", "salu_insts", "valu_busy", "salu_busy"):
+            for k in ("l2_hit_rate", "valu_insts", "salu_insts", "valu_busy", "salu_busy",
+                      "valu_lanes_active"):
                 if k in p:
                     e[k] = p[k]
         res[name] = e
@@ -360,7 +361,7 @@ def main():
                            "time; not measured HBM traffic",
             "algorithmic_bytes_per_launch": d["algorithmic_bytes"],
             "per_traversal": d["per_traversal"]}
-    for k in ("hbm_gbs", "hbm_frac", "l2_hit_rate"):
+    for k in ("hbm_gbs", "hbm_frac", "l2_hit_rate", "valu_busy", "valu_lanes_active"):
         if k in d:
             roof[k] = d[k]
     print(f"# dominant kernel: {dom} ({d['ms']:.3f} ms)", file=sys.stderr, flush=True)
@@ -650,6 +651,12 @@ def summarize_profiles(args):
         for k, kk in (("SQ_INSTS_VALU", "valu_insts"), ("SQ_INSTS_SALU", "salu_insts")):
             if k in avg:
                 e[kk] = int(avg[k])
+        # derived metrics in percent: time the vector / scalar ALUs are busy,
+        # lanes active per vector instruction
+        for k, kk in (("VALUBusy", "valu_busy"), ("SALUBusy", "salu_busy"),
+                      ("VALUUtilization", "valu_lanes_active")):
+            if k in avg:
+                e[kk] = round(avg[k], 1)
         if name in out:
             e["ms"] = out[name]["ms"]
             e["kernel_name"] = out[name]["kernel_name"]

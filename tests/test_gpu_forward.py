@@ -593,6 +593,18 @@ def test_wave_walk_equals_lane_walk(srt, W, L, N, spp, mode, lim, image, any_hit
         hi = np.repeat(tmax[:, None], spp, 1)
         assert np.all((t[hit] > lo[hit]) & (t[hit] < hi[hit]))
         assert np.all(wave["hit_gid"][hit] != np.repeat(ign[:, None], spp, 1)[hit])
+        # each reported id is a valid candidate of the ray that its sample's
+        # own number accepts (u < alpha), whichever accepted one the walk met
+        rec = oracle.Records(sc)
+        for r_, k_ in np.argwhere(hit)[:: max(1, int(hit.sum()) // 200)]:
+            gid = int(wave["hit_gid"][r_, k_])
+            cands = oracle.candidates(rec, o[r_], d[r_], tmin=float(tmin[r_]),
+                                      tmax=float(tmax[r_]), ignore_gid=int(ign[r_]),
+                                      depth_mode=mode)
+            pos = np.nonzero(cands["gid"] == gid)[0]
+            assert len(pos) == 1, (r_, k_, gid)
+            u = oracle.accept_u(13, r_, 3 + k_, gid)
+            assert u < cands["alpha"][pos[0]] + 1e-9, (r_, k_, gid, u)
     else:
         for k in ("hit_gid", "hit_t", "rgb"):
             np.testing.assert_array_equal(wave[k], lane[k], err_msg=k)
