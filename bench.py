@@ -65,6 +65,11 @@ def parse():
     p.add_argument("--batched-scale", type=int, default=1,
                    help="run the batched workload at 1/k of its pixels and incoherent rays")
     p.add_argument("--batched-reps", type=int, default=1)
+    p.add_argument("--batched-only", action="store_true",
+                   help="run only the persistent-vs-plain measurement and print its record")
+    p.add_argument("--batched-config", metavar="W,L,THRESHOLD,WAVES",
+                   help="skip the autotuner: both kinds at this tree (size split 4), the "
+                        "persistent one at this refill threshold and workgroups per CU")
     p.add_argument("--no-multisample", action="store_true",
                    help="skip the N = 1 vs N = 4 comparison on the object-like scene")
     p.add_argument("--profile-kernels", action="store_true",
@@ -294,6 +299,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda:0"
+    if args.batched_only:
+        print(json.dumps({"persistent_vs_plain": bench_batched(args, srt, si, torch, dev)}))
+        return
     st = Step(args, srt, si, torch, dev)
     print(f"# workload: {st.sc_host.num_gaussians} Gaussians, {st.cam.width}x{st.cam.height}, "
           f"{st.spp} spp, N={st.N}, W={args.width}, L={args.leaf}", file=sys.stderr, flush=True)
@@ -686,11 +694,15 @@ def bench_batched(args, srt, si, torch, dev):
     with the same spp, and 1/k of the incoherent rays). The autotuner sweeps
     width {2,4,8} x leaf size {1,2,4,8} (size split 4: Gaussians more than 16x
     apart in size in subtrees of their own, 2x faster than none on this scene)
-    x refill threshold {16,32,48} on a subsample that keeps the workload's
-    coherence and mix: every 16th view at full resolution with its spp, and
+    x refill threshold {16,32} x workgroups per CU {8,12} (each persistent
+    grid capped at what its kernel keeps resident) on a subsample that keeps
+    the workload's
+    coherence and mix: every 8th view in order of spp, at full resolution, and
     the incoherent rays in the same proportion to the camera samples; each
     kind then runs the workload at its pick, one warm-up launch and
     --batched-reps timed launches."""
+    import numpy as np
+
     from paper_2504_06598_amd.autotune import autotune
     t0 = time.perf_counter()
     w = si.workload(5)
@@ -706,18 +718,32 @@ def bench_batched(args, srt, si, torch, dev):
     print(f"# batched workload: {sc.num_gaussians} Gaussians, {len(cams)} views {side}x{side}, "
           f"{n_inc} incoherent rays (generated in {time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
-    sub = slice(0, None, 16)
-    tcams = si.fibonacci_cameras(len(cams), 3.0, 512, 512)[sub]
-    n_t = max(1, int(round(n_all * sum(spp[sub]) / sum(spp))))
+    # every 8th view in order of spp: the tuning launch keeps the workload's
+    # spp mix and so its passes per sample (a pass of N samples costs about
+    # the same whatever its number of active samples)
+    order = np.argsort(np.asarray(spp), kind="stable")
+    sub = sorted(int(i) for i in order[4::8])
+    full_cams = si.fibonacci_cameras(len(cams), 3.0, 512, 512)
+    tcams = [full_cams[i] for i in sub]
+    tspp = [spp[i] for i in sub]
+    n_t = max(1, int(round(n_all * sum(tspp) / sum(spp))))
     t1 = time.perf_counter()
-    tune = autotune(sc, tcams, spp[sub], extra_origins=eo[:n_t], extra_dirs=ed[:n_t],
-                    extra_spp=1, seed=si.PHILOX_SEED, n_per_traversal=BATCH_N,
-                    widths=(2, 4, 8), leaves=(1, 2, 4, 8),
-                    splits=(4,), thresholds=(16, 32, 48), waves=(8,), reps=1,
-                    use_cache=False, cache_path=None,
-                    log=lambda r: print("# tune", r, file=sys.stderr, flush=True))
-    print(f"# autotuner ({time.perf_counter() - t1:.1f} s): persistent {tune['persistent']}, "
-          f"plain {tune['plain']}, rejected {tune['rejected']}", file=sys.stderr, flush=True)
+    if args.batched_config:
+        W, L, thr, wpc = (int(x) for x in args.batched_config.split(","))
+        base = {"width": W, "leaf_size": L, "size_split": 4, "refill_threshold": thr,
+                "waves_per_cu": wpc}
+        tune = {"persistent": dict(base, persistent=True),
+                "plain": dict(base, persistent=False), "table": []}
+    else:
+        tune = autotune(sc, tcams, tspp, extra_origins=eo[:n_t], extra_dirs=ed[:n_t],
+                        extra_spp=1, seed=si.PHILOX_SEED, n_per_traversal=BATCH_N,
+                        widths=(2, 4, 8), leaves=(1, 2, 4, 8),
+                        splits=(4,), thresholds=(16, 32), waves=(8, 12), reps=1,
+                        use_cache=False, cache_path=None,
+                        log=lambda r: print("# tune", r, file=sys.stderr, flush=True))
+        print(f"# autotuner ({time.perf_counter() - t1:.1f} s): persistent "
+              f"{tune['persistent']}, plain {tune['plain']}, rejected {tune['rejected']}",
+              file=sys.stderr, flush=True)
     res = {}
     for kind in ("plain", "persistent"):
         cfg = tune[kind]

@@ -453,14 +453,17 @@ typedef struct {
 } srt_batch;
 
 /* Launch shape. persistent = 1: the work-stealing kernel (a grid of
- * waves_per_cu one-wave workgroups per compute unit; a wave claims new items
- * once at least refill_threshold of its 64 lanes are idle); persistent = 0:
- * the plain kernel, one lane per ray. With opts->walk != 1 the views' pixels
- * use wave-shared walks of 8x8 tiles instead: persistent, a wave first
- * refills its lanes with extra rays while any are left, then claims one
- * (tile, pass) group of 64 items per atomic; plain, one wave per tile. The extra rays
- * always walk one lane per ray. Results do not depend on the choice (colours
- * up to the order of the persistent kernel's FP32 atomic additions). */
+ * waves_per_cu one-wave workgroups per compute unit, capped at the number
+ * the kernel keeps resident; a wave claims new items once at least
+ * refill_threshold of its 64 lanes are idle, and the records of the leaves
+ * its lanes reach are tested one per lane from a queue in LDS);
+ * persistent = 0: the plain kernel, one lane per ray. With opts->walk != 1
+ * the views' pixels use wave-shared walks of 8x8 tiles instead: persistent,
+ * the extra rays run first on the work-stealing kernel, then a second
+ * persistent grid claims one (tile, pass) group of 64 items per atomic;
+ * plain, one wave per tile. The extra rays always walk one lane per ray.
+ * Results do not depend on the choice (colours up to the order of the
+ * persistent kernels' FP32 atomic additions). */
 typedef struct {
     int32_t persistent;
     int32_t refill_threshold;  /* 1..64 */

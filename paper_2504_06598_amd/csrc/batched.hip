@@ -10,12 +10,14 @@
 // Two kernels compute the same per-sample results:
 //  * plain: one lane per ray (pixel or extra ray), looping over its passes;
 //  * persistent: a grid sized to the machine; every wave keeps stepping its
-//    lanes' traversals one node or leaf at a time, and whenever at least
+//    lanes' traversals one node at a time, and whenever at least
 //    `refill_threshold` of its 64 lanes are idle it claims that many new items
 //    with a single atomic on a global counter (ballot + prefix count hand them
 //    out), so lanes whose rays finish early are refilled instead of idling
-//    until the longest ray of the wave is done. Colour accumulates into the
-//    image with FP32 atomics (each item adds its samples' colours / spp).
+//    until the longest ray of the wave is done. The records of the leaves the
+//    lanes reach go to a wave-wide queue in LDS and are tested one per lane.
+//    Colour accumulates into the image with FP32 atomics (each item adds its
+//    samples' colours / spp).
 // With wave-shared walks (srt_trace_opts.walk != 1) the camera pixels go to
 // tile kernels instead: plain, one wave per 8x8 tile looping over its
 // passes; persistent, each wave first joins the lane refilling for the extra
@@ -400,28 +402,53 @@ __device__ __forceinline__ void decode_item(const BatchArgs& a, int64_t item, in
     }
 }
 
+// Records a walking lane hands to the wave's queue per step.
+constexpr int kQueueRecs = 8;
+
+// Lane stack entries of the queued lane refilling.
+constexpr int kQueueStack = 32;
+
+// LDS of the queued lane refilling: the lane stacks, the N sample keys of
+// each lane, the record queue (record index, owner lane).
+template <int N>
+struct QueueLds {
+    int32_t stack[kQueueStack * kPersistBlock];
+    unsigned long long keys[N * kPersistBlock];
+    uint32_t q_rec[kQueueRecs * kPersistBlock];
+    uint8_t q_lane[kQueueRecs * kPersistBlock];
+    unsigned long long dirty;  // bit l: a key of lane l fell in this step
+};
+
 // The lane-refilling loop over items numbered from the work counter's
-// starting value up to n_items; lds holds 32 stack entries per lane.
+// starting value up to n_items, with the record tests taken off the lanes'
+// walks (the scheme of the queued shadow kernel, for closest hits). Each step a walking lane hands up to kQueueRecs records of the leaf it is
+// at to a wave-wide queue in LDS and then takes one node step; the wave tests
+// the queued records one per lane with the owner's ray read through lane
+// shuffles, and lowers the owner's sample keys (kept in LDS) with atomic
+// minima. An owner's depth cut follows its keys one step later, which only
+// tests more records. A lane whose walk has ended shades its samples once
+// the records it queued in its last step are tested.
 template <int W, int N, bool COUNT, int DM>
-__device__ __forceinline__ void persist_lanes(const BatchArgs& a, int32_t* lds, LaneCounts& cnt)
+__device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L, LaneCounts& cnt)
 {
     const int lane = threadIdx.x;
-    const int cap = min(32, a.stack_cap);
+    const int cap = min(kQueueStack, a.stack_cap);
     const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
+    unsigned long long* keys = L.keys + lane;
+    const unsigned long long miss_key = pack_key(INFINITY, 0x7FFFFFFF);
 
-    // lane state
-    bool active = false;
-    BRay b;
-    b.valid = false;
+    bool active = false, walking = false, exhausted = false;
+    BRay b{};
     int32_t pass = 0, n_act = 0;
     int64_t item_id = 0;
-    Ray lr;
-    DepthCtx dc;
-    FwdSamples<N> st;
+    uint32_t s0 = 0;
+    Ray lr = make_ray(0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f);
+    DepthCtx dc = make_depth(0, a.depth_axis, lr, a.r_max);
+    float wt = INFINITY, tcut = 0.0f;
+    int32_t wg = 0x7FFFFFFF;
     int32_t node = 0;
     int sp = 0;
     int64_t steps = 0;
-    bool exhausted = false;
 
     for (;;) {
         // ---- refill idle lanes (wave-uniform decision) ----
@@ -441,84 +468,163 @@ __device__ __forceinline__ void persist_lanes(const BatchArgs& a, int32_t* lds, 
                     int32_t seg;
                     int64_t ray;
                     decode_item(a, it, seg, ray, pass);
-                    const Segment& S = a.segs[seg];
-                    b = seg_ray(a, S, ray);
+                    b = seg_ray(a, a.segs[seg], ray);
                     if (b.valid) {
                         item_id = it;
                         n_act = min(N, b.spp - pass * N);
+                        s0 = a.soff + (uint32_t)(pass * N);
                         lr = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
                         dc = make_depth(a.depth_mode, a.depth_axis, lr, a.r_max);
-                        st.reset(n_act, b.tmax);
+#pragma unroll
+                        for (int k = 0; k < N; ++k) keys[64 * k] = miss_key;
+                        wt = INFINITY;
+                        wg = 0x7FFFFFFF;
+                        tcut = b.tmax;
                         node = 0;
                         sp = 0;
                         steps = 0;
-                        active = true;
+                        active = walking = true;
                         ++cnt.trav;
                     }
                 }
             }
         }
-        if (!active) continue;
+        __syncthreads();
 
-        // ---- one traversal step: one node or one leaf ----
-        bool done = false, overflow = false;
-        if (++steps > a.max_steps) {
-            overflow = true;
-        } else if (node >= 0) {
-            ++cnt.nodes;
-            NodeBuf<W> nb;
-            load_node<W>(nodes, node, nb);
-            uint32_t key[W];
-            slab_keys<W>(nb, lr, st.tcut + (DM == 0 ? 0.0f : dc.node_slack), key);
-            sort_keys<W>(key);
-            int nh = 0;
-#pragma unroll
-            for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
-            if (nh > 0) {
-                if (sp + nh - 1 > cap) {
-                    overflow = true;
-                } else {
-#pragma unroll
-                    for (int c = W - 1; c >= 1; --c)
-                        if (key[c] != 0xFFFFFFFFu) {
-                            lds[sp * kPersistBlock + lane] = child_at<W>(nb, key[c] & 7u);
-                            ++sp;
-                        }
-                    node = child_at<W>(nb, key[0] & 7u);
+        // ---- one step of every walking lane: up to kQueueRecs records of
+        // the leaf it is at go to the queue, then it takes one node step ----
+        uint32_t q_first = 0;
+        int q_n = 0;
+        if (active && walking) {
+            bool ended = false;
+            if (++steps > a.max_steps) {
+                ended = true;
+            } else {
+                if (node < 0) {
+                    const uint32_t first = leaf_first(node), count = leaf_count(node);
+                    q_first = first;
+                    q_n = (int)min(count, (uint32_t)kQueueRecs);
+                    if (count > (uint32_t)q_n) {
+                        node = make_leaf(first + (uint32_t)q_n, count - (uint32_t)q_n);
+                    } else if (sp > 0) {
+                        --sp;
+                        node = L.stack[sp * kPersistBlock + lane];
+                    } else {
+                        walking = false;
+                    }
                 }
-            } else if (sp == 0) {
-                done = true;
-            } else {
-                --sp;
-                node = lds[sp * kPersistBlock + lane];
+                if (walking && node >= 0) {
+                    ++cnt.nodes;
+                    NodeBuf<W> nb;
+                    load_node<W>(nodes, node, nb);
+                    uint32_t key[W];
+                    slab_keys<W>(nb, lr, tcut + (DM == 0 ? 0.0f : dc.node_slack), key);
+                    sort_keys<W>(key);
+                    int nh = 0;
+#pragma unroll
+                    for (int c = 0; c < W; ++c) nh += key[c] != 0xFFFFFFFFu;
+                    if (nh > 0) {
+                        if (sp + nh - 1 > cap) {
+                            ended = true;
+                        } else {
+#pragma unroll
+                            for (int c = W - 1; c >= 1; --c)
+                                if (key[c] != 0xFFFFFFFFu) {
+                                    L.stack[sp * kPersistBlock + lane] = child_at<W>(nb, key[c] & 7u);
+                                    ++sp;
+                                }
+                            node = child_at<W>(nb, key[0] & 7u);
+                        }
+                    } else if (sp > 0) {
+                        --sp;
+                        node = L.stack[sp * kPersistBlock + lane];
+                    } else {
+                        walking = false;
+                    }
+                }
             }
-        } else {
-            const uint32_t first = leaf_first(node), count = leaf_count(node);
-            const double tmin_d = b.tmin, tmax_d = b.tmax;
-            const ForwardCtx fc{a.recs, b.purpose, a.k0, a.k1};
-            FwdCounts fcnt;
-            const uint32_t s0 = a.soff + (uint32_t)(pass * N);
-            for (uint32_t i = 0; i < count; ++i) {
-                ++cnt.prims;
-                const Record r = load_record(a.recs, first + i);
-                fwd_offer<N, false, false, DM>(st, r, lr, dc, tmin_d, tmax_d, -1, b.rid, s0, fc,
-                                                     fcnt);
-            }
-            cnt.cands += fcnt.cands;
-            cnt.philox += fcnt.philox;
-            if (sp == 0) {
-                done = true;
-            } else {
-                --sp;
-                node = lds[sp * kPersistBlock + lane];
+            if (ended) {
+                // stack or step bound exceeded: the deep pass reruns the item
+                const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
+                a.ovf_list[slot] = (uint64_t)item_id;
+                q_n = 0;
+                active = walking = false;
             }
         }
-        if (overflow) {
-            const uint32_t slot = atomicAdd(&a.ctrl[0], 1u);
-            a.ovf_list[slot] = (uint64_t)item_id;
-            active = false;
-        } else if (done) {
-            // shade and accumulate this item's samples
+
+        // ---- queue the records (wave prefix sum of the counts) ----
+        int incl = q_n;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, 63, 64);
+        for (int i = 0; i < q_n; ++i) {
+            L.q_rec[incl - q_n + i] = q_first + (uint32_t)i;
+            L.q_lane[incl - q_n + i] = (uint8_t)lane;
+        }
+        if (lane == 0) L.dirty = 0ull;
+        __syncthreads();
+
+        // ---- test the queued records, one per lane ----
+        for (int e0 = 0; e0 < total; e0 += 64) {
+            const int e = e0 + lane;
+            const bool has = e < total;
+            const int owner = has ? (int)L.q_lane[e] : lane;
+            Ray rr;
+            rr.ox = __shfl(lr.ox, owner, 64);
+            rr.oy = __shfl(lr.oy, owner, 64);
+            rr.oz = __shfl(lr.oz, owner, 64);
+            rr.dx = __shfl(lr.dx, owner, 64);
+            rr.dy = __shfl(lr.dy, owner, 64);
+            rr.dz = __shfl(lr.dz, owner, 64);
+            rr.ix = rr.iy = rr.iz = 0.0f;  // not used by the record test
+            rr.tmin = __shfl(lr.tmin, owner, 64);
+            rr.inv_dd = __shfl(lr.inv_dd, owner, 64);
+            rr.inv_len = __shfl(lr.inv_len, owner, 64);
+            const float r_tmin = __shfl(b.tmin, owner, 64), r_tmax = __shfl(b.tmax, owner, 64);
+            const float r_tcut = __shfl(tcut, owner, 64), r_wt = __shfl(wt, owner, 64);
+            const int32_t r_wg = __shfl(wg, owner, 64);
+            const uint32_t r_rid = (uint32_t)__shfl((int32_t)b.rid, owner, 64);
+            const uint32_t r_pur = (uint32_t)__shfl((int32_t)b.purpose, owner, 64);
+            const uint32_t r_s0 = (uint32_t)__shfl((int32_t)s0, owner, 64);
+            const int r_nact = __shfl(n_act, owner, 64);
+            DepthCtx rdc = dc;
+            if (DM != 0) rdc.inv_den = __shfl(dc.inv_den, owner, 64);
+            if (has) {
+                ++cnt.prims;
+                const Record rec = load_record(a.recs, L.q_rec[e]);
+                FwdCounts fcnt;
+                if (keyed_offer<N, DM>(rec, rr, rdc, (double)r_tmin, (double)r_tmax, r_tcut, r_wt,
+                                       r_wg, r_rid, r_s0, r_nact, r_pur, a.k0, a.k1,
+                                       L.keys + owner, fcnt))
+                    atomicOr(&L.dirty, 1ull << owner);
+                cnt.cands += fcnt.cands;
+                cnt.philox += fcnt.philox;
+            }
+        }
+        __syncthreads();
+
+        if (!active) continue;
+        // ---- the depth cut follows the keys; an ended walk shades ----
+        if ((L.dirty >> lane) & 1ull) {
+            wt = -INFINITY;
+            wg = (int32_t)0x80000000;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                if (k >= n_act) continue;
+                float t;
+                int32_t g;
+                unpack_key(keys[64 * k], t, g);
+                if (key_less(wt, wg, t, g)) {
+                    wt = t;
+                    wg = g;
+                }
+            }
+            tcut = fminf(cut_after(wt), b.tmax);
+        }
+        if (!walking) {
             cnt.samples += (uint32_t)n_act;
             float Y[16];
             const float nn = sqrtf(b.d[0] * b.d[0] + b.d[1] * b.d[1] + b.d[2] * b.d[2]);
@@ -527,10 +633,13 @@ __device__ __forceinline__ void persist_lanes(const BatchArgs& a, int32_t* lds, 
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 if (k >= n_act) continue;
-                const bool hit = st.bg[k] != 0x7FFFFFFF;
-                if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? st.bg[k] : -1;
+                float t;
+                int32_t g;
+                unpack_key(keys[64 * k], t, g);
+                const bool hit = g != 0x7FFFFFFF;
+                if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? g : -1;
                 if (hit) {
-                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, st.bg[k], Y));
+                    const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, g, Y));
                     c0 += c.x; c1 += c.y; c2 += c.z;
                 } else {
                     c0 += a.bg[0]; c1 += a.bg[1]; c2 += a.bg[2];
@@ -548,9 +657,9 @@ __device__ __forceinline__ void persist_lanes(const BatchArgs& a, int32_t* lds, 
 template <int W, int N, bool COUNT, int DM>
 __global__ __launch_bounds__(kPersistBlock) void k_persistent(BatchArgs a)
 {
-    __shared__ int32_t lds[32 * kPersistBlock];
+    __shared__ QueueLds<N> q;
     LaneCounts cnt;
-    persist_lanes<W, N, COUNT, DM>(a, lds, cnt);
+    persist_queue<W, N, COUNT, DM>(a, q, cnt);
     flush_counts<COUNT>(a, cnt, 0, 0);
 }
 
@@ -564,22 +673,19 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 
 constexpr int kWaveCap = 48;  // wave-shared stack entries (12 KB of LDS per wave)
 
-// Persistent with wave-shared walks: first the lane refilling over the extra
-// rays (whose counter the host starts at n_cam; their walks are long and
-// uneven, so they start first and the camera groups fill in around them),
-// then camera (tile, pass) groups, one per atomic. The LDS holds the lane
-// stacks, then the wave stack.
+// Persistent with wave-shared walks for the camera pixels: each wave claims
+// camera (tile, pass) groups, one per atomic, and walks each with its 64
+// rays together. (The extra rays go to k_persistent, launched before it at
+// its own occupancy: its lane walks need fewer registers than these.)
 template <int W, int N, bool COUNT, int DM>
 __global__ __launch_bounds__(kPersistBlock) void k_persistent_wave(BatchArgs a,
                                                                    const void* __restrict__ nodes_v,
                                                                    const Record* __restrict__ recs)
 {
     __shared__ float lds[kWaveCap * 64];
-    static_assert(kWaveCap * 64 >= 32 * kPersistBlock, "lane stacks fit the same LDS");
     const WideNode<W>* __restrict__ nodes = static_cast<const WideNode<W>*>(nodes_v);
     const int lane = threadIdx.x;
     LaneCounts cnt;
-    persist_lanes<W, N, COUNT, DM>(a, reinterpret_cast<int32_t*>(lds), cnt);
     WaveStack stk{lds, kWaveCap, nullptr, 0, min(kWaveCap, a.stack_cap)};
     for (;;) {
         unsigned long long g = 0;
@@ -740,6 +846,7 @@ struct srt_batch_plan {
     int32_t* deep_stack = nullptr;
     int64_t ovf_cap = 0;
     int32_t n_cu = 0;
+    int32_t resident[2][2] = {{1, 1}, {1, 1}};  // [counters][lane, wave]: workgroups per CU
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -814,14 +921,21 @@ srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* count
         k_zero_f32<<<1024, 256, 0, s>>>(rgb, 3 * p->rows);
         SRT_HIP_TRY(hipGetLastError());
         a.n_items = p->n_items;
+        // a persistent grid beyond what stays resident only adds waves that
+        // start when the work is gone
         const int wpc = std::max(1, p->tuning.waves_per_cu);
-        if (wave)
-            hipLaunchKernelGGL(k.persistent_wave, dim3((unsigned)(p->n_cu * wpc)),
-                               dim3(kPersistBlock), 0, s, a, nodes, recs);
-        else
-            hipLaunchKernelGGL(k.persistent, dim3((unsigned)(p->n_cu * wpc)), dim3(kPersistBlock),
-                               0, s, a);
-        SRT_HIP_TRY(hipGetLastError());
+        const int ci = counters ? 1 : 0;
+        if (p->n_items > a.n_cam) {  // lane items: all (lane walks) or the extra rays
+            const int g = p->n_cu * std::min(wpc, p->resident[ci][0]);
+            hipLaunchKernelGGL(k.persistent, dim3((unsigned)g), dim3(kPersistBlock), 0, s, a);
+            SRT_HIP_TRY(hipGetLastError());
+        }
+        if (wave) {
+            const int g = p->n_cu * std::min(wpc, p->resident[ci][1]);
+            hipLaunchKernelGGL(k.persistent_wave, dim3((unsigned)g), dim3(kPersistBlock), 0, s, a,
+                               nodes, recs);
+            SRT_HIP_TRY(hipGetLastError());
+        }
         hipLaunchKernelGGL(k.persistent_deep, dim3(kDeepThreads / kPlainBlock), dim3(kPlainBlock),
                            0, s, a);
         SRT_HIP_TRY(hipGetLastError());
@@ -937,6 +1051,24 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
         return SRT_ERR_HIP;
     }
     p->n_cu = prop.multiProcessorCount;
+    for (int c = 0; c < 2; ++c) {
+        Kernels k{};
+        if (!pick(b->W, N, c == 1, opts->depth_mode, k)) {
+            plan_free(p);
+            return SRT_ERR_UNSUPPORTED;
+        }
+        int nl = 0, nw = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nl, reinterpret_cast<const void*>(k.persistent), kPersistBlock, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nw, reinterpret_cast<const void*>(k.persistent_wave), kPersistBlock, 0) !=
+                hipSuccess) {
+            plan_free(p);
+            return SRT_ERR_HIP;
+        }
+        p->resident[c][0] = std::max(1, nl);
+        p->resident[c][1] = std::max(1, nw);
+    }
     p->ovf_cap = std::max<int64_t>(items, rays) + 1;
     if (hipMalloc(&p->d_segs, sizeof(Segment) * std::max<size_t>(1, p->segs.size())) != hipSuccess ||
         hipMalloc(&p->work, 2 * sizeof(unsigned long long)) != hipSuccess ||

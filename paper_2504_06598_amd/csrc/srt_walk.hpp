@@ -333,6 +333,30 @@ struct FwdCounts {
     uint32_t cands = 0, philox = 0;
 };
 
+// Validity of record r as a candidate of the ray (Sec. 3.1): the ray passes
+// within the Gaussian's k-sigma ellipsoid (q <= k^2) and the candidate's
+// depth t lies in (tmin, tmax), r not being the ignored Gaussian. In mean
+// depth mode a bounding-sphere test against [ray.tmin, tcut] rejects records
+// first (tcut: no candidate past it can change a result); the centre-depth
+// depth is not bounded by the sphere's span, so there only a sphere the ray
+// misses is rejected. tm: the 1D mean along the ray.
+template <int DM>
+__device__ __forceinline__ bool valid_candidate(const Record& r, const Ray& ray,
+                                                const DepthCtx& dc, double tmin, double tmax,
+                                                float tcut, int32_t ign, double& t, double& tm,
+                                                double& q)
+{
+    if (depth_mode_of<DM>(dc) == 0) {
+        if (sphere_reject(r, ray, ray.tmin, tcut)) return false;
+    } else if (sphere_reject(r, ray, -INFINITY, INFINITY)) {
+        return false;
+    }
+    isect_tq(r, ray, tm, q);
+    t = depth_of<DM>(dc, r, ray, tm);
+    if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
+    return true;
+}
+
 // Offer record r to the samples; true when an any-hit walk may stop. HASH:
 // acceptance numbers from the trigonometric hash of the hit position instead
 // of Philox.
@@ -342,15 +366,8 @@ __device__ __forceinline__ bool fwd_offer(FwdSamples<N>& st, const Record& r, co
                                           int32_t ign, uint32_t rid, uint32_t s0,
                                           const ForwardCtx& fc, FwdCounts& cnt)
 {
-    if (depth_mode_of<DM>(dc) == 0) {
-        if (sphere_reject(r, ray, ray.tmin, st.tcut)) return false;
-    } else if (sphere_reject(r, ray, -INFINITY, INFINITY)) {
-        return false;
-    }
-    double tm, q;
-    isect_tq(r, ray, tm, q);
-    const double t = depth_of<DM>(dc, r, ray, tm);
-    if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return false;
+    double t, tm, q;
+    if (!valid_candidate<DM>(r, ray, dc, tmin, tmax, st.tcut, ign, t, tm, q)) return false;
     ++cnt.cands;
     const float t32 = (float)t;
     if (!key_less(t32, r.gid, st.wt, st.wg)) return false;
@@ -408,15 +425,8 @@ __device__ __forceinline__ uint64_t group_offer(const Record& r, const Ray& ray,
                                                 uint32_t s0, uint64_t pending,
                                                 const ForwardCtx& fc, FwdCounts& cnt)
 {
-    if (depth_mode_of<DM>(dc) == 0) {
-        if (sphere_reject(r, ray, ray.tmin, tcut)) return 0;
-    } else if (sphere_reject(r, ray, -INFINITY, INFINITY)) {
-        return 0;
-    }
-    double tm, q;
-    isect_tq(r, ray, tm, q);
-    const double t = depth_of<DM>(dc, r, ray, tm);
-    if (!(q <= kEllipsoidQ && t > tmin && t < tmax) || r.gid == ign) return 0;
+    double t, tm, q;
+    if (!valid_candidate<DM>(r, ray, dc, tmin, tmax, tcut, ign, t, tm, q)) return 0;
     ++cnt.cands;
     const AlphaTest at(r.opacity, q);
     uint64_t occ = 0, m = pending;
@@ -434,6 +444,66 @@ __device__ __forceinline__ uint64_t group_offer(const Record& r, const Ray& ray,
         if (at.accepts(word_of(w, s & 3u))) occ |= 1ull << j;
     }
     return occ;
+}
+
+// (t, gid) key as one unsigned 64-bit value whose integer order is
+// key_less's order: the depth's bits mapped monotonically (-0 taken as +0),
+// then the id with its sign bit flipped.
+__device__ __forceinline__ uint64_t pack_key(float t, int32_t gid)
+{
+    uint32_t b = __float_as_uint(t + 0.0f);
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ((uint64_t)b << 32) | ((uint32_t)gid ^ 0x80000000u);
+}
+
+__device__ __forceinline__ void unpack_key(uint64_t k, float& t, int32_t& gid)
+{
+    uint32_t b = (uint32_t)(k >> 32);
+    b = (b & 0x80000000u) ? (b & 0x7FFFFFFFu) : ~b;
+    t = __uint_as_float(b);
+    gid = (int32_t)((uint32_t)k ^ 0x80000000u);
+}
+
+// fwd_offer for samples whose keys live in LDS (key of sample k at
+// keys[64 k]) and may be lowered by other lanes in the same step: the
+// validity test, then each of the n_act samples whose key the candidate's
+// beats draws its number and on acceptance lowers the key with an LDS atomic
+// minimum. (wt, wg) and tcut may lag the keys: a larger bound only tests more
+// records, and each sample's result is the minimum over its accepted
+// candidates whatever the order they are offered in. True when a key fell.
+template <int N, int DM>
+__device__ __forceinline__ bool keyed_offer(const Record& r, const Ray& ray, const DepthCtx& dc,
+                                            double tmin, double tmax, float tcut, float wt,
+                                            int32_t wg, uint32_t rid, uint32_t s0, int n_act,
+                                            uint32_t purpose, uint32_t k0, uint32_t k1,
+                                            unsigned long long* keys, FwdCounts& cnt)
+{
+    double t, tm, q;
+    if (!valid_candidate<DM>(r, ray, dc, tmin, tmax, tcut, -1, t, tm, q)) return false;
+    ++cnt.cands;
+    const float t32 = (float)t;
+    if (!key_less(t32, r.gid, wt, wg)) return false;
+    const unsigned long long key = pack_key(t32, r.gid);
+    const AlphaTest at(r.opacity, q);
+    uint4 w = make_uint4(0, 0, 0, 0);
+    uint32_t grp = 0xFFFFFFFFu;
+    bool changed = false;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if (k < n_act && key < keys[64 * k]) {
+            const uint32_t s = s0 + (uint32_t)k;
+            if ((s >> 2) != grp) {
+                grp = s >> 2;
+                w = philox4x32_10(make_uint4(rid, grp, (uint32_t)r.gid, purpose), k0, k1);
+                ++cnt.philox;
+            }
+            if (at.accepts(word_of(w, s & 3u))) {
+                atomicMin(keys + 64 * k, key);
+                changed = true;
+            }
+        }
+    }
+    return changed;
 }
 
 template <int W, int N, bool ANY, class Stack, bool HASH = false, int DM = -1>
