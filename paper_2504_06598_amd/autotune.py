@@ -31,20 +31,27 @@ def _signature(scene: DeviceScene, cameras, spp, n_extra, n_per_traversal):
     return h.hexdigest()[:16]
 
 
-def _time_plan(plan: BatchPlan, reps: int, hits=None):
+def _time_plan(plan: BatchPlan, reps: int, hits, prune_ms=None):
+    """Milliseconds per launch, and whether timing was cut short. The first
+    launch writes the guarded hit ids (and captures the plan's graph, which
+    the timed launches replay); when it already takes longer than prune_ms
+    the configuration cannot win and its time is that launch's."""
     rgb = torch.empty((plan.rows, 3), device=plan.bvh.scene.means.device)
-    if hits is not None:
-        plan.execute(rgb=rgb, hit_gid=hits)  # the guarded run (its own graph)
-    plan.execute(rgb=rgb)  # captures the timed graph, warms caches
-    torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record()
-    for _ in range(reps):
-        plan.execute(rgb=rgb)
+    plan.execute(rgb=rgb, hit_gid=hits)
     stop.record()
     torch.cuda.synchronize()
-    return start.elapsed_time(stop) / reps
+    first = start.elapsed_time(stop)
+    if prune_ms is not None and first > prune_ms:
+        return first, True
+    start.record()
+    for _ in range(reps):
+        plan.execute(rgb=rgb, hit_gid=hits)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps, False
 
 
 def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs=None,
@@ -80,6 +87,7 @@ def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs
     samples = ref_plan.samples
     del ref_plan
     table = []
+    best = {}  # fastest time so far per kind; configurations 1.5x slower are not re-timed
     for W in widths:
         for L in leaves:
             for split in splits:
@@ -90,13 +98,17 @@ def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs
                 for persistent, thr, wpc in shapes:
                     plan = plan_for(bvh, persistent, thr, wpc)
                     hits = torch.empty(samples, dtype=torch.int32, device=dev)
-                    ms = _time_plan(plan, reps, hits)
+                    b = best.get(persistent)
+                    ms, pruned = _time_plan(plan, reps, hits, None if b is None else 1.5 * b)
                     ok = bool(torch.equal(hits, ref_hits))
+                    if ok and not pruned:
+                        best[persistent] = ms if b is None else min(b, ms)
                     row = {"width": W, "leaf_size": L, "size_split": split,
                            "persistent": persistent, "refill_threshold": thr,
                            "waves_per_cu": wpc, "ms": round(ms, 4),
                            "mrays_per_s": round(samples / (ms * 1e-3) / 1e6, 2),
-                           "build_ms": round(build_ms, 2), "ids_equal": ok}
+                           "build_ms": round(build_ms, 2), "ids_equal": ok,
+                           "pruned": pruned}
                     table.append(row)
                     if log:
                         log(row)
