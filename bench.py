@@ -67,9 +67,10 @@ def parse():
     p.add_argument("--batched-reps", type=int, default=1)
     p.add_argument("--batched-only", action="store_true",
                    help="run only the persistent-vs-plain measurement and print its record")
-    p.add_argument("--batched-config", metavar="W,L,THRESHOLD,WAVES",
-                   help="skip the autotuner: both kinds at this tree (size split 4), the "
-                        "persistent one at this refill threshold and workgroups per CU")
+    p.add_argument("--batched-config", metavar="W,L,THRESHOLD,WAVES,N",
+                   help="skip the autotuner: both kinds at this tree (size split 4) and N "
+                        "samples per traversal, the persistent one at this refill threshold "
+                        "and workgroups per CU")
     p.add_argument("--no-multisample", action="store_true",
                    help="skip the N = 1 vs N = 4 comparison on the object-like scene")
     p.add_argument("--profile-kernels", action="store_true",
@@ -681,9 +682,11 @@ def summarize_profiles(args):
             json.dump(full, fh, indent=1)
 
 
-# samples per traversal in the batched launch: in this scene's fog of large
-# Gaussians a traversal tests ~10k records whatever its N, so N = 8 halves the
-# traversals of views with 8 or more spp (camera items 3.5 -> 2.1 s at full size)
+# samples per traversal of the batched launch's sweep: in this scene's fog of
+# large Gaussians a traversal tests ~10k records whatever its N, so larger N
+# means fewer traversals of views with many spp (camera items at full size:
+# 3.5 s at N = 4, 2.1 s at N = 8); the best configuration of each kind is also
+# timed at N = 16
 BATCH_N = 8
 
 
@@ -695,7 +698,8 @@ def bench_batched(args, srt, si, torch, dev):
     width {2,4,8} x leaf size {1,2,4,8} (size split 4: Gaussians more than 16x
     apart in size in subtrees of their own, 2x faster than none on this scene)
     x refill threshold {16,32} x workgroups per CU {8,12} (each persistent
-    grid capped at what its kernel keeps resident) on a subsample that keeps
+    grid capped at what its kernel keeps resident) at N = 8 samples per
+    traversal, then the best of each kind at N = 16, on a subsample that keeps
     the workload's
     coherence and mix: every 8th view in order of spp, at full resolution, and
     the incoherent rays in the same proportion to the camera samples; each
@@ -729,9 +733,9 @@ def bench_batched(args, srt, si, torch, dev):
     n_t = max(1, int(round(n_all * sum(tspp) / sum(spp))))
     t1 = time.perf_counter()
     if args.batched_config:
-        W, L, thr, wpc = (int(x) for x in args.batched_config.split(","))
+        W, L, thr, wpc, n = (int(x) for x in args.batched_config.split(","))
         base = {"width": W, "leaf_size": L, "size_split": 4, "refill_threshold": thr,
-                "waves_per_cu": wpc}
+                "waves_per_cu": wpc, "n_per_traversal": n}
         tune = {"persistent": dict(base, persistent=True),
                 "plain": dict(base, persistent=False), "table": []}
     else:
@@ -739,7 +743,7 @@ def bench_batched(args, srt, si, torch, dev):
                         extra_spp=1, seed=si.PHILOX_SEED, n_per_traversal=BATCH_N,
                         widths=(2, 4, 8), leaves=(1, 2, 4, 8),
                         splits=(4,), thresholds=(16, 32), waves=(8, 12), reps=1,
-                        use_cache=False, cache_path=None,
+                        more_n=(16,), use_cache=False, cache_path=None,
                         log=lambda r: print("# tune", r, file=sys.stderr, flush=True))
         print(f"# autotuner ({time.perf_counter() - t1:.1f} s): persistent "
               f"{tune['persistent']}, plain {tune['plain']}, rejected {tune['rejected']}",
@@ -750,7 +754,7 @@ def bench_batched(args, srt, si, torch, dev):
         bvh = srt.srt_build_bvh(sc, cfg["width"], cfg["leaf_size"], cfg["size_split"])
         plan = srt.srt_batch_plan_create(bvh, cams, spp, extra_origins=eo, extra_dirs=ed,
                                          extra_spp=1, seed=si.PHILOX_SEED,
-                                         n_per_traversal=BATCH_N,
+                                         n_per_traversal=cfg["n_per_traversal"],
                                          persistent=cfg["persistent"],
                                          refill_threshold=cfg["refill_threshold"],
                                          waves_per_cu=cfg["waves_per_cu"])
@@ -768,6 +772,7 @@ def bench_batched(args, srt, si, torch, dev):
                      "leaf_size": cfg["leaf_size"], "size_split": cfg["size_split"],
                      "refill_threshold": cfg["refill_threshold"],
                      "waves_per_cu": cfg["waves_per_cu"],
+                     "n_per_traversal": cfg["n_per_traversal"],
                      "per_traversal": {"nodes": round(c["nodes"] / tr, 1),
                                        "records": round(c["prims"] / tr, 1),
                                        "candidates": round(c["candidates"] / tr, 1),
@@ -780,7 +785,8 @@ def bench_batched(args, srt, si, torch, dev):
     scale = "full size" if k == 1 else f"1/{k} of the pixels and incoherent rays"
     res["workload"] = (f"3.3M Gaussians (3M object-like + 300k large diffuse); 64 views on a "
                        f"Fibonacci sphere at {side}x{side}, spp per view from {{1,...,64}}; "
-                       f"{n_inc} incoherent rays; N={BATCH_N}; one graph launch ({scale})")
+                       f"{n_inc} incoherent rays; one graph launch ({scale}); samples per "
+                       f"traversal tuned from {{{BATCH_N}, 16}} per kind")
     res["autotune_configs"] = len(tune["table"])
     return res
 

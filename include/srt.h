@@ -474,6 +474,10 @@ typedef struct srt_batch_plan srt_batch_plan; /* opaque, library-owned */
 
 /* Output rows: the views' pixels (view by view, y*W + x), then the extra
  * rays. Per-sample outputs follow the same order, spp entries per row.
+ * opts->n_per_traversal may also be 16 here: the views' pixels then take 16
+ * samples per traversal on wave-shared walks (opts->walk != 1), while lane
+ * walks (the extra rays, and the views with walk = 1) take at most 8; the
+ * per-sample results do not depend on it.
  * Copies the view table to the device and allocates the plan's work counter,
  * overflow queue and deep stacks; synchronises `stream`. The handle and the
  * extra-ray arrays must outlive the plan. Errors: INVALID_ARG, OOM, HIP. */

@@ -1,6 +1,7 @@
 """Autotuner of the batched forward: BVH width, leaf size and size split (a
 new BVH per triple) and the persistent kernel's refill threshold and waves
-per CU.
+per CU; optionally, for the best configuration of each kind, other numbers
+of samples per traversal.
 
 Every candidate's per-sample hit ids must equal the reference launch's bit
 for bit (plain kernel on a W=4, L=4 tree): the accepted set does not depend
@@ -57,14 +58,17 @@ def _time_plan(plan: BatchPlan, reps: int, hits, prune_ms=None):
 def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs=None,
              extra_spp=1, seed=0, n_per_traversal=4, widths=(2, 4, 8), leaves=(1, 2, 4, 8),
              splits=(0,), thresholds=(8, 16, 32, 48), waves=(4, 8, 12), reps=2,
-             cache_path=DEFAULT_CACHE,
+             more_n=(), cache_path=DEFAULT_CACHE,
              use_cache=True, log=None):
-    """Sweep and return {"persistent": {...}, "plain": {...}, "table": [...]}."""
+    """Sweep and return {"persistent": {...}, "plain": {...}, "table": [...]}.
+    The sweep runs at n_per_traversal; the best configuration of each kind is
+    then also timed at each N in more_n (results do not depend on N, only
+    the cost of a traversal and the number of traversals do)."""
     dev = scene.means.device
     gpu = torch.cuda.get_device_name(dev)
     n_extra = 0 if extra_origins is None else int(extra_origins.shape[0])
     key = (f"{gpu}|{_signature(scene, cameras, spp, n_extra, n_per_traversal)}|"
-           f"{widths}|{leaves}|{splits}|{thresholds}|{waves}")
+           f"{widths}|{leaves}|{splits}|{thresholds}|{waves}|{tuple(more_n)}")
     if use_cache and cache_path and os.path.exists(cache_path):
         try:
             cache = json.load(open(cache_path))
@@ -73,10 +77,10 @@ def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs
         except (OSError, ValueError):
             pass
 
-    def plan_for(bvh, persistent, thr, wpc):
+    def plan_for(bvh, persistent, thr, wpc, n=n_per_traversal):
         return srt_batch_plan_create(bvh, cameras, spp, extra_origins=extra_origins,
                                      extra_dirs=extra_dirs, extra_spp=extra_spp, seed=seed,
-                                     n_per_traversal=n_per_traversal, persistent=persistent,
+                                     n_per_traversal=n, persistent=persistent,
                                      refill_threshold=thr, waves_per_cu=wpc)
 
     ref_bvh = srt_build_bvh(scene, 4, 4, 0)
@@ -88,6 +92,24 @@ def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs
     del ref_plan
     table = []
     best = {}  # fastest time so far per kind; configurations 1.5x slower are not re-timed
+
+    def measure(bvh, W, L, split, build_ms, persistent, thr, wpc, n):
+        plan = plan_for(bvh, persistent, thr, wpc, n)
+        hits = torch.empty(samples, dtype=torch.int32, device=dev)
+        b = best.get(persistent)
+        ms, pruned = _time_plan(plan, reps, hits, None if b is None else 1.5 * b)
+        ok = bool(torch.equal(hits, ref_hits))
+        if ok and not pruned:
+            best[persistent] = ms if b is None else min(b, ms)
+        row = {"width": W, "leaf_size": L, "size_split": split, "persistent": persistent,
+               "refill_threshold": thr, "waves_per_cu": wpc, "n_per_traversal": n,
+               "ms": round(ms, 4), "mrays_per_s": round(samples / (ms * 1e-3) / 1e6, 2),
+               "build_ms": round(build_ms, 2), "ids_equal": ok, "pruned": pruned}
+        table.append(row)
+        if log:
+            log(row)
+        del plan
+
     for W in widths:
         for L in leaves:
             for split in splits:
@@ -96,24 +118,18 @@ def autotune(scene: DeviceScene, cameras, spp, *, extra_origins=None, extra_dirs
                 build_ms = (time.perf_counter() - t0) * 1e3
                 shapes = [(False, 16, 8)] + [(True, t, w) for t in thresholds for w in waves]
                 for persistent, thr, wpc in shapes:
-                    plan = plan_for(bvh, persistent, thr, wpc)
-                    hits = torch.empty(samples, dtype=torch.int32, device=dev)
-                    b = best.get(persistent)
-                    ms, pruned = _time_plan(plan, reps, hits, None if b is None else 1.5 * b)
-                    ok = bool(torch.equal(hits, ref_hits))
-                    if ok and not pruned:
-                        best[persistent] = ms if b is None else min(b, ms)
-                    row = {"width": W, "leaf_size": L, "size_split": split,
-                           "persistent": persistent, "refill_threshold": thr,
-                           "waves_per_cu": wpc, "ms": round(ms, 4),
-                           "mrays_per_s": round(samples / (ms * 1e-3) / 1e6, 2),
-                           "build_ms": round(build_ms, 2), "ids_equal": ok,
-                           "pruned": pruned}
-                    table.append(row)
-                    if log:
-                        log(row)
-                    del plan
+                    measure(bvh, W, L, split, build_ms, persistent, thr, wpc, n_per_traversal)
                 del bvh
+    for n in more_n:
+        for persistent in (True, False):
+            r = max((r for r in table if r["ids_equal"] and r["persistent"] == persistent),
+                    key=lambda r: r["mrays_per_s"], default=None)
+            if r is None:
+                continue
+            bvh = srt_build_bvh(scene, r["width"], r["leaf_size"], r["size_split"])
+            measure(bvh, r["width"], r["leaf_size"], r["size_split"], r["build_ms"], persistent,
+                    r["refill_threshold"], r["waves_per_cu"], n)
+            del bvh
     good = [r for r in table if r["ids_equal"]]
     best_p = max((r for r in good if r["persistent"]), key=lambda r: r["mrays_per_s"], default=None)
     best_plain = max((r for r in good if not r["persistent"]), key=lambda r: r["mrays_per_s"],

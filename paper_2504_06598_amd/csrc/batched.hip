@@ -49,6 +49,7 @@ struct Segment {
     int64_t sample_begin; // first sample index in the per-sample outputs
     int32_t width, height, tiles_x;
     int32_t spp, passes;
+    int32_t n;            // samples per pass (per traversal)
     uint32_t ray_id_base;
     int64_t rays;         // pixels or extra rays
 };
@@ -135,7 +136,7 @@ struct BRay {
     float o[3], d[3];
     float tmin, tmax;
     uint32_t rid, purpose;
-    int32_t spp;
+    int32_t spp, npass;   // samples, samples per pass
     bool valid;
 };
 
@@ -144,6 +145,7 @@ __device__ __forceinline__ BRay seg_ray(const BatchArgs& a, const Segment& S, in
 {
     BRay b;
     b.spp = S.spp;
+    b.npass = S.n;
     for (int i = 0; i < 3; ++i) {
         b.o[i] = 0.0f;
         b.d[i] = 0.0f;
@@ -202,7 +204,7 @@ template <int W, int N, int DM, class Stack>
 __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int pass, Stack& stk,
                                          LaneCounts& cnt, bool atomic, float acc[3])
 {
-    const int n_act = min(N, b.spp - pass * N);
+    const int n_act = min(b.npass, b.spp - pass * b.npass);
     Ray ray = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
     const ForwardCtx fc{a.recs, b.purpose, a.k0, a.k1};
     const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, ray, a.r_max);
@@ -211,8 +213,8 @@ __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int 
     ++cnt.trav;
     const int res = resolve_samples<W, N, false, Stack, false, DM>(
         static_cast<const WideNode<W>*>(a.nodes), fc, dc, ray, (double)b.tmin, (double)b.tmax, -1,
-        b.rid, a.soff + (uint32_t)(pass * N), n_act, stk, a.max_steps, bt, bg, cnt.nodes, cnt.prims,
-        cnt.cands, cnt.philox);
+        b.rid, a.soff + (uint32_t)(pass * b.npass), n_act, stk, a.max_steps, bt, bg, cnt.nodes,
+        cnt.prims, cnt.cands, cnt.philox);
     if (res == kWalkOverflow) return false;
     float Y[16];
     const float n = sqrtf(b.d[0] * b.d[0] + b.d[1] * b.d[1] + b.d[2] * b.d[2]);
@@ -222,7 +224,7 @@ __device__ __forceinline__ bool run_pass(const BatchArgs& a, const BRay& b, int 
     for (int k = 0; k < N; ++k) {
         if (k >= n_act) continue;
         const bool hit = bg[k] != 0x7FFFFFFF;
-        if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? bg[k] : -1;
+        if (a.hit_gid) a.hit_gid[b.sample0 + pass * b.npass + k] = hit ? bg[k] : -1;
         if (hit) {
             const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, bg[k], Y));
             c0 += c.x; c1 += c.y; c2 += c.z;
@@ -253,7 +255,7 @@ __device__ __forceinline__ bool wave_pass(const BatchArgs& a, const WideNode<W>*
                                           float acc[3])
 {
     const bool live = b.valid && b.tmax > b.tmin;
-    const int n_act = live ? min(N, b.spp - pass * N) : 0;
+    const int n_act = live ? min(b.npass, b.spp - pass * b.npass) : 0;
     Ray ray = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
     const ForwardCtx fc{recs, b.purpose, a.k0, a.k1};
     const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, ray, a.r_max);
@@ -262,7 +264,7 @@ __device__ __forceinline__ bool wave_pass(const BatchArgs& a, const WideNode<W>*
     uint32_t n_nodes = 0, n_prims = 0;
     const int res = resolve_samples_wave<W, N, DM>(
         nodes, recs, fc, dc, ray, live, (double)b.tmin, (double)b.tmax, -1, b.rid,
-        a.soff + (uint32_t)(pass * N), n_act, stk, a.max_steps, bt, bg, n_nodes, n_prims,
+        a.soff + (uint32_t)(pass * b.npass), n_act, stk, a.max_steps, bt, bg, n_nodes, n_prims,
         cnt.cands, cnt.philox);
     if (live) {
         ++cnt.trav;
@@ -275,12 +277,12 @@ __device__ __forceinline__ bool wave_pass(const BatchArgs& a, const WideNode<W>*
     const float n = sqrtf(b.d[0] * b.d[0] + b.d[1] * b.d[1] + b.d[2] * b.d[2]);
     sh_eval(a.deg, b.d[0] / n, b.d[1] / n, b.d[2] / n, Y);
     float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-    const int n_out = min(N, b.spp - pass * N);  // an empty ray's samples are misses
+    const int n_out = min(b.npass, b.spp - pass * b.npass);  // an empty ray's samples are misses
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         if (k >= n_out) continue;
         const bool hit = k < n_act && bg[k] != 0x7FFFFFFF;
-        if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? bg[k] : -1;
+        if (a.hit_gid) a.hit_gid[b.sample0 + pass * b.npass + k] = hit ? bg[k] : -1;
         if (hit) {
             const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, bg[k], Y));
             c0 += c.x; c1 += c.y; c2 += c.z;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(BatchArgs a)
         if (b.valid) {
             float acc[3] = {0.0f, 0.0f, 0.0f};
             bool ok = true;
-            for (int pass = 0; pass * N < b.spp && ok; ++pass)
+            for (int pass = 0; pass * b.npass < b.spp && ok; ++pass)
                 ok = run_pass<W, N, DM>(a, b, pass, stk, cnt, false, acc);
             if (ok) {
                 cnt.samples += (uint32_t)b.spp;
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_deep(BatchArgs a)
         float acc[3] = {0.0f, 0.0f, 0.0f};
         bool ok = true;
         ++deep;
-        for (int pass = 0; pass * N < b.spp && ok; ++pass)
+        for (int pass = 0; pass * b.npass < b.spp && ok; ++pass)
             ok = run_pass<W, N, DM>(a, b, pass, stk, cnt, false, acc);
         if (!ok) {
             ++lost;
@@ -471,8 +473,8 @@ __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L
                     b = seg_ray(a, a.segs[seg], ray);
                     if (b.valid) {
                         item_id = it;
-                        n_act = min(N, b.spp - pass * N);
-                        s0 = a.soff + (uint32_t)(pass * N);
+                        n_act = min(b.npass, b.spp - pass * b.npass);
+                        s0 = a.soff + (uint32_t)(pass * b.npass);
                         lr = make_ray(b.o[0], b.o[1], b.o[2], b.d[0], b.d[1], b.d[2], b.tmin);
                         dc = make_depth(a.depth_mode, a.depth_axis, lr, a.r_max);
 #pragma unroll
@@ -637,7 +639,7 @@ __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L
                 int32_t g;
                 unpack_key(keys[64 * k], t, g);
                 const bool hit = g != 0x7FFFFFFF;
-                if (a.hit_gid) a.hit_gid[b.sample0 + pass * N + k] = hit ? g : -1;
+                if (a.hit_gid) a.hit_gid[b.sample0 + pass * b.npass + k] = hit ? g : -1;
                 if (hit) {
                     const float3 c = clamp0(sh_colour_pre(a.sh, a.deg, g, Y));
                     c0 += c.x; c1 += c.y; c2 += c.z;
@@ -709,7 +711,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent_wave(BatchArgs a,
 // Plain with wave-shared walks: one wave per 8x8 tile of a view, over all
 // passes of its pixels (the camera lanes [0, n_cam) of the plain numbering).
 template <int W, int N, bool COUNT, int DM>
-__global__ __launch_bounds__(64) void k_plain_wave(BatchArgs a, const void* __restrict__ nodes_v,
+__global__ __launch_bounds__(64, 2) void k_plain_wave(BatchArgs a, const void* __restrict__ nodes_v,
                                                    const Record* __restrict__ recs)
 {
     __shared__ float lds[kWaveCap * 64];
@@ -789,12 +791,17 @@ struct Kernels {
     WaveBatchFn plain_wave, persistent_wave;
 };
 
+// Samples per pass of lane walks (their per-lane state lives in registers
+// or, queued, in LDS): larger passes go to wave-shared walks only.
+constexpr int kLaneMaxN = 8;
+
 template <int W, int N, bool C, int DM>
 void pick_all(Kernels& k)
 {
-    k.plain = k_plain<W, N, C, DM>;
+    constexpr int NL = N < kLaneMaxN ? N : kLaneMaxN;
+    k.plain = k_plain<W, NL, C, DM>;
     k.plain_deep = k_plain_deep<W, N, C, DM>;
-    k.persistent = k_persistent<W, N, C, DM>;
+    k.persistent = k_persistent<W, NL, C, DM>;
     k.persistent_deep = k_persistent_deep<W, N, C, DM>;
     k.plain_wave = k_plain_wave<W, N, C, DM>;
     k.persistent_wave = k_persistent_wave<W, N, C, DM>;
@@ -808,6 +815,7 @@ bool pick_w(int N, Kernels& k)
     case 2: pick_all<W, 2, C, DM>(k); return true;
     case 4: pick_all<W, 4, C, DM>(k); return true;
     case 8: pick_all<W, 8, C, DM>(k); return true;
+    case 16: pick_all<W, 16, C, DM>(k); return true;
     }
     return false;
 }
@@ -972,7 +980,11 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
     if (!b || !batch || !opts || !tuning || !out) return SRT_ERR_INVALID_ARG;
     *out = nullptr;
     const int N = opts->n_per_traversal;
-    if (N != 1 && N != 2 && N != 4 && N != 8) return SRT_ERR_INVALID_ARG;
+    if (N != 1 && N != 2 && N != 4 && N != 8 && N != 16) return SRT_ERR_INVALID_ARG;
+    // passes of the views' pixels on wave-shared walks take N samples, lane
+    // walks at most kLaneMaxN
+    const int n_lane = std::min(N, kLaneMaxN);
+    const int n_cam = opts->walk == 1 ? n_lane : N;
     if (opts->any_hit || opts->stack_limit < 0) return SRT_ERR_INVALID_ARG;
     if (opts->depth_mode != 0 && opts->depth_mode != 1) return SRT_ERR_INVALID_ARG;
     if (opts->rng != 0 && opts->rng != 1) return SRT_ERR_INVALID_ARG;
@@ -1005,7 +1017,8 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
         S.height = c.height;
         S.tiles_x = (c.width + kTile - 1) / kTile;
         S.spp = spp;
-        S.passes = (spp + N - 1) / N;
+        S.n = n_cam;
+        S.passes = (spp + n_cam - 1) / n_cam;
         S.rays = (int64_t)c.width * c.height;
         S.item_begin = items;
         S.enum_begin = rays;
@@ -1025,7 +1038,8 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
         Segment S{};
         S.width = 0;
         S.spp = batch->extra_spp;
-        S.passes = (batch->extra_spp + N - 1) / N;
+        S.n = n_lane;
+        S.passes = (batch->extra_spp + n_lane - 1) / n_lane;
         S.rays = batch->extra.count;
         S.item_begin = items;
         S.enum_begin = rays;

@@ -231,3 +231,33 @@ def test_wave_and_lane_walks_agree(srt, setup, N, mode):
     for k, (rgb, hits) in out.items():
         assert np.array_equal(hits, ref_hits), k
         np.testing.assert_allclose(rgb, ref_rgb, atol=2e-6, rtol=1e-5, err_msg=str(k))
+
+
+def test_sixteen_samples_per_traversal(srt, setup):
+    """N = 16 (views on wave-shared walks take passes of 16 samples, lane
+    walks passes of 8): the same hit ids as N = 4, with extra rays of 20
+    samples (three lane passes of 8, 8 and 4), views whose spp are not
+    multiples of 16, and the deep-stack pass (stack limit 1) for both
+    pass sizes."""
+    s = setup
+    say("batched N=16 vs N=4")
+    kw = dict(extra_origins=s["eoc"][:5000], extra_dirs=s["edc"][:5000], extra_spp=20, seed=8)
+    ref = srt.srt_batch_plan_create(s["bvh"], s["cams"], s["spp"], n_per_traversal=4,
+                                    persistent=False, walk="lane", **kw)
+    ref_rgb, ref_hits, _ = _run(ref)
+    del ref
+    for persistent in (False, True):
+        for walk in ("wave", "lane"):
+            for lim in (0, 1):
+                plan = srt.srt_batch_plan_create(s["bvh"], s["cams"], s["spp"],
+                                                 n_per_traversal=16, persistent=persistent,
+                                                 walk=walk, stack_limit=lim, **kw)
+                rgb, hits, cnt = _run(plan)
+                key = (persistent, walk, lim)
+                assert cnt[6] == plan.samples and cnt[7] == 0, key
+                if lim:
+                    assert cnt[5] > 0, key
+                assert np.array_equal(hits, ref_hits), key
+                np.testing.assert_allclose(rgb, ref_rgb, atol=2e-6, rtol=1e-5, err_msg=str(key))
+                del plan
+
