@@ -261,18 +261,22 @@ def test_differentiation_recipe_full_size(srt):
 def test_batched_workload_full_size_sampled(srt):
     """The batched workload at its stated size (3.3M Gaussians, 64 views of
     512x512 with spp drawn per view, 4M incoherent rays) in one persistent
-    graph launch: ids of 96 sampled camera pixels and 96 sampled incoherent
-    rays against the oracle, every view's spp included."""
+    graph launch in the configuration the benchmark times (width 4, leaf 8,
+    size split 4, 16 samples per traversal, refill threshold 16, 12
+    workgroups per CU): ids of 96 sampled camera pixels and 96 sampled
+    incoherent rays against the oracle, every view's spp included; the plain
+    launch's ids equal the persistent one's everywhere."""
     w = si.workload(5)
     sc = w["scene"]
     cams, spp = w["cameras"], w["spp"]
     eo, ed = w["incoherent"]
     say(f"batched workload at full size: {sc.num_gaussians} Gaussians, {len(cams)} views "
         f"{cams[0].width}x{cams[0].height}, {len(eo)} incoherent rays")
-    bvh = srt.srt_build_bvh(device_scene(sc), 4, 2, 4)
-    plan = srt.srt_batch_plan_create(bvh, cams, spp, extra_origins=_cu(eo), extra_dirs=_cu(ed),
-                                     extra_spp=1, seed=si.PHILOX_SEED, n_per_traversal=4,
-                                     persistent=True, refill_threshold=32, waves_per_cu=8)
+    bvh = srt.srt_build_bvh(device_scene(sc), 4, 8, 4)
+    kw = dict(extra_origins=_cu(eo), extra_dirs=_cu(ed), extra_spp=1, seed=si.PHILOX_SEED,
+              n_per_traversal=16)
+    plan = srt.srt_batch_plan_create(bvh, cams, spp, persistent=True, refill_threshold=16,
+                                     waves_per_cu=12, **kw)
     hits = torch.empty(plan.samples, dtype=torch.int32, device="cuda")
     cnt = srt.new_counters()
     rgb = plan.execute(hit_gid=hits, counters=cnt)
@@ -281,6 +285,13 @@ def test_batched_workload_full_size_sampled(srt):
     assert c["ray_samples"] == plan.samples and c["lost"] == 0
     hits = to_np(hits)
     rgb = to_np(rgb)
+    say("plain launch of the same workload")
+    plain = srt.srt_batch_plan_create(bvh, cams, spp, persistent=False, **kw)
+    p_hits = torch.empty(plain.samples, dtype=torch.int32, device="cuda")
+    plain.execute(hit_gid=p_hits)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(p_hits), hits)
+    del plain, p_hits
     rec = oracle.Records(sc)
     rng = np.random.default_rng(105)
     R = cams[0].width * cams[0].height
