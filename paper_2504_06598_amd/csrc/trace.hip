@@ -1162,13 +1162,14 @@ __global__ __launch_bounds__(kGroupBlock) void k_shadow_groups_wave(int64_t n, S
 
 // Work-stealing waves over the groups (the refill scheme of k_trace_persist),
 // with the record tests taken off the lanes' walks. A lane walks one group's
-// ray. Each iteration every walking lane hands up to two records of the leaf
-// it is at to a wave-wide queue in LDS, then takes one node step; the wave
-// then tests the queued records one per lane, reading the owner's ray from
-// the owner's registers with lane shuffles, and occludes samples of the
-// owner's group through a per-lane mask in LDS (64-bit LDS atomics). So the
-// node code and the record code do not run for different lanes of one step
-// one after the other, and a leaf's records are tested side by side.
+// ray. Each iteration every walking lane hands up to four records of the
+// leaf it is at (and of a leaf it pops right after) to a wave-wide queue in
+// LDS, then takes one node step; the wave then tests the queued records one
+// per lane, reading the owner's ray from the owner's registers with lane
+// shuffles, and occludes samples of the owner's group through a per-lane
+// mask in LDS (64-bit LDS atomics). So the node code and the record code do
+// not run for different lanes of one step one after the other, and a leaf's
+// records are tested side by side.
 // `a` describes the per-sample shadow rays (spp 1, any-hit); hit_gid of each
 // occluded sample receives a Gaussian that occluded it, -1 if none did. A
 // group whose stack overflows queues each of its samples for the deep pass.
@@ -1176,7 +1177,7 @@ template <int W, bool COUNT, int DM>
 __global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 4) void k_shadow_queue(TraceArgs a,
                                                                                 ShadowGroups g)
 {
-    constexpr int kRecPerStep = 2;
+    constexpr int kRecPerStep = 4;
     constexpr int kStack = LdsStack<W>::value;
     __shared__ int32_t lds[kStack * kPersistBlock];
     __shared__ uint32_t q_rec[kPersistBlock * kRecPerStep];
@@ -1245,11 +1246,27 @@ __global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 4) void k_shadow_queue(
         __syncthreads();
 
         // ---- one step of every walking lane: the records of the leaf it is
-        // at go to the queue (two at a time), then it takes one node step ----
-        uint32_t q_first = 0;
-        int q_n = 0;
+        // at go to the queue (up to kRecPerStep, from at most two leaves met
+        // one after the other), then it takes one node step ----
+        uint32_t q_first = 0, q_first2 = 0;
+        int q_n = 0, q_n2 = 0;
         if (active && walking) {
             bool ended = false;
+            // the next stack entry, or the whole tree after the start
+            // subtree; false when the walk is over
+            auto next_entry = [&]() -> bool {
+                if (sp > 0) {
+                    --sp;
+                    node = lds[sp * kPersistBlock + lane];
+                    return true;
+                }
+                if (!phase2) {
+                    phase2 = true;
+                    node = 0;
+                    return true;
+                }
+                return false;
+            };
             if (s_pend[lane] == 0) {
                 walking = false;  // every sample occluded
             } else if (++steps > a.max_steps) {
@@ -1261,14 +1278,16 @@ __global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 4) void k_shadow_queue(
                     q_n = (int)min(count, (uint32_t)kRecPerStep);
                     if (count > (uint32_t)q_n) {
                         node = make_leaf(first + (uint32_t)q_n, count - (uint32_t)q_n);
-                    } else if (sp > 0) {
-                        --sp;
-                        node = lds[sp * kPersistBlock + lane];
-                    } else if (!phase2) {
-                        phase2 = true;
-                        node = 0;
-                    } else {
+                    } else if (!next_entry()) {
                         walking = false;
+                    } else if (node < 0 && q_n < kRecPerStep) {
+                        const uint32_t f2 = leaf_first(node), c2 = leaf_count(node);
+                        q_first2 = f2;
+                        q_n2 = (int)min(c2, (uint32_t)(kRecPerStep - q_n));
+                        if (c2 > (uint32_t)q_n2)
+                            node = make_leaf(f2 + (uint32_t)q_n2, c2 - (uint32_t)q_n2);
+                        else if (!next_entry())
+                            walking = false;
                     }
                 }
                 if (walking && node >= 0) {
@@ -1322,17 +1341,21 @@ __global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 4) void k_shadow_queue(
             }
         }
 
-        // ---- queue the records (wave prefix sum of the counts) ----
-        int incl = q_n;
+        // ---- queue the records (wave prefix sum of the counts, bit by bit:
+        // a lane queues at most kRecPerStep < 8) ----
+        static_assert(kRecPerStep < 8, "three bits per count");
+        const int q_all = q_n + q_n2;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int excl = 0, total = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += v;
+        for (int bit = 0; bit < 3; ++bit) {
+            const unsigned long long m = __ballot((q_all >> bit) & 1);
+            excl += __popcll(m & below) << bit;
+            total += __popcll(m) << bit;
         }
-        const int total = __shfl(incl, 63, 64);
-        for (int i = 0; i < q_n; ++i) {
-            q_rec[incl - q_n + i] = q_first + (uint32_t)i;
-            q_lane[incl - q_n + i] = (uint8_t)lane;
+        for (int i = 0; i < q_all; ++i) {
+            q_rec[excl + i] = i < q_n ? q_first + (uint32_t)i : q_first2 + (uint32_t)(i - q_n);
+            q_lane[excl + i] = (uint8_t)lane;
         }
         __syncthreads();
 
