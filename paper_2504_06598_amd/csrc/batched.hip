@@ -679,8 +679,11 @@ constexpr int kWaveCap = 48;  // wave-shared stack entries (12 KB of LDS per wav
 // camera (tile, pass) groups, one per atomic, and walks each with its 64
 // rays together. (The extra rays go to k_persistent, launched before it at
 // its own occupancy: its lane walks need fewer registers than these.)
+// Registers are capped for 3 waves per SIMD (views at 16 samples per
+// traversal, 3.3M Gaussians: 1.57 -> 1.40 s with the spills; the plain tile
+// kernel lost with the same cap, 2.04 -> 2.17 s, and keeps 2).
 template <int W, int N, bool COUNT, int DM>
-__global__ __launch_bounds__(kPersistBlock) void k_persistent_wave(BatchArgs a,
+__global__ __launch_bounds__(kPersistBlock, 3) void k_persistent_wave(BatchArgs a,
                                                                    const void* __restrict__ nodes_v,
                                                                    const Record* __restrict__ recs)
 {

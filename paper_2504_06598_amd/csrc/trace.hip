@@ -469,8 +469,12 @@ __device__ __forceinline__ int64_t wave_pixel(int64_t t, int32_t w, int64_t h, i
 
 // PH: the pixels of an image launch get a.phases (2 or 4) lanes, one per
 // pass; otherwise one lane per ray (no registers for the colour hand-over).
+// Registers are capped for 3 waves per SIMD: the walk waits on its node and
+// record fetches, and at 8 samples per traversal the kernel would otherwise
+// hold 233 VGPRs and 2 waves (measured: camera rays of the path-tracer mix
+// 12.3 -> 10.4 ms with the spills; a cap for 4 waves was slower, 15.5 ms).
 template <int W, int N, bool ANY, bool COUNT, int DM, bool PH>
-__global__ __launch_bounds__(64) void k_trace_wave(TraceArgs a, const void* __restrict__ nodes_v,
+__global__ __launch_bounds__(64, 3) void k_trace_wave(TraceArgs a, const void* __restrict__ nodes_v,
                                                    const Record* __restrict__ recs)
 {
     __shared__ float lds_t[kWaveCap * 64];
