@@ -479,7 +479,9 @@ typedef struct srt_batch_plan srt_batch_plan; /* opaque, library-owned */
  * walks (the extra rays, and the views with walk = 1) take at most 8; the
  * per-sample results do not depend on it.
  * Copies the view table to the device and allocates the plan's work counter,
- * overflow queue and deep stacks; synchronises `stream`. The handle and the
+ * overflow queue and deep stacks (persistent plans: also the global-memory
+ * part of the lane stacks, 4 B per entry beyond the 24 kept in LDS, for
+ * every lane of the largest resident grid); synchronises `stream`. The handle and the
  * extra-ray arrays must outlive the plan. Errors: INVALID_ARG, OOM, HIP. */
 srt_status srt_batch_plan_create(const srt_bvh* bvh, const srt_batch* batch,
                                  const srt_trace_opts* opts, const srt_tuning* tuning,

@@ -84,6 +84,8 @@ struct BatchArgs {
     uint64_t* ovf_list;   // queued items (persistent) or rays (plain)
     int32_t* deep_stack;
     int32_t deep_cap;
+    int32_t* lane_stack;     // persistent lane kernel: stack entries beyond LDS
+    int32_t lane_stack_cap;  // entries per lane there
     int32_t threshold;
     int64_t max_steps;
     int32_t N;
@@ -407,8 +409,9 @@ __device__ __forceinline__ void decode_item(const BatchArgs& a, int64_t item, in
 // Records a walking lane hands to the wave's queue per step.
 constexpr int kQueueRecs = 8;
 
-// Lane stack entries of the queued lane refilling.
-constexpr int kQueueStack = 32;
+// Lane stack entries of the queued lane refilling kept in LDS; deeper ones
+// go to the lane's part of a global-memory stack (BatchArgs::lane_stack).
+constexpr int kQueueStack = 24;
 
 // LDS of the queued lane refilling: the lane stacks, the N sample keys of
 // each lane, the record queue (record index, owner lane).
@@ -434,9 +437,13 @@ template <int W, int N, bool COUNT, int DM>
 __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L, LaneCounts& cnt)
 {
     const int lane = threadIdx.x;
-    const int cap = min(kQueueStack, a.stack_cap);
+    const int cap = min(kQueueStack + a.lane_stack_cap, a.stack_cap);
     const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
     unsigned long long* keys = L.keys + lane;
+    // entry e >= kQueueStack of this lane's stack: glb[(e - kQueueStack) * gstride]
+    const int64_t gstride = (int64_t)gridDim.x * kPersistBlock;
+    int32_t* glb = a.lane_stack ? a.lane_stack + (int64_t)blockIdx.x * kPersistBlock + lane
+                                : nullptr;
     const unsigned long long miss_key = pack_key(INFINITY, 0x7FFFFFFF);
 
     bool active = false, walking = false, exhausted = false;
@@ -451,6 +458,18 @@ __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L
     int32_t node = 0;
     int sp = 0;
     int64_t steps = 0;
+    auto push = [&](int32_t v) {
+        if (sp < kQueueStack)
+            L.stack[sp * kPersistBlock + lane] = v;
+        else
+            glb[(int64_t)(sp - kQueueStack) * gstride] = v;
+        ++sp;
+    };
+    auto pop = [&]() -> int32_t {
+        --sp;
+        return sp < kQueueStack ? L.stack[sp * kPersistBlock + lane]
+                                : glb[(int64_t)(sp - kQueueStack) * gstride];
+    };
 
     for (;;) {
         // ---- refill idle lanes (wave-uniform decision) ----
@@ -509,8 +528,7 @@ __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L
                     if (count > (uint32_t)q_n) {
                         node = make_leaf(first + (uint32_t)q_n, count - (uint32_t)q_n);
                     } else if (sp > 0) {
-                        --sp;
-                        node = L.stack[sp * kPersistBlock + lane];
+                        node = pop();
                     } else {
                         walking = false;
                     }
@@ -531,15 +549,11 @@ __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L
                         } else {
 #pragma unroll
                             for (int c = W - 1; c >= 1; --c)
-                                if (key[c] != 0xFFFFFFFFu) {
-                                    L.stack[sp * kPersistBlock + lane] = child_at<W>(nb, key[c] & 7u);
-                                    ++sp;
-                                }
+                                if (key[c] != 0xFFFFFFFFu) push(child_at<W>(nb, key[c] & 7u));
                             node = child_at<W>(nb, key[0] & 7u);
                         }
                     } else if (sp > 0) {
-                        --sp;
-                        node = L.stack[sp * kPersistBlock + lane];
+                        node = pop();
                     } else {
                         walking = false;
                     }
@@ -855,6 +869,8 @@ struct srt_batch_plan {
     uint32_t* ctrl = nullptr;
     uint64_t* ovf = nullptr;
     int32_t* deep_stack = nullptr;
+    int32_t* lane_stack = nullptr;  // persistent lane kernel's stack entries beyond LDS
+    int32_t lane_stack_cap = 0;
     int64_t ovf_cap = 0;
     int32_t n_cu = 0;
     int32_t resident[2][2] = {{1, 1}, {1, 1}};  // [counters][lane, wave]: workgroups per CU
@@ -879,6 +895,7 @@ void plan_free(srt_batch_plan* p)
     (void)hipFree(p->ctrl);
     (void)hipFree(p->ovf);
     (void)hipFree(p->deep_stack);
+    (void)hipFree(p->lane_stack);
     delete p;
 }
 
@@ -915,6 +932,8 @@ srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* count
     a.ovf_list = p->ovf;
     a.deep_stack = p->deep_stack;
     a.deep_cap = deep_stack_cap(b);
+    a.lane_stack = p->lane_stack;
+    a.lane_stack_cap = p->lane_stack ? p->lane_stack_cap : 0;
     a.threshold = std::max(1, std::min(64, p->tuning.refill_threshold));
     a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
     a.N = p->opts.n_per_traversal;
@@ -1095,6 +1114,19 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
             hipSuccess) {
         plan_free(p);
         return SRT_ERR_OOM;
+    }
+    if (tuning->persistent) {
+        // every lane of the largest lane-kernel grid gets the entries a walk
+        // can need beyond its LDS part
+        p->lane_stack_cap = std::max(0, deep_stack_cap(b) - kQueueStack);
+        const size_t lanes = (size_t)p->n_cu *
+                             (size_t)std::max(p->resident[0][0], p->resident[1][0]) * kPersistBlock;
+        if (p->lane_stack_cap > 0 &&
+            hipMalloc(&p->lane_stack, sizeof(int32_t) * lanes * (size_t)p->lane_stack_cap) !=
+                hipSuccess) {
+            plan_free(p);
+            return SRT_ERR_OOM;
+        }
     }
     if (!p->segs.empty() &&
         hipMemcpyAsync(p->d_segs, p->segs.data(), sizeof(Segment) * p->segs.size(),
