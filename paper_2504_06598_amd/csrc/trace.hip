@@ -992,63 +992,107 @@ __global__ void k_spawn(int64_t R, int32_t spp, uint32_t rid_base, const float* 
     }
 }
 
-__global__ void k_compose(int64_t R, int32_t spp, int32_t deg, const float* __restrict__ sh,
-                          const float* __restrict__ cd, const int32_t* __restrict__ cam_gid,
-                          SecRays shr, SecRays mrr, const int32_t* __restrict__ sh_hit,
-                          const int32_t* __restrict__ mr_hit, float bg0, float bg1, float bg2,
-                          float* __restrict__ rgb, uint8_t* __restrict__ vis_out,
-                          int32_t* __restrict__ mirror_out)
+// One thread per pixel, 64 pixels per workgroup. The per-sample inputs are
+// staged through LDS 16 samples of each pixel at a time, loaded by
+// consecutive threads from consecutive samples (a thread reading its own
+// pixel's samples would touch a different cache line per lane on every
+// load); the per-sample outputs are written from the same coalesced pass.
+constexpr int kComposePix = 64;
+constexpr int kComposeChunk = 16;
+
+__global__ __launch_bounds__(kComposePix) void k_compose(
+    int64_t R, int32_t spp, int32_t deg, const float* __restrict__ sh,
+    const float* __restrict__ cd, const int32_t* __restrict__ cam_gid, SecRays shr, SecRays mrr,
+    const int32_t* __restrict__ sh_hit, const int32_t* __restrict__ mr_hit, float bg0, float bg1,
+    float bg2, float* __restrict__ rgb, uint8_t* __restrict__ vis_out,
+    int32_t* __restrict__ mirror_out)
 {
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= R) return;
-    const float dx = cd[3 * p], dy = cd[3 * p + 1], dz = cd[3 * p + 2];
-    const float n = sqrtf(dx * dx + dy * dy + dz * dz);
+    // sample k of pixel t of the chunk at [t * (kComposeChunk + 1) + k]
+    constexpr int kRow = kComposeChunk + 1;
+    __shared__ uint8_t s_flag[kComposePix * kRow];  // 1 shadow ray, 2 mirror ray, 4 unoccluded
+    __shared__ int32_t s_gid[kComposePix * kRow];   // camera hit, or mirror hit
+    __shared__ float s_nl[kComposePix * kRow];      // max(light direction y, 0)
+    const int t = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * kComposePix;
+    const int64_t p = p0 + t;
+    const bool in = p < R;
     float Yc[16], Ym[16];
-    sh_eval(deg, dx / n, dy / n, dz / n, Yc);
-    sh_eval(deg, dx / n, -dy / n, dz / n, Ym);
+    if (in) {
+        const float dx = cd[3 * p], dy = cd[3 * p + 1], dz = cd[3 * p + 2];
+        const float n = sqrtf(dx * dx + dy * dy + dz * dz);
+        sh_eval(deg, dx / n, dy / n, dz / n, Yc);
+        sh_eval(deg, dx / n, -dy / n, dz / n, Ym);
+    }
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
     // a pixel's samples often shade the same Gaussian: the last colour of
     // each kind is kept (the same inputs give the same bits)
     int32_t last_g = -1, last_m = -1;
     float3 col_g = make_float3(0.0f, 0.0f, 0.0f), col_m = col_g;
-    for (int32_t s = 0; s < spp; ++s) {
-        const int64_t i = p * spp + s;
-        const bool has_shadow = shr.tmax[i] > shr.tmin[i];
-        const bool has_mirror = mrr.tmax[i] > mrr.tmin[i];
-        float c0 = bg0, c1 = bg1, c2 = bg2;
-        uint8_t vis = 255;
-        int32_t mg = -2;
-        if (has_shadow) {
-            const float V = sh_hit[i] < 0 ? 1.0f : 0.0f;
-            vis = sh_hit[i] < 0 ? 1 : 0;
-            if (!has_mirror) {
-                const int32_t g = cam_gid[i];
-                if (g != last_g) {
-                    col_g = clamp0(sh_colour_pre(sh, deg, g, Yc));
-                    last_g = g;
+    for (int32_t c0 = 0; c0 < spp; c0 += kComposeChunk) {
+        const int n_c = min(kComposeChunk, spp - c0);
+        __syncthreads();
+        for (int e = t; e < kComposePix * kComposeChunk; e += kComposePix) {
+            const int px = e / kComposeChunk, k = e % kComposeChunk;
+            if (k >= n_c || p0 + px >= R) continue;
+            const int64_t i = (p0 + px) * spp + c0 + k;
+            const bool has_shadow = shr.tmax[i] > shr.tmin[i];
+            const bool has_mirror = mrr.tmax[i] > mrr.tmin[i];
+            uint8_t f = 0;
+            int32_t g = 0;
+            float nl = 0.0f;
+            uint8_t vis = 255;
+            int32_t mg = -2;
+            if (has_shadow) {
+                const bool unocc = sh_hit[i] < 0;
+                vis = unocc ? 1 : 0;
+                f = (uint8_t)(1 | (unocc ? 4 : 0));
+                if (!has_mirror) {
+                    g = cam_gid[i];
+                } else {
+                    f |= 2;
+                    g = mg = mr_hit[i];
+                    nl = fmaxf(shr.d[3 * i + 1], 0.0f);
                 }
-                const float3 c = col_g;
-                const float f = 0.3f + 0.7f * V;
-                c0 = c.x * f; c1 = c.y * f; c2 = c.z * f;
-            } else {
-                float3 Lm = make_float3(bg0, bg1, bg2);
-                mg = mr_hit[i];
-                if (mg >= 0) {
-                    if (mg != last_m) {
-                        col_m = clamp0(sh_colour_pre(sh, deg, mg, Ym));
-                        last_m = mg;
-                    }
-                    Lm = col_m;
-                }
-                const float nl = fmaxf(shr.d[3 * i + 1], 0.0f);
-                const float lit = 0.5f * V * nl;
-                c0 = lit + 0.5f * Lm.x; c1 = lit + 0.5f * Lm.y; c2 = lit + 0.5f * Lm.z;
             }
+            s_flag[px * kRow + k] = f;
+            s_gid[px * kRow + k] = g;
+            s_nl[px * kRow + k] = nl;
+            if (vis_out) vis_out[i] = vis;
+            if (mirror_out) mirror_out[i] = mg;
         }
-        a0 += c0; a1 += c1; a2 += c2;
-        if (vis_out) vis_out[i] = vis;
-        if (mirror_out) mirror_out[i] = mg;
+        __syncthreads();
+        if (!in) continue;
+        for (int k = 0; k < n_c; ++k) {
+            const uint8_t f = s_flag[t * kRow + k];
+            float c0_ = bg0, c1_ = bg1, c2_ = bg2;
+            if (f & 1) {
+                const float V = (f & 4) ? 1.0f : 0.0f;
+                const int32_t g = s_gid[t * kRow + k];
+                if (!(f & 2)) {
+                    if (g != last_g) {
+                        col_g = clamp0(sh_colour_pre(sh, deg, g, Yc));
+                        last_g = g;
+                    }
+                    const float3 c = col_g;
+                    const float fv = 0.3f + 0.7f * V;
+                    c0_ = c.x * fv; c1_ = c.y * fv; c2_ = c.z * fv;
+                } else {
+                    float3 Lm = make_float3(bg0, bg1, bg2);
+                    if (g >= 0) {
+                        if (g != last_m) {
+                            col_m = clamp0(sh_colour_pre(sh, deg, g, Ym));
+                            last_m = g;
+                        }
+                        Lm = col_m;
+                    }
+                    const float lit = 0.5f * V * s_nl[t * kRow + k];
+                    c0_ = lit + 0.5f * Lm.x; c1_ = lit + 0.5f * Lm.y; c2_ = lit + 0.5f * Lm.z;
+                }
+            }
+            a0 += c0_; a1 += c1_; a2 += c2_;
+        }
     }
+    if (!in) return;
     const float inv = 1.0f / (float)spp;
     rgb[3 * p] = a0 * inv;
     rgb[3 * p + 1] = a1 * inv;
@@ -1751,7 +1795,7 @@ srt_status srt_trace_pathmix(const srt_bvh* b, const srt_camera* cam, uint32_t r
         if (st != SRT_OK) return st;
     }
     if (stages & SRT_PATHMIX_COMPOSE) {
-        k_compose<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(
+        k_compose<<<(unsigned)((R + kComposePix - 1) / kComposePix), kComposePix, 0, s>>>(
             R, opts->spp, b->deg, b->sh, w.cd, cg, w.sh, w.mr, w.sh_hit, w.mr_hit, opts->bg[0],
             opts->bg[1], opts->bg[2], rgb, shadow_vis, mirror_gid);
         SRT_HIP_TRY(hipGetLastError());
