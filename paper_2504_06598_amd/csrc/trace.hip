@@ -945,24 +945,18 @@ __global__ void k_spawn(int64_t R, int32_t spp, uint32_t rid_base, const float* 
     const bool on_gauss = g >= 0 && tg <= tp;
     const bool on_plane = !on_gauss && tp < INFINITY;
     const uint32_t rid = rid_base + (uint32_t)p;
-    // empty slots: tmin = 1 > tmax = 0 (the trace skips them)
-    sh.tmin[idx] = 1.0f;
-    sh.tmax[idx] = 0.0f;
-    mr.tmin[idx] = 1.0f;
-    mr.tmax[idx] = 0.0f;
-    for (int i = 0; i < 3; ++i) {
-        sh.o[3 * idx + i] = 0.0f;
-        sh.d[3 * idx + i] = 0.0f;
-        mr.o[3 * idx + i] = 0.0f;
-        mr.d[3 * idx + i] = 0.0f;
+    // empty slots: tmin = 1 > tmax = 0; the kernels that read these rays
+    // skip them, and nothing reads an empty slot's other fields
+    if (!on_plane) {
+        mr.tmin[idx] = 1.0f;
+        mr.tmax[idx] = 0.0f;
     }
-    sh.ign[idx] = -1;
-    mr.ign[idx] = -1;
-    sh.rid[idx] = rid;
-    mr.rid[idx] = rid;
-    sh.sid[idx] = s;
-    mr.sid[idx] = s;
-    if (!on_gauss && !on_plane) return;
+    if (!on_gauss && !on_plane) {
+        sh.tmin[idx] = 1.0f;
+        sh.tmax[idx] = 0.0f;
+        sh.ign[idx] = -1;
+        return;
+    }
     const float t = on_gauss ? tg : tp;
     float P[3];
     for (int i = 0; i < 3; ++i) {
@@ -982,6 +976,8 @@ __global__ void k_spawn(int64_t R, int32_t spp, uint32_t rid_base, const float* 
     sh.tmin[idx] = pm.tmin_secondary;
     sh.tmax[idx] = len;
     sh.ign[idx] = on_gauss ? g : -1;
+    sh.rid[idx] = rid;
+    sh.sid[idx] = s;
     if (on_plane) {
         for (int i = 0; i < 3; ++i) mr.o[3 * idx + i] = P[i];
         mr.d[3 * idx] = d[0];
@@ -989,6 +985,9 @@ __global__ void k_spawn(int64_t R, int32_t spp, uint32_t rid_base, const float* 
         mr.d[3 * idx + 2] = d[2];
         mr.tmin[idx] = pm.tmin_secondary;
         mr.tmax[idx] = INFINITY;
+        mr.ign[idx] = -1;
+        mr.rid[idx] = rid;
+        mr.sid[idx] = s;
     }
 }
 
