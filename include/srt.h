@@ -468,6 +468,9 @@ typedef struct {
     int32_t persistent;
     int32_t refill_threshold;  /* 1..64 */
     int32_t waves_per_cu;      /* >= 1 */
+    int32_t lds_stack;         /* work-stealing lane kernel: stack entries per lane
+                                  kept in LDS, 1..24, 0 = 24; deeper entries live in
+                                  global memory (smaller values test that part) */
 } srt_tuning;
 
 typedef struct srt_batch_plan srt_batch_plan; /* opaque, library-owned */
@@ -480,7 +483,7 @@ typedef struct srt_batch_plan srt_batch_plan; /* opaque, library-owned */
  * per-sample results do not depend on it.
  * Copies the view table to the device and allocates the plan's work counter,
  * overflow queue and deep stacks (persistent plans: also the global-memory
- * part of the lane stacks, 4 B per entry beyond the 24 kept in LDS, for
+ * part of the lane stacks, 4 B per entry beyond those kept in LDS, for
  * every lane of the largest resident grid); synchronises `stream`. The handle and the
  * extra-ray arrays must outlive the plan. Errors: INVALID_ARG, OOM, HIP. */
 srt_status srt_batch_plan_create(const srt_bvh* bvh, const srt_batch* batch,

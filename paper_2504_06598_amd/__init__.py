@@ -445,7 +445,8 @@ def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_d
                           extra_spp=1, ray_id_base=0, seed=0, n_per_traversal=4,
                           sample_offset=0, bg=(0.0, 0.0, 0.0), stack_limit=0, persistent=True,
                           refill_threshold=16, waves_per_cu=8, depth_mode=0,
-                          depth_axis=(0.0, 0.0, 0.0), rng="philox", walk="auto") -> BatchPlan:
+                          depth_axis=(0.0, 0.0, 0.0), rng="philox", walk="auto",
+                          lds_stack=0) -> BatchPlan:
     """Plan of the batched forward (views with their spp, plus extra rays).
     walk: "auto"/"wave" trace the views' 8x8 tiles as wave-shared walks,
     "lane" one lane per pixel; extra rays always walk one lane per ray."""
@@ -460,7 +461,8 @@ def srt_batch_plan_create(bvh: Bvh, cameras, spp, *, extra_origins=None, extra_d
                           int(extra_spp) if n_extra else 0, int(ray_id_base))
     opts = _opts(seed, 1, n_per_traversal, sample_offset, bg, False, stack_limit, depth_mode,
                  depth_axis, rng=rng, walk=walk)
-    tun = _lib.SrtTuning(1 if persistent else 0, int(refill_threshold), int(waves_per_cu))
+    tun = _lib.SrtTuning(1 if persistent else 0, int(refill_threshold), int(waves_per_cu),
+                         int(lds_stack))
     h = C.c_void_p()
     _lib.check("srt_batch_plan_create", lib.srt_batch_plan_create(
         bvh.handle, C.byref(batch), C.byref(opts), C.byref(tun), _stream(), C.byref(h)))

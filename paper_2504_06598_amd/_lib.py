@@ -65,7 +65,7 @@ class SrtBatch(C.Structure):
 
 class SrtTuning(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("refill_threshold", C.c_int32),
-                ("waves_per_cu", C.c_int32)]
+                ("waves_per_cu", C.c_int32), ("lds_stack", C.c_int32)]
 
 
 # name -> (restype, argtypes)

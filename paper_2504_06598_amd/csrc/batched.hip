@@ -86,6 +86,7 @@ struct BatchArgs {
     int32_t deep_cap;
     int32_t* lane_stack;     // persistent lane kernel: stack entries beyond LDS
     int32_t lane_stack_cap;  // entries per lane there
+    int32_t lds_stack;       // entries per lane kept in LDS (<= kQueueStack)
     int32_t threshold;
     int64_t max_steps;
     int32_t N;
@@ -437,10 +438,11 @@ template <int W, int N, bool COUNT, int DM>
 __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L, LaneCounts& cnt)
 {
     const int lane = threadIdx.x;
-    const int cap = min(kQueueStack + a.lane_stack_cap, a.stack_cap);
+    const int n_lds = a.lds_stack;
+    const int cap = min(n_lds + a.lane_stack_cap, a.stack_cap);
     const WideNode<W>* nodes = static_cast<const WideNode<W>*>(a.nodes);
     unsigned long long* keys = L.keys + lane;
-    // entry e >= kQueueStack of this lane's stack: glb[(e - kQueueStack) * gstride]
+    // entry e >= n_lds of this lane's stack: glb[(e - n_lds) * gstride]
     const int64_t gstride = (int64_t)gridDim.x * kPersistBlock;
     int32_t* glb = a.lane_stack ? a.lane_stack + (int64_t)blockIdx.x * kPersistBlock + lane
                                 : nullptr;
@@ -459,16 +461,16 @@ __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L
     int sp = 0;
     int64_t steps = 0;
     auto push = [&](int32_t v) {
-        if (sp < kQueueStack)
+        if (sp < n_lds)
             L.stack[sp * kPersistBlock + lane] = v;
         else
-            glb[(int64_t)(sp - kQueueStack) * gstride] = v;
+            glb[(int64_t)(sp - n_lds) * gstride] = v;
         ++sp;
     };
     auto pop = [&]() -> int32_t {
         --sp;
-        return sp < kQueueStack ? L.stack[sp * kPersistBlock + lane]
-                                : glb[(int64_t)(sp - kQueueStack) * gstride];
+        return sp < n_lds ? L.stack[sp * kPersistBlock + lane]
+                          : glb[(int64_t)(sp - n_lds) * gstride];
     };
 
     for (;;) {
@@ -934,6 +936,7 @@ srt_status enqueue(srt_batch_plan* p, float* rgb, int32_t* hits, uint64_t* count
     a.deep_cap = deep_stack_cap(b);
     a.lane_stack = p->lane_stack;
     a.lane_stack_cap = p->lane_stack ? p->lane_stack_cap : 0;
+    a.lds_stack = p->tuning.lds_stack > 0 ? p->tuning.lds_stack : kQueueStack;
     a.threshold = std::max(1, std::min(64, p->tuning.refill_threshold));
     a.max_steps = 2 * b->num_nodes + 2 * b->G + 64;
     a.N = p->opts.n_per_traversal;
@@ -1018,7 +1021,8 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
     if (batch->extra.count > 0 &&
         (!batch->extra.origins || !batch->extra.dirs || batch->extra_spp < 1))
         return SRT_ERR_INVALID_ARG;
-    if (tuning->refill_threshold < 1 || tuning->refill_threshold > 64 || tuning->waves_per_cu < 1)
+    if (tuning->refill_threshold < 1 || tuning->refill_threshold > 64 || tuning->waves_per_cu < 1 ||
+        tuning->lds_stack < 0 || tuning->lds_stack > kQueueStack)
         return SRT_ERR_INVALID_ARG;
     srt_batch_plan* p = new srt_batch_plan();
     p->bvh = b;
@@ -1118,7 +1122,8 @@ srt_status srt_batch_plan_create(const srt_bvh* b, const srt_batch* batch,
     if (tuning->persistent) {
         // every lane of the largest lane-kernel grid gets the entries a walk
         // can need beyond its LDS part
-        p->lane_stack_cap = std::max(0, deep_stack_cap(b) - kQueueStack);
+        const int n_lds = tuning->lds_stack > 0 ? tuning->lds_stack : kQueueStack;
+        p->lane_stack_cap = std::max(0, deep_stack_cap(b) - n_lds);
         const size_t lanes = (size_t)p->n_cu *
                              (size_t)std::max(p->resident[0][0], p->resident[1][0]) * kPersistBlock;
         if (p->lane_stack_cap > 0 &&

@@ -186,8 +186,24 @@ def test_deep_stack_and_widths(srt, setup):
     for W, L in [(2, 1), (8, 8), (8, 2)]:
         bvh = srt.srt_build_bvh(s["dsc"], W, L)
         plan = _plan(srt, s, bvh=bvh, persistent=True)
-        _, hits, _ = _run(plan)
+        _, hits, cnt = _run(plan)
         assert np.array_equal(hits, ref_hits), (W, L)
+    # the lane kernel's stacks with 1 or 2 entries per lane in LDS: every
+    # deeper entry goes to the lanes' global-memory part, none to the deep pass
+    for lds in (1, 2):
+        for walk in ("wave", "lane"):
+            plan = _plan(srt, s, persistent=True, walk=walk, lds_stack=lds)
+            _, hits, cnt = _run(plan)
+            assert np.array_equal(hits, ref_hits), (lds, walk)
+            assert cnt[5] == 0 and cnt[7] == 0 and cnt[6] == plan.samples
+    for bad in (-1, 25):
+        with pytest.raises(srt.SrtError) as e:
+            _plan(srt, s, persistent=True, lds_stack=bad)
+        assert e.value.code == 1
+    for n in (3, 32):
+        with pytest.raises(srt.SrtError) as e:
+            srt.srt_batch_plan_create(s["bvh"], s["cams"], s["spp"], n_per_traversal=n)
+        assert e.value.code == 1
 
 
 def test_autotuner_guards_and_picks(srt, setup, tmp_path):
