@@ -90,6 +90,28 @@ __device__ __forceinline__ void atomic_add_f32(float* p, float v)
     if (v != 0.0f) atomicAdd(p, v);
 }
 
+// x of a lane 16 * r + (i <op> j) of the same row of 16, by a DPP move
+// (a vector-ALU operand modifier, where a lane shuffle goes through LDS).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum of x over the wave's 64 lanes, held by every lane (each lane may add
+// in its own order, so the lanes' values can differ in the last bits):
+// within quads and rows of 16 by DPP, across rows by two lane shuffles.
+__device__ __forceinline__ float wave_sum(float x)
+{
+    x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_move<0x124>(x);  // row_ror:4
+    x += dpp_move<0x128>(x);  // row_ror:8
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+}
+
 struct Table {
     int32_t* keys;  // [kTableSlots], -1 = empty
     float* vals;    // [kAccVals][kTableSlots]
@@ -400,12 +422,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_backward(BwdArgs a, const void* _
                         const uint64_t m = __ballot(c);
                         if (m != 0) {
 #pragma unroll
-                            for (int j = 0; j < kAccVals; ++j) {
-                                float x = c ? v[j] : 0.0f;
-#pragma unroll
-                                for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-                                v[j] = x;
-                            }
+                            for (int j = 0; j < kAccVals; ++j) v[j] = wave_sum(c ? v[j] : 0.0f);
                             if ((int)__lane_id() == __builtin_ctzll(m))
                                 table_add(table, a.acc, r.gid, v);
                         }
