@@ -98,18 +98,34 @@ __device__ __forceinline__ float dpp_move(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
+// x + (x of lane i ^ 16) and x + (x of lane i ^ 32): the CDNA4 lane-swap
+// instructions exchange rows 1 and 3 with rows 0 and 2 (resp. the wave's
+// halves) of two registers; swapping a register with itself gives both
+// values of every pair in the two results.
+__device__ __forceinline__ float add_xor16(float x)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(x), __float_as_int(x), false,
+                                                    false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
+__device__ __forceinline__ float add_xor32(float x)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(x), __float_as_int(x), false,
+                                                    false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
 // Sum of x over the wave's 64 lanes, held by every lane (each lane may add
 // in its own order, so the lanes' values can differ in the last bits):
-// within quads and rows of 16 by DPP, across rows by two lane shuffles.
+// within quads and rows of 16 by DPP, across rows by lane swaps; no LDS.
 __device__ __forceinline__ float wave_sum(float x)
 {
     x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]
     x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]
     x += dpp_move<0x124>(x);  // row_ror:4
     x += dpp_move<0x128>(x);  // row_ror:8
-    x += __shfl_xor(x, 16, 64);
-    x += __shfl_xor(x, 32, 64);
-    return x;
+    return add_xor32(add_xor16(x));
 }
 
 struct Table {
