@@ -570,17 +570,20 @@ __device__ __forceinline__ void persist_queue(const BatchArgs& a, QueueLds<N>& L
             }
         }
 
-        // ---- queue the records (wave prefix sum of the counts) ----
-        int incl = q_n;
+        // ---- queue the records (wave prefix sum of the counts, bit by
+        // bit: a lane queues at most kQueueRecs <= 8) ----
+        static_assert(kQueueRecs <= 8, "four bits per count");
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int excl = 0, total = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += v;
+        for (int bit = 0; bit < 4; ++bit) {
+            const unsigned long long m = __ballot((q_n >> bit) & 1);
+            excl += __popcll(m & below) << bit;
+            total += __popcll(m) << bit;
         }
-        const int total = __shfl(incl, 63, 64);
         for (int i = 0; i < q_n; ++i) {
-            L.q_rec[incl - q_n + i] = q_first + (uint32_t)i;
-            L.q_lane[incl - q_n + i] = (uint8_t)lane;
+            L.q_rec[excl + i] = q_first + (uint32_t)i;
+            L.q_lane[excl + i] = (uint8_t)lane;
         }
         if (lane == 0) L.dirty = 0ull;
         __syncthreads();
