@@ -58,7 +58,7 @@ def test_summariser_scales_counters_by_the_calibration_copy(tmp_path, capsys):
                                           [(copy, 131072.0, 262144.0, 1.0, 1.0)]:
         disp += 1
         for cn, cv in (("FETCH_SIZE", fetch), ("WRITE_SIZE", write), ("TCC_HIT_sum", hit),
-                       ("TCC_MISS_sum", miss)):
+                       ("TCC_MISS_sum", miss), ("VALUBusy", 95.26), ("VALUUtilization", 39.4)):
             rows.append({"Dispatch_Id": disp, "Kernel_Name": name, "Counter_Name": cn,
                          "Counter_Value": cv})
     _write_csv(d / "run_counter_collection.csv", rows)
@@ -74,5 +74,7 @@ def test_summariser_scales_counters_by_the_calibration_copy(tmp_path, capsys):
     # FETCH_SIZE x 2 (the copy reads 256 MiB, reported as 128 MiB), WRITE_SIZE x 1
     assert k["hbm_bytes_per_launch"] == 1024 * (100 * 2 + 50)
     assert abs(k["l2_hit_rate"] - 0.9) < 1e-9
+    assert k["valu_busy"] == 95.3  # percent, rounded to 0.1
+    assert k["valu_lanes_active"] == 39.4
     assert k["ms"] == [2.0]
     assert rec["sources_sha1"] == bench.sources_sha1(bench.PROFILE_SOURCES)
