@@ -52,7 +52,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--width", type=int, default=4)
-    p.add_argument("--leaf", type=int, default=2)
+    p.add_argument("--leaf", type=int, default=4)
     p.add_argument("--n-per-traversal", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--overlap", action=argparse.BooleanOptionalAction, default=True,

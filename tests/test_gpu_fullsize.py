@@ -1,6 +1,6 @@
 """GPU parity at full size, in the launch configurations the benchmark times:
 the path-tracer mix and its camera-ray kernel on the 1M-Gaussian scene
-(1920x1080, 16 spp, N = 8 samples per traversal, width 4, leaf size 2), the
+(1920x1080, 16 spp, N = 8 samples per traversal, width 4, leaf size 4), the
 forward + backward of the 1M ring views (8 x 800x800, 4 spp), and the
 differentiation recipe (the 1,000-Gaussian scene, 8 x 800x800, 4 spp) against
 the FP64 exact gradient and finite differences.
@@ -20,7 +20,7 @@ from _parity import compare_ids, compare_rgb, device_scene, say, to_np
 
 pytestmark = pytest.mark.gpu
 
-BENCH_W, BENCH_L, BENCH_N = 4, 2, 8
+BENCH_W, BENCH_L, BENCH_N = 4, 4, 8
 NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
