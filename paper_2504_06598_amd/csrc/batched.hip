@@ -20,11 +20,13 @@
 //    samples' colours / spp).
 // With wave-shared walks (srt_trace_opts.walk != 1) the camera pixels go to
 // tile kernels instead: plain, one wave per 8x8 tile looping over its
-// passes; persistent, each wave first joins the lane refilling for the extra
-// rays, then claims one (tile, pass) group of 64 items per atomic on a second
-// counter and walks it with its 64 rays together (walk_wave).
-// All queue items whose on-chip stack overflows; a deep pass with a
-// global-memory stack reruns them (an item contributes only once complete).
+// passes; persistent, after the extra rays' work-stealing grid, a second
+// persistent grid claims one (tile, pass) group of 64 items per atomic on a
+// second counter and walks it with its 64 rays together (walk_wave).
+// Items whose stack overflows (the lane kernel keeps entries beyond its LDS
+// part in global memory, so there only a walk past the tree's depth bound
+// does) are queued; a deep pass with a global-memory stack reruns them (an
+// item contributes only once complete).
 #include <algorithm>
 #include <climits>
 #include <vector>
