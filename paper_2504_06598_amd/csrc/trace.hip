@@ -473,7 +473,9 @@ __device__ __forceinline__ int64_t wave_pixel(int64_t t, int32_t w, int64_t h, i
 // record fetches, and at 8 samples per traversal the kernel would otherwise
 // hold 233 VGPRs and 2 waves (measured: camera rays of the path-tracer mix
 // 12.3 -> 10.4 ms with the spills; a cap for 4 waves was slower, 15.5 ms).
-template <int W, int N, bool ANY, bool COUNT, int DM, bool PH>
+// SH: false for launches without colour output (ids and depths only; the
+// path-tracer mix's camera rays), whose registers then hold no colours.
+template <int W, int N, bool ANY, bool COUNT, int DM, bool PH, bool SH = true>
 __global__ __launch_bounds__(64, 3) void k_trace_wave(TraceArgs a, const void* __restrict__ nodes_v,
                                                    const Record* __restrict__ recs)
 {
@@ -501,7 +503,7 @@ __global__ __launch_bounds__(64, 3) void k_trace_wave(TraceArgs a, const void* _
     const ForwardCtx fc{recs, a.purpose, a.k0, a.k1};
     const DepthCtx dc = make_depth(a.depth_mode, a.depth_axis, rd, a.r_max);
     const float slack = DM == 0 ? 0.0f : dc.node_slack;
-    const bool shade = a.rgb != nullptr && !ANY;
+    const bool shade = SH && a.rgb != nullptr && !ANY;
     const int cap = min(kWaveCap, a.stack_cap);
 
     Counts cnt;
@@ -556,6 +558,7 @@ __global__ __launch_bounds__(64, 3) void k_trace_wave(TraceArgs a, const void* _
             const int64_t o = ray * a.spp + pass * N + k;
             if (a.hit_gid) a.hit_gid[o] = hit ? st.bg[k] : -1;
             if (a.hit_t) a.hit_t[o] = hit ? st.bt[k] : INFINITY;
+            if constexpr (!SH) continue;
             float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
             if (ANY) {
                 c0 = c1 = c2 = hit ? 0.0f : 1.0f;
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(64, 3) void k_trace_wave(TraceArgs a, const void* _
             }
         }
     }
-    if (PH && !overflow) {
+    if (PH && SH && !overflow) {
         // the pixel's colour sums its samples in sample order, as one lane
         // would: phase 0's samples, then phase 1's, ...; the running sum moves
         // to the pixel's lane of the next phase
@@ -601,7 +604,7 @@ __global__ __launch_bounds__(64, 3) void k_trace_wave(TraceArgs a, const void* _
             a.ovf_list[slot] = (uint32_t)ray;
         }
     } else if (valid) {
-        if (a.rgb && phase == Q - 1) {
+        if (SH && a.rgb && phase == Q - 1) {
             const float inv = 1.0f / (float)a.spp;
             a.rgb[3 * ray] = acc0 * inv;
             a.rgb[3 * ray + 1] = acc1 * inv;
@@ -621,39 +624,49 @@ __global__ __launch_bounds__(64, 3) void k_trace_wave(TraceArgs a, const void* _
 
 using WaveFn = void (*)(TraceArgs, const void*, const Record*);
 
-template <int W, int N, bool ANY, int DM, bool PH>
+template <int W, int N, bool ANY, int DM, bool PH, bool SH = true>
 WaveFn wave_c(bool count)
 {
-    return count ? k_trace_wave<W, N, ANY, true, DM, PH> : k_trace_wave<W, N, ANY, false, DM, PH>;
+    return count ? k_trace_wave<W, N, ANY, true, DM, PH, SH>
+                 : k_trace_wave<W, N, ANY, false, DM, PH, SH>;
 }
 
+// shade = false: the launch writes no colours (instantiated without them for
+// the pass-per-lane layouts at 4 and 8 samples per traversal)
 template <int W, int DM>
-WaveFn wave_w(int N, bool any, bool count, bool ph)
+WaveFn wave_w(int N, bool any, bool count, bool ph, bool shade)
 {
     if (any) return N == 1 && !ph ? wave_c<W, 1, true, DM, false>(count) : nullptr;
     switch (N) {
     case 1: return ph ? wave_c<W, 1, false, DM, true>(count) : wave_c<W, 1, false, DM, false>(count);
     case 2: return ph ? wave_c<W, 2, false, DM, true>(count) : wave_c<W, 2, false, DM, false>(count);
-    case 4: return ph ? wave_c<W, 4, false, DM, true>(count) : wave_c<W, 4, false, DM, false>(count);
-    case 8: return ph ? wave_c<W, 8, false, DM, true>(count) : wave_c<W, 8, false, DM, false>(count);
+    case 4:
+        if (ph) return shade ? wave_c<W, 4, false, DM, true>(count)
+                             : wave_c<W, 4, false, DM, true, false>(count);
+        return wave_c<W, 4, false, DM, false>(count);
+    case 8:
+        if (ph) return shade ? wave_c<W, 8, false, DM, true>(count)
+                             : wave_c<W, 8, false, DM, true, false>(count);
+        return wave_c<W, 8, false, DM, false>(count);
     }
     return nullptr;
 }
 
 template <int DM>
-WaveFn wave_dm(int W, int N, bool any, bool count, bool ph)
+WaveFn wave_dm(int W, int N, bool any, bool count, bool ph, bool shade)
 {
     switch (W) {
-    case 2: return wave_w<2, DM>(N, any, count, ph);
-    case 4: return wave_w<4, DM>(N, any, count, ph);
-    case 8: return wave_w<8, DM>(N, any, count, ph);
+    case 2: return wave_w<2, DM>(N, any, count, ph, shade);
+    case 4: return wave_w<4, DM>(N, any, count, ph, shade);
+    case 8: return wave_w<8, DM>(N, any, count, ph, shade);
     }
     return nullptr;
 }
 
-WaveFn pick_wave(int W, int N, bool any, bool count, int depth_mode, bool ph)
+WaveFn pick_wave(int W, int N, bool any, bool count, int depth_mode, bool ph, bool shade)
 {
-    return depth_mode == 0 ? wave_dm<0>(W, N, any, count, ph) : wave_dm<1>(W, N, any, count, ph);
+    return depth_mode == 0 ? wave_dm<0>(W, N, any, count, ph, shade)
+                           : wave_dm<1>(W, N, any, count, ph, shade);
 }
 
 using KernelFn = void (*)(TraceArgs);
@@ -838,7 +851,7 @@ srt_status launch_trace(const srt_bvh* b, const srt_rays* rays, const srt_trace_
         const int passes = (o->spp + o->n_per_traversal - 1) / o->n_per_traversal;
         if (a.img_w > 0 && !o->any_hit && (passes == 2 || passes == 4)) a.phases = passes;
         wf = pick_wave(b->W, o->n_per_traversal, o->any_hit != 0, counters != nullptr,
-                       o->depth_mode, a.phases > 1);
+                       o->depth_mode, a.phases > 1, rgb != nullptr);
         if (!wf) return SRT_ERR_UNSUPPORTED;
     }
     KernelFn pf = nullptr;
