@@ -1222,8 +1222,8 @@ __global__ __launch_bounds__(kGroupBlock) void k_shadow_groups_wave(int64_t n, S
 
 // Work-stealing waves over the groups (the refill scheme of k_trace_persist),
 // with the record tests taken off the lanes' walks. A lane walks one group's
-// ray. Each iteration every walking lane hands up to four records of the
-// leaf it is at (and of a leaf it pops right after) to a wave-wide queue in
+// ray. Each iteration every walking lane hands up to kRecPerStep records of
+// the leaf it is at (and of a leaf it pops right after) to a wave-wide queue in
 // LDS, then takes one node step; the wave then tests the queued records one
 // per lane, reading the owner's ray from the owner's registers with lane
 // shuffles, and occludes samples of the owner's group through a per-lane
@@ -1237,8 +1237,11 @@ template <int W, bool COUNT, int DM>
 __global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 4) void k_shadow_queue(TraceArgs a,
                                                                                 ShadowGroups g)
 {
-    constexpr int kRecPerStep = 4;
-    constexpr int kStack = LdsStack<W>::value;
+    // width 4: a 28-entry stack leaves LDS for 7 queued records per lane at
+    // 4 waves per SIMD (stack 28 + 7 records: 9.9 KB per wave); the extra
+    // groups a shorter stack sends to the deep pass are few at leaf size 4
+    constexpr int kRecPerStep = W == 4 ? 7 : 4;
+    constexpr int kStack = W == 4 ? 28 : LdsStack<W>::value;
     __shared__ int32_t lds[kStack * kPersistBlock];
     __shared__ uint32_t q_rec[kPersistBlock * kRecPerStep];
     __shared__ uint8_t q_lane[kPersistBlock * kRecPerStep];
@@ -1402,13 +1405,14 @@ __global__ __launch_bounds__(kPersistBlock, W == 8 ? 3 : 4) void k_shadow_queue(
         }
 
         // ---- queue the records (wave prefix sum of the counts, bit by bit:
-        // a lane queues at most kRecPerStep < 8) ----
-        static_assert(kRecPerStep < 8, "three bits per count");
+        // a lane queues at most kRecPerStep) ----
+        constexpr int kCountBits = kRecPerStep < 8 ? 3 : 4;
+        static_assert(kRecPerStep < 16, "at most four bits per count");
         const int q_all = q_n + q_n2;
         const unsigned long long below = (1ull << lane) - 1ull;
         int excl = 0, total = 0;
 #pragma unroll
-        for (int bit = 0; bit < 3; ++bit) {
+        for (int bit = 0; bit < kCountBits; ++bit) {
             const unsigned long long m = __ballot((q_all >> bit) & 1);
             excl += __popcll(m & below) << bit;
             total += __popcll(m) << bit;
