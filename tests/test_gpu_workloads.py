@@ -24,8 +24,8 @@ def _pick(n_total, k, seed):
     return np.sort(rng.choice(n_total, size=k, replace=False))
 
 
-def _pathmix_check(srt, sc, cam, spp, N, pixels, seed=0):
-    bvh = srt.srt_build_bvh(device_scene(sc), 4, 4)
+def _pathmix_check(srt, sc, cam, spp, N, pixels, seed=0, width=4, leaf=4):
+    bvh = srt.srt_build_bvh(device_scene(sc), width, leaf)
     cnt = srt.new_counters()
     res = srt.srt_trace_pathmix(bvh, cam, seed=seed, spp=spp, n_per_traversal=N,
                                 light=si.LIGHT_POS, plane_y=si.PLANE_Y,
@@ -56,6 +56,20 @@ def test_pathmix_small(srt):
     g, ora, c = _pathmix_check(srt, w["scene"], cam, 4, 4, np.arange(R))
     assert (ora["mirror_gid"] >= -1).any() and (ora["shadow_vis"] == 0).any()
     assert (ora["cam_gid"] >= 0).mean() > 0.2
+
+
+@pytest.mark.parametrize("width,leaf", [(2, 2), (8, 4), (4, 8)])
+def test_pathmix_widths_and_leaf_sizes(srt, width, leaf):
+    """The shadow-group queue at each width: width 4 queues up to 7 records
+    per lane and step, so leaves of 8 are taken in two parts; widths 2 and 8
+    queue up to 4 over their own stack depths."""
+    say(f"path-tracer mix: 40k Gaussians, 96x54, 4 spp, N=4, width {width}, leaf {leaf}")
+    w = si.workload(3, small=True)
+    cam = w["cameras"][0]
+    R = cam.width * cam.height
+    g, ora, c = _pathmix_check(srt, w["scene"], cam, 4, 4, np.arange(R), seed=7, width=width,
+                               leaf=leaf)
+    assert (ora["shadow_vis"] == 0).any() and c["lost"] == 0
 
 
 def test_object_scene_full_size_sampled(srt):
